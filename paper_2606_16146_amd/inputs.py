@@ -1,0 +1,176 @@
+"""Seeded synthetic ZeroCheck workloads.
+
+This module only draws random field elements and lays them out; it holds no
+step of the SumCheck prover (no eq table, no round polynomial, no fold, no
+transcript).  It is the one piece of code that both the CPU oracle's tests
+and the GPU path consume, so that both sides see the very same inputs.
+
+Recipe (one independent stream per (seed, instance, table)):
+
+* ``numpy.random.Generator(PCG64(SeedSequence([seed, inst, table_id])))``
+  draws ``u32[N][8]`` little-endian limbs; the top two bits of limb 7 are
+  cleared (value < 2^254 < 2p) and p is subtracted once when the value is
+  >= p, which gives a canonical element of F_p.
+* The eq point ``r`` uses ``table_id = 0xFFFF`` and the same recipe.
+* The witness is made to satisfy the gate on every hypercube point by
+  setting its last column: ``qC = -(qM*a*b + qL*a + qR*b + qO*c)`` for the
+  vanilla gate, ``o = s*w1*...*wm`` for the product gate.  That single
+  column is computed here with Python integers modulo p; a wrong column
+  would only make the witness non-satisfying, which the protocol-level
+  tests (first claim equal to 0) detect independently of either prover.
+
+Table order is the gate's column order: vanilla ``[a, b, c, qM, qL, qR, qO,
+qC]``; product ``[s, w1, ..., wm, o]``.  These are the paper's workload
+shapes (Table 1 lists degree / unique polynomials / additive terms; the
+vanilla gate is the HyperPlonk-style gate, the product gate sweeps degree).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+# BN254 scalar field modulus (decimal form).
+P = 21888242871839275222246405745257275088548364400416034343698204186575808495617
+
+GATE_VANILLA = 0
+GATE_PROD = 1
+
+R_TABLE_ID = 0xFFFF
+
+
+def gate_tables(gate: int, m: int) -> int:
+    """Number of witness tables (eq not included) of a gate."""
+    if gate == GATE_VANILLA:
+        return 8
+    if gate == GATE_PROD:
+        if not 1 <= m <= 8:
+            raise ValueError("product gate needs 1 <= m <= 8")
+        return m + 2
+    raise ValueError(f"unknown gate {gate}")
+
+
+def gate_degree(gate: int, m: int) -> int:
+    """Total degree d of the gate polynomial in its multilinear inputs."""
+    if gate == GATE_VANILLA:
+        return 3
+    if gate == GATE_PROD:
+        return m + 1
+    raise ValueError(f"unknown gate {gate}")
+
+
+def _stream(seed: int, inst: int, table_id: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, inst, table_id])))
+
+
+_P_LIMBS = np.array([(P >> (32 * k)) & 0xFFFFFFFF for k in range(8)], dtype=np.int64)
+
+
+def limbs_to_ints(a: np.ndarray) -> list:
+    """u32[n][8] little-endian limbs -> list of Python ints."""
+    b = np.ascontiguousarray(a, dtype=np.uint32).tobytes()
+    return [int.from_bytes(b[i:i + 32], "little") for i in range(0, len(b), 32)]
+
+
+def ints_to_limbs(vals) -> np.ndarray:
+    """Python ints in [0, 2^256) -> u32[n][8] little-endian limbs."""
+    b = b"".join(int(v).to_bytes(32, "little") for v in vals)
+    return np.frombuffer(b, dtype=np.uint32).reshape(-1, 8).copy()
+
+
+def _geq_p(raw: np.ndarray) -> np.ndarray:
+    """Row-wise raw >= p for u32[n][8] limbs (lexicographic from the top limb)."""
+    gt = np.zeros(raw.shape[0], dtype=bool)
+    eq = np.ones(raw.shape[0], dtype=bool)
+    for k in range(7, -1, -1):
+        col = raw[:, k].astype(np.int64)
+        gt |= eq & (col > _P_LIMBS[k])
+        eq &= col == _P_LIMBS[k]
+    return gt | eq
+
+
+def _sub_p_rows(raw: np.ndarray, mask: np.ndarray) -> None:
+    """raw[mask] -= p in place (rows known to be >= p)."""
+    sel = raw[mask].astype(np.int64)
+    borrow = np.zeros(sel.shape[0], dtype=np.int64)
+    for k in range(8):
+        dif = sel[:, k] - _P_LIMBS[k] - borrow
+        borrow = (dif < 0).astype(np.int64)
+        sel[:, k] = dif + (borrow << 32)
+    raw[mask] = sel.astype(np.uint32)
+
+
+def draw_elements(seed: int, inst: int, table_id: int, n: int) -> np.ndarray:
+    """n canonical field elements as u32[n][8] (recipe in the module docstring)."""
+    raw = _stream(seed, inst, table_id).integers(0, 1 << 32, size=(n, 8), dtype=np.uint32)
+    raw[:, 7] &= np.uint32(0x3FFFFFFF)
+    ge = _geq_p(raw)
+    if ge.any():
+        _sub_p_rows(raw, ge)
+    return raw
+
+
+@dataclass
+class Instance:
+    """One ZeroCheck instance: canonical tables u32[k][N][8] and r u32[mu][8]."""
+
+    seed: int
+    inst: int
+    mu: int
+    gate: int
+    m: int
+    tables: np.ndarray  # uint32[k][2^mu][8], canonical, little-endian limbs
+    r: np.ndarray  # uint32[mu][8], canonical
+
+    @property
+    def k(self) -> int:
+        return self.tables.shape[0]
+
+    @property
+    def degree(self) -> int:
+        return gate_degree(self.gate, self.m)
+
+    def tables_int(self) -> list[list[int]]:
+        return [limbs_to_ints(t) for t in self.tables]
+
+    def r_int(self) -> list[int]:
+        return limbs_to_ints(self.r)
+
+
+def make_instance(seed: int, inst: int, mu: int, gate: int, m: int = 0,
+                  satisfying: bool = True) -> Instance:
+    """Draw one instance.  ``satisfying=False`` leaves the last column random."""
+    if mu < 1:
+        raise ValueError("mu must be >= 1")
+    k = gate_tables(gate, m)
+    n = 1 << mu
+    tabs = np.empty((k, n, 8), dtype=np.uint32)
+    for t in range(k - 1):
+        tabs[t] = draw_elements(seed, inst, t, n)
+    if satisfying:
+        cols = [limbs_to_ints(tabs[t]) for t in range(k - 1)]
+        if gate == GATE_VANILLA:
+            last = [(-(qm * a % P * b + ql * a + qr * b + qo * c)) % P
+                    for a, b, c, qm, ql, qr, qo in zip(*cols)]
+        else:
+            last = cols[0]
+            for w in cols[1:]:
+                last = [x * y % P for x, y in zip(last, w)]
+        tabs[k - 1] = ints_to_limbs(last)
+    else:
+        tabs[k - 1] = draw_elements(seed, inst, k - 1, n)
+    r = draw_elements(seed, inst, R_TABLE_ID, mu)
+    return Instance(seed, inst, mu, gate, m, tabs, r)
+
+
+# Named workloads (sizes and gate shapes of the paper's synthetic polynomials).
+PRESETS = {
+    "plain12": dict(seed=1, mu=12, gate=GATE_VANILLA, m=0),
+    "plain20_d3": dict(seed=2, mu=20, gate=GATE_VANILLA, m=0),
+    "plain20_d9": dict(seed=3, mu=20, gate=GATE_PROD, m=8),
+}
+
+
+def preset_instance(name: str, inst: int = 0) -> Instance:
+    cfg = PRESETS[name]
+    return make_instance(cfg["seed"], inst, cfg["mu"], cfg["gate"], cfg["m"])
