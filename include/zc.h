@@ -1,0 +1,132 @@
+/*
+ * zc.h -- C ABI of the MI355X (gfx950) SumCheck prover for multilinear
+ * ZeroCheck over the BN254 scalar field.
+ *
+ * The operation is the multilinear ZeroCheck of "When Proofs Meet Hardware:
+ * Comparing NTT and SumCheck in Zero-Knowledge Systems", Fig. 2 (right) and
+ * Sec. 3.3 (Eq. (1)): given the MLE tables of the witness columns of a gate
+ * f_M and a point r, prove sum_x f_M(x) eq_r(x) = 0 over {0,1}^mu by
+ * SumCheck.  Round i sends G_i(X) = sum over x_{i+1..mu} of
+ * f_M(alpha_1..alpha_{i-1}, X, x_{>i}) eq_r(...) as its d+2 values at
+ * X = 0..d+1, takes alpha_i from the transcript, and folds every table
+ * (Sec. 4.1).  After mu rounds the tables hold the openings at alpha.
+ *
+ * Conventions shared by every entry point:
+ *  - Field elements at the boundary are canonical (< p), 8 x uint32
+ *    little-endian limbs (= the 32-byte little-endian encoding).
+ *  - Tables handed to the prover are in the library's internal form made by
+ *    zc_pack: limb-planar, limb l of element j at table[l * pitch + j],
+ *    pitch = 2^mu, Montgomery form.  They are opaque otherwise.
+ *  - Index convention: table index b = sum_i x_i 2^(mu-i); x_1 is the most
+ *    significant bit and is bound first.
+ *  - Transcript: T_0 = SHA-256("ZCv1" || u32le mu || u32le gate || u32le m ||
+ *    enc(r_1) .. enc(r_mu)); T_i = SHA-256(T_{i-1} || enc(G_i(0)) .. enc(G_i(d+1)));
+ *    alpha_i = T_i read as a little-endian integer, mod p.
+ *  - All pointers are device pointers unless stated otherwise; the caller
+ *    allocates and owns every buffer.  The library allocates nothing and
+ *    keeps no global state between calls; calls with distinct workspaces may
+ *    run concurrently on distinct streams.
+ *  - Work is enqueued on `stream` and is complete when that stream has been
+ *    synchronized.  Host-side argument checks return a negative zc_status
+ *    and enqueue nothing.  A failed launch returns ZC_EHIP.  Conditions the
+ *    device detects (an input >= p, a stepping call out of order) are stored
+ *    in the workspace and returned by zc_read_error.
+ */
+#ifndef ZC_H
+#define ZC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ZC_OK = 0,
+  ZC_EINVAL = -1,       /* bad argument (null pointer, mu out of range, bad round index) */
+  ZC_EUNSUPPORTED = -2, /* unknown gate or gate parameter */
+  ZC_EHIP = -3,         /* a HIP call or kernel launch failed */
+  ZC_ERANGE = -4,       /* (device) an input element was >= p */
+  ZC_ESTATE = -5        /* (device) zc_round / zc_fold called out of order */
+} zc_status;
+
+typedef enum {
+  /* f = qM*a*b + qL*a + qR*b + qO*c + qC, degree 3,
+     tables [a, b, c, qM, qL, qR, qO, qC] (HyperPlonk-style vanilla gate) */
+  ZC_GATE_VANILLA = 0,
+  /* f = s*w1*...*wm - o, degree m+1, tables [s, w1, .., wm, o], 1 <= m <= 8 */
+  ZC_GATE_PROD = 1
+} zc_gate;
+
+/* Instance shape: 1 <= mu <= 30, gate in zc_gate, m used by ZC_GATE_PROD. */
+typedef struct {
+  uint32_t mu;
+  uint32_t gate;
+  uint32_t m;
+} zc_shape;
+
+/* Number of witness tables k of the gate (eq not counted), or a negative zc_status. */
+int zc_table_count(const zc_shape* shape);
+
+/* Gate degree d (the round polynomial has degree d+1, d+2 values), or a negative zc_status. */
+int zc_degree(const zc_shape* shape);
+
+/* Bytes of device workspace a proof of this shape needs (0 for an invalid shape):
+   control block, eq table (2^mu elements), folded copies of all k+1 tables
+   (2^(mu-1) elements each), per-block partial sums.  256-byte alignment required. */
+size_t zc_workspace_bytes(const zc_shape* shape);
+
+/* Convert n canonical elements (canon: uint32[n][8], 16-byte aligned) into the
+   internal limb-planar Montgomery form (mont_planar: uint32[8][n], pitch n).
+   Elements >= p are flagged (ZC_ERANGE via zc_read_error); only the control
+   block of ws is used, so a workspace of any valid shape will do. */
+int zc_pack(const uint32_t* canon, uint32_t* mont_planar, uint64_t n, void* ws, hipStream_t stream);
+
+/* Inverse of zc_pack for the first n elements of a limb-planar table with the
+   given pitch (canon: uint32[n][8], 16-byte aligned). */
+int zc_unpack(const uint32_t* mont_planar, uint64_t pitch, uint32_t* canon, uint64_t n, hipStream_t stream);
+
+/* Whole proof (Fig. 2, right).
+   tables      host array of k device pointers (gate column order), each a
+               packed table of 2^mu elements; READ ONLY (the folds go to ws).
+   r           mu canonical elements (uint32[mu][8]); r_i >= p is flagged.
+   ws          workspace of zc_workspace_bytes(shape) bytes.
+   round_evals out: uint32[mu][d+2][8], G_i(0..d+1), canonical.
+   challenges  out: uint32[mu][8], alpha_1..alpha_mu, canonical.
+   openings    out: uint32[k+1][8], every witness table's MLE at alpha in
+               column order, then eq_r(alpha), canonical. */
+int zc_prove(const zc_shape* shape, const uint32_t* const* tables, const uint32_t* r, void* ws,
+             uint32_t* round_evals, uint32_t* challenges, uint32_t* openings, hipStream_t stream);
+
+/* Stepping form of the same proof, same bytes as zc_prove.
+   zc_round(i), 1 <= i <= mu: evaluates G_i on tables that have been folded
+   i-1 times (2^(mu-i+1) live entries, pitch 2^mu), writes
+   round_evals[(i-1)(d+2)..] and challenges[i-1] (same layout as zc_prove),
+   and keeps alpha_i in ws.  zc_round(1) also checks r, starts the
+   transcript and builds the eq table in ws.  Must follow zc_fold(i-1). */
+int zc_round(const zc_shape* shape, const uint32_t* const* tables, const uint32_t* r, void* ws, uint32_t i,
+             uint32_t* round_evals, uint32_t* challenges, hipStream_t stream);
+
+/* Folds the k caller tables (IN PLACE, pitch 2^mu) and ws's eq table with
+   alpha_i: t[j] <- t[j] + alpha_i (t[j + h] - t[j]) for j < h = 2^(mu-i).
+   Must follow zc_round(i).  After zc_fold(mu) entry 0 of each table is its
+   opening (read it with zc_unpack, pitch 2^mu). */
+int zc_fold(const zc_shape* shape, uint32_t* const* tables, void* ws, uint32_t i, hipStream_t stream);
+
+/* Synchronizes `stream` and returns the first device-detected error stored in
+   ws (ZC_OK if none), or ZC_EHIP if the synchronization fails.  The error word
+   is cleared when zc_prove or zc_round(1) starts; a workspace that has run
+   neither must be zero-filled before zc_pack can report through it. */
+int zc_read_error(void* ws, hipStream_t stream);
+
+/* Static description of a status code. */
+const char* zc_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ZC_H */

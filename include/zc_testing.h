@@ -1,0 +1,42 @@
+/*
+ * zc_testing.h -- test hooks of libzc (not part of the prover's API).
+ *
+ * They run single device building blocks of the prover on caller buffers so
+ * that tests can compare them with Python integers and hashlib: the field
+ * arithmetic (Montgomery product of Sec. 5.1 / Table 2's modular
+ * multiplier, modular addition) and the SHA-256 used for the Fiat-Shamir
+ * challenges of Fig. 2.  Same conventions as zc.h: device pointers,
+ * canonical 8 x uint32 little-endian elements, work enqueued on `stream`.
+ */
+#ifndef ZC_TESTING_H
+#define ZC_TESTING_H
+
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ZC_TEST_MUL = 0,        /* out = a*b mod p (canonical in, canonical out) */
+  ZC_TEST_ADD = 1,        /* out = a+b mod p */
+  ZC_TEST_SUB = 2,        /* out = a-b mod p */
+  ZC_TEST_MONT_RAW = 3,   /* out = A*B*2^-261 mod p for raw 256-bit A, B (any value < 2^256) */
+  ZC_TEST_TO_MONT = 4,    /* out = a*2^261 mod p */
+  ZC_TEST_FROM_MONT = 5,  /* out = a*2^-261 mod p, a any value < 2^256 */
+  ZC_TEST_EXT_SQR = 6     /* E = a + 10*b as plain sum (a, b < p); out = E*E*2^-522 mod p */
+} zc_test_op;
+
+/* Element-wise op over n elements: a, b, out are uint32[n][8]. */
+int zc_test_field(int op, const uint32_t* a, const uint32_t* b, uint32_t* out, uint64_t n, hipStream_t stream);
+
+/* SHA-256 of len bytes (msg: little-endian packed uint32 words); out: 32 bytes as uint32[8]. */
+int zc_test_sha256(const uint32_t* msg, uint32_t len, uint32_t* out, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ZC_TESTING_H */

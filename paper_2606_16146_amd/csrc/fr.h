@@ -1,0 +1,296 @@
+// BN254 scalar field F_p on the gfx950 VALU.
+//
+// The paper's accelerator multiplies with Montgomery multipliers for its
+// 255-bit prime (Sec. 5.1, Table 2).  Here the Montgomery product is laid out
+// for the CDNA4 vector ALU instead:
+//
+// * An element in registers is 9 limbs of 29 bits (radix 2^29, 261 bits),
+//   in Montgomery form x*R mod p with R = 2^261.
+// * The product is computed by product scanning: every partial product
+//   a_i*b_j and m_i*p_j is one v_mad_u64_u32 that adds straight into a
+//   64-bit column accumulator.  A column holds at most 18 products of
+//   < 2^58 plus a < 2^35 carry, so it never overflows and no carry
+//   instruction is needed between the multiplies (with 32-bit limbs every
+//   step needs a separate 64-bit addend and carry handling).
+// * R/p > 2^7 leaves room for lazy reduction: for inputs a < A*p, b < B*p
+//   with A*B <= 128 the product is < p*(1 + A*B/128) <= 2p.
+//
+// In memory an element is 8 x 32-bit words holding the same integer (< p),
+// one limb plane per word (limb-planar tables); fe_load8 / fe_store8 convert.
+//
+// Only p is written down; every derived constant (-p^-1 mod 2^29, R mod p,
+// R^2 mod p, multiples of p) is computed by constexpr evaluation.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace zc {
+
+constexpr int NL = 9;                    // limbs per element
+constexpr uint32_t LM = (1u << 29) - 1;  // limb mask
+
+struct Fe {
+  uint32_t l[NL];
+};
+
+// p = 0x30644e72e131a029b85045b68181585d2833e84879b9709143e1f593f0000001
+struct W8 {
+  uint32_t v[8];
+};
+constexpr W8 kPWords = {{0xf0000001u, 0x43e1f593u, 0x79b97091u, 0x2833e848u, 0x8181585du,
+                         0xb85045b6u, 0xe131a029u, 0x30644e72u}};
+
+struct L9 {
+  uint32_t v[NL];
+};
+
+namespace detail {
+
+constexpr L9 words_to_l9(const W8& w) {
+  L9 r{};
+  for (int i = 0; i < NL; ++i) {
+    const int bit = 29 * i, wi = bit / 32, s = bit % 32;
+    uint64_t x = w.v[wi] >> s;
+    if (wi + 1 < 8 && s > 0) x |= (uint64_t)w.v[wi + 1] << (32 - s);
+    r.v[i] = (uint32_t)x & LM;
+  }
+  return r;
+}
+
+constexpr L9 kP = words_to_l9(kPWords);
+
+constexpr bool geq(const L9& a, const L9& b) {
+  for (int i = NL - 1; i >= 0; --i)
+    if (a.v[i] != b.v[i]) return a.v[i] > b.v[i];
+  return true;
+}
+
+constexpr L9 add(const L9& a, const L9& b) {
+  L9 r{};
+  uint32_t c = 0;
+  for (int i = 0; i < NL; ++i) {
+    uint32_t s = a.v[i] + b.v[i] + c;
+    c = s >> 29;
+    r.v[i] = i == NL - 1 ? s : (s & LM);
+  }
+  return r;
+}
+
+constexpr L9 sub(const L9& a, const L9& b) {  // requires a >= b
+  L9 r{};
+  int32_t br = 0;
+  for (int i = 0; i < NL; ++i) {
+    int32_t t = (int32_t)a.v[i] - (int32_t)b.v[i] + br;
+    br = t < 0 ? -1 : 0;
+    r.v[i] = (uint32_t)t & LM;
+  }
+  return r;
+}
+
+constexpr L9 pow2_mod(int e) {
+  L9 v{};
+  v.v[0] = 1;
+  for (int i = 0; i < e; ++i) {
+    v = add(v, v);
+    if (geq(v, kP)) v = sub(v, kP);
+  }
+  return v;
+}
+
+constexpr L9 mul_small(const L9& a, uint32_t k) {
+  L9 r{};
+  for (uint32_t i = 0; i < k; ++i) r = add(r, a);
+  return r;
+}
+
+constexpr uint32_t neg_inv29() {
+  uint32_t x = 1;  // Newton: x <- x (2 - p0 x) doubles the correct low bits
+  for (int i = 0; i < 6; ++i) x *= 2u - kP.v[0] * x;
+  return (0u - x) & LM;
+}
+
+}  // namespace detail
+
+constexpr L9 kP = detail::kP;
+constexpr uint32_t kNInv = detail::neg_inv29();  // -p^-1 mod 2^29
+constexpr L9 kOne = detail::pow2_mod(261);       // R mod p: Montgomery form of 1
+constexpr L9 kR2 = detail::pow2_mod(522);        // R^2 mod p
+constexpr L9 kP2 = detail::mul_small(kP, 2);
+constexpr L9 kP4 = detail::mul_small(kP, 4);
+constexpr L9 kP8 = detail::mul_small(kP, 8);
+constexpr L9 kP16 = detail::mul_small(kP, 16);
+
+static_assert(((kP.v[0] * kNInv) & LM) == LM, "-p^-1 mod 2^29");
+static_assert(kP.v[8] < (1u << 22), "p < 2^254");
+
+// Constant limb i of a compile-time L9 (folded after unrolling).
+#define ZC_CL(C, i) (C).v[i]
+
+__device__ __forceinline__ Fe fe_zero() {
+  Fe r;
+#pragma unroll
+  for (int i = 0; i < NL; ++i) r.l[i] = 0;
+  return r;
+}
+
+__device__ __forceinline__ Fe fe_const(const L9& c) {
+  Fe r;
+#pragma unroll
+  for (int i = 0; i < NL; ++i) r.l[i] = c.v[i];
+  return r;
+}
+
+// ---- conversion between the 8-word memory form and 9 x 29-bit limbs -------
+
+__device__ __forceinline__ Fe fe_from_words(const uint32_t w[8]) {
+  Fe r;
+#pragma unroll
+  for (int i = 0; i < NL; ++i) {
+    const int bit = 29 * i, wi = bit / 32, s = bit % 32;
+    uint32_t x;
+    if (wi + 1 < 8 && s + 29 > 32)
+      x = __builtin_amdgcn_alignbit(w[wi + 1], w[wi], s);
+    else
+      x = w[wi] >> s;
+    r.l[i] = x & LM;
+  }
+  return r;
+}
+
+// Requires normalized limbs and a value < 2^256.
+__device__ __forceinline__ void fe_to_words(const Fe& a, uint32_t w[8]) {
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int bit = 32 * j, li = bit / 29, s = bit % 29;
+    // word j = bits [32j, 32j+32) = (l_li >> s) | l_{li+1} << (29-s) | l_{li+2} << (58-s)
+    uint32_t x = a.l[li] >> s;
+    if (li + 1 < NL) x |= a.l[li + 1] << (29 - s);
+    if (li + 2 < NL && 58 - s < 32) x |= a.l[li + 2] << (58 - s);
+    w[j] = x;
+  }
+}
+
+// ---- additive operations ----------------------------------------------------
+
+// a + b as integers, limbs normalized (a, b normalized; value < 2^261).
+__device__ __forceinline__ Fe fe_add(const Fe& a, const Fe& b) {
+  Fe r;
+  uint32_t c = 0;
+#pragma unroll
+  for (int i = 0; i < NL; ++i) {
+    const uint32_t s = a.l[i] + b.l[i] + c;
+    c = s >> 29;
+    r.l[i] = (i == NL - 1) ? s : (s & LM);
+  }
+  return r;
+}
+
+// a - C if a >= C, else a (a, C normalized).
+__device__ __forceinline__ Fe fe_csub(const Fe& a, const L9& C) {
+  Fe d;
+  int32_t br = 0;
+#pragma unroll
+  for (int i = 0; i < NL; ++i) {
+    const int32_t t = (int32_t)a.l[i] - (int32_t)C.v[i] + br;
+    br = t >> 29;  // 0 or -1 (t > -2^30)
+    d.l[i] = (uint32_t)t & LM;
+  }
+#pragma unroll
+  for (int i = 0; i < NL; ++i) d.l[i] = br ? a.l[i] : d.l[i];
+  return d;
+}
+
+// a + C*... : a + K - b for a constant K >= b (b normalized, value b <= K).
+__device__ __forceinline__ Fe fe_sub_plus(const Fe& a, const Fe& b, const L9& K) {
+  Fe r;
+  int32_t c = 0;
+#pragma unroll
+  for (int i = 0; i < NL; ++i) {
+    const int32_t t = (int32_t)a.l[i] + (int32_t)K.v[i] - (int32_t)b.l[i] + c;
+    c = t >> 29;  // arithmetic shift: signed carry
+    r.l[i] = (i == NL - 1) ? (uint32_t)t : ((uint32_t)t & LM);
+  }
+  return r;
+}
+
+// (a + b) mod p for a, b < p; result < p.
+__device__ __forceinline__ Fe fe_addmod(const Fe& a, const Fe& b) { return fe_csub(fe_add(a, b), kP); }
+
+// (a - b) mod p for a, b < p; result < p.
+__device__ __forceinline__ Fe fe_submod(const Fe& a, const Fe& b) {
+  return fe_csub(fe_sub_plus(a, b, kP), kP);
+}
+
+// Reduce a value < 2p into [0, p).
+__device__ __forceinline__ Fe fe_reduce2(const Fe& a) { return fe_csub(a, kP); }
+
+// Reduce a value < 32p into [0, p).
+__device__ __forceinline__ Fe fe_reduce32(const Fe& a) {
+  return fe_csub(fe_csub(fe_csub(fe_csub(fe_csub(a, kP16), kP8), kP4), kP2), kP);
+}
+
+// ---- Montgomery product -----------------------------------------------------
+
+// a*b*R^-1 mod p up to a multiple of p: for a < A*p, b < B*p with
+// A*B <= 128 the result is < 2p.  Limbs of a and b normalized (< 2^29;
+// the top limb of a value < 2^258 is < 2^26).  Result limbs normalized.
+__device__ __forceinline__ Fe fe_mul(const Fe& a, const Fe& b) {
+  uint32_t m[NL];
+  Fe r;
+  uint64_t acc = 0;
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+#pragma unroll
+    for (int i = 0; i < k; ++i) {
+      acc = (uint64_t)a.l[i] * b.l[k - i] + acc;
+      acc = (uint64_t)m[i] * ZC_CL(kP, k - i) + acc;
+    }
+    acc = (uint64_t)a.l[k] * b.l[0] + acc;
+    m[k] = ((uint32_t)acc * kNInv) & LM;
+    acc = (uint64_t)m[k] * ZC_CL(kP, 0) + acc;  // low 29 bits become 0
+    acc >>= 29;
+  }
+#pragma unroll
+  for (int k = NL; k < 2 * NL - 1; ++k) {
+#pragma unroll
+    for (int i = k - NL + 1; i < NL; ++i) {
+      acc = (uint64_t)a.l[i] * b.l[k - i] + acc;
+      acc = (uint64_t)m[i] * ZC_CL(kP, k - i) + acc;
+    }
+    r.l[k - NL] = (uint32_t)acc & LM;
+    acc >>= 29;
+  }
+  r.l[NL - 1] = (uint32_t)acc;
+  return r;
+}
+
+// canonical x < p  ->  Montgomery form x*R mod p, < p.
+__device__ __forceinline__ Fe fe_to_mont(const Fe& x) { return fe_reduce2(fe_mul(x, fe_const(kR2))); }
+
+// Montgomery form (value < 2p)  ->  canonical x < p.
+__device__ __forceinline__ Fe fe_from_mont(const Fe& a) {
+  Fe one = fe_zero();
+  one.l[0] = 1;
+  return fe_reduce2(fe_mul(a, one));
+}
+
+__device__ __forceinline__ bool fe_is_zero(const Fe& a) {
+  uint32_t o = 0;
+#pragma unroll
+  for (int i = 0; i < NL; ++i) o |= a.l[i];
+  return o == 0;
+}
+
+// 256-bit word form w < p ?
+__device__ __forceinline__ bool words_lt_p(const uint32_t w[8]) {
+  int32_t br = 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int64_t t = (int64_t)w[i] - (int64_t)kPWords.v[i] + br;
+    br = t < 0 ? -1 : 0;
+  }
+  return br != 0;
+}
+
+}  // namespace zc

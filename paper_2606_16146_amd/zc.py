@@ -1,0 +1,185 @@
+"""Python binding of libzc (include/zc.h): argument marshalling only.
+
+Every step of a proof runs in the library's HIP kernels; torch provides the
+device buffers and the stream.  Tensors are uint32 on the current CUDA
+(HIP) device; element arrays are uint32[..][8] canonical little-endian
+limbs, packed tables are uint32[8][pitch] limb-planar.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libzc.so")
+INCLUDE = os.path.join(os.path.dirname(HERE), "include")
+
+ZC_OK, ZC_EINVAL, ZC_EUNSUPPORTED, ZC_EHIP, ZC_ERANGE, ZC_ESTATE = 0, -1, -2, -3, -4, -5
+GATE_VANILLA, GATE_PROD = 0, 1
+
+
+class Shape(ctypes.Structure):
+    _fields_ = [("mu", ctypes.c_uint32), ("gate", ctypes.c_uint32), ("m", ctypes.c_uint32)]
+
+
+class ZcError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {status} ({strerror(status)})")
+        self.status = status
+
+
+_lib = None
+_VP = ctypes.c_void_p
+_SIGS = {
+    "zc_table_count": (ctypes.c_int, [ctypes.POINTER(Shape)]),
+    "zc_degree": (ctypes.c_int, [ctypes.POINTER(Shape)]),
+    "zc_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Shape)]),
+    "zc_pack": (ctypes.c_int, [_VP, _VP, ctypes.c_uint64, _VP, _VP]),
+    "zc_unpack": (ctypes.c_int, [_VP, ctypes.c_uint64, _VP, ctypes.c_uint64, _VP]),
+    "zc_prove": (ctypes.c_int, [ctypes.POINTER(Shape), _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "zc_round": (ctypes.c_int, [ctypes.POINTER(Shape), _VP, _VP, _VP, ctypes.c_uint32, _VP, _VP, _VP]),
+    "zc_fold": (ctypes.c_int, [ctypes.POINTER(Shape), _VP, _VP, ctypes.c_uint32, _VP]),
+    "zc_read_error": (ctypes.c_int, [_VP, _VP]),
+    "zc_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "zc_test_field": (ctypes.c_int, [ctypes.c_int, _VP, _VP, _VP, ctypes.c_uint64, _VP]),
+    "zc_test_sha256": (ctypes.c_int, [_VP, ctypes.c_uint32, _VP, _VP]),
+}
+
+
+def lib():
+    """Load libzc.so (built in-tree by __graft_entry__.build()); fail loudly if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        h = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(h, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = h
+    return _lib
+
+
+def declared_symbols() -> list[str]:
+    """Every function name declared in include/*.h."""
+    names = []
+    for fn in sorted(os.listdir(INCLUDE)):
+        if fn.endswith(".h"):
+            text = open(os.path.join(INCLUDE, fn)).read()
+            names += re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(zc_[a-z_0-9]+)\s*\(", text, re.M)
+    return names
+
+
+def strerror(status: int) -> str:
+    return lib().zc_strerror(status).decode()
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != ZC_OK:
+        raise ZcError(rc, what)
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: torch.Tensor):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def shape(mu: int, gate: int, m: int = 0) -> Shape:
+    return Shape(mu, gate, m)
+
+
+def table_count(s: Shape) -> int:
+    return lib().zc_table_count(ctypes.byref(s))
+
+
+def degree(s: Shape) -> int:
+    return lib().zc_degree(ctypes.byref(s))
+
+
+def workspace_bytes(s: Shape) -> int:
+    return lib().zc_workspace_bytes(ctypes.byref(s))
+
+
+def new_workspace(s: Shape, device="cuda") -> torch.Tensor:
+    nb = workspace_bytes(s)
+    if nb == 0:
+        raise ZcError(ZC_EINVAL, "workspace size")
+    return torch.zeros(nb, dtype=torch.uint8, device=device)  # error word starts clear
+
+
+def pack(canon: torch.Tensor, ws: torch.Tensor, stream=None) -> torch.Tensor:
+    """uint32[n][8] canonical (device) -> uint32[8][n] packed table."""
+    n = canon.shape[0]
+    out = torch.empty((8, n), dtype=torch.uint32, device=canon.device)
+    _check(lib().zc_pack(_ptr(canon), _ptr(out), n, _ptr(ws), _stream(stream)), "zc_pack")
+    return out
+
+
+def unpack(planar: torch.Tensor, n: int | None = None, stream=None) -> torch.Tensor:
+    """Packed table uint32[8][pitch] -> first n elements as uint32[n][8] canonical."""
+    pitch = planar.shape[1]
+    n = pitch if n is None else n
+    out = torch.empty((n, 8), dtype=torch.uint32, device=planar.device)
+    _check(lib().zc_unpack(_ptr(planar), pitch, _ptr(out), n, _stream(stream)), "zc_unpack")
+    return out
+
+
+def _table_array(tables):
+    arr = (ctypes.c_void_p * len(tables))(*[t.data_ptr() for t in tables])
+    return arr
+
+
+def new_outputs(s: Shape, device="cuda"):
+    d, k = degree(s), table_count(s)
+    evals = torch.empty((s.mu, d + 2, 8), dtype=torch.uint32, device=device)
+    alphas = torch.empty((s.mu, 8), dtype=torch.uint32, device=device)
+    openings = torch.empty((k + 1, 8), dtype=torch.uint32, device=device)
+    return evals, alphas, openings
+
+
+def prove(s: Shape, tables, r: torch.Tensor, ws: torch.Tensor, outputs=None, stream=None):
+    """Whole proof; returns (round_evals, challenges, openings) device tensors."""
+    evals, alphas, openings = outputs if outputs is not None else new_outputs(s, r.device)
+    arr = _table_array(tables)
+    rc = lib().zc_prove(ctypes.byref(s), arr, _ptr(r), _ptr(ws), _ptr(evals), _ptr(alphas),
+                        _ptr(openings), _stream(stream))
+    _check(rc, "zc_prove")
+    return evals, alphas, openings
+
+
+def round_(s: Shape, tables, r: torch.Tensor, ws: torch.Tensor, i: int, evals, alphas, stream=None):
+    arr = _table_array(tables)
+    rc = lib().zc_round(ctypes.byref(s), arr, _ptr(r) if r is not None else None, _ptr(ws), i,
+                        _ptr(evals), _ptr(alphas), _stream(stream))
+    _check(rc, "zc_round")
+
+
+def fold(s: Shape, tables, ws: torch.Tensor, i: int, stream=None):
+    arr = _table_array(tables)
+    _check(lib().zc_fold(ctypes.byref(s), arr, _ptr(ws), i, _stream(stream)), "zc_fold")
+
+
+def read_error(ws: torch.Tensor, stream=None) -> int:
+    return lib().zc_read_error(_ptr(ws), _stream(stream))
+
+
+def test_field(op: int, a: torch.Tensor, b: torch.Tensor, stream=None) -> torch.Tensor:
+    out = torch.empty_like(a)
+    _check(lib().zc_test_field(op, _ptr(a), _ptr(b), _ptr(out), a.shape[0], _stream(stream)),
+           "zc_test_field")
+    return out
+
+
+def test_sha256(msg_words: torch.Tensor, length: int, stream=None) -> torch.Tensor:
+    out = torch.empty(8, dtype=torch.uint32, device=msg_words.device)
+    _check(lib().zc_test_sha256(_ptr(msg_words), length, _ptr(out), _stream(stream)),
+           "zc_test_sha256")
+    return out

@@ -1,0 +1,67 @@
+"""C ABI of libzc on the CPU: the library loads, exports every declared
+symbol, and host-side argument checks fail before any GPU work."""
+import ctypes
+
+import pytest
+
+from paper_2606_16146_amd import zc
+
+
+def test_library_exports_every_declared_symbol():
+    h = zc.lib()
+    names = zc.declared_symbols()
+    assert {"zc_prove", "zc_round", "zc_fold", "zc_pack", "zc_unpack", "zc_workspace_bytes",
+            "zc_read_error", "zc_strerror", "zc_table_count", "zc_degree"} <= set(names)
+    for name in names:
+        assert hasattr(h, name), name
+
+
+@pytest.mark.parametrize("mu,gate,m,k,d", [(20, 0, 0, 8, 3), (20, 1, 8, 10, 9), (12, 1, 4, 6, 5),
+                                           (1, 1, 1, 3, 2)])
+def test_shape_queries(mu, gate, m, k, d):
+    s = zc.shape(mu, gate, m)
+    assert zc.table_count(s) == k
+    assert zc.degree(s) == d
+    ws = zc.workspace_bytes(s)
+    n = 1 << mu
+    # at least eq (n elements) + folded copies of k+1 tables (n/2 each)
+    assert ws >= 32 * n + 32 * (k + 1) * max(n // 2, 1)
+    assert ws % 256 == 0
+
+
+@pytest.mark.parametrize("mu,gate,m", [(0, 0, 0), (31, 0, 0), (10, 2, 0), (10, 1, 0), (10, 1, 9)])
+def test_invalid_shapes(mu, gate, m):
+    s = zc.shape(mu, gate, m)
+    assert zc.workspace_bytes(s) == 0
+    if gate not in (0, 1) or (gate == 1 and not 1 <= m <= 8):
+        assert zc.table_count(s) == zc.ZC_EUNSUPPORTED
+
+
+def test_host_validation_rejects_bad_arguments_without_gpu():
+    h = zc.lib()
+    s = zc.shape(4, 0)
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    tabs = (ctypes.c_void_p * 8)(*([0x1000] * 8))
+    null_tabs = (ctypes.c_void_p * 8)(*([0x1000] * 7 + [0]))
+    assert h.zc_prove(None, tabs, fake, fake, fake, fake, fake, None) == zc.ZC_EINVAL
+    assert h.zc_prove(ctypes.byref(s), null_tabs, fake, fake, fake, fake, fake, None) == zc.ZC_EINVAL
+    assert h.zc_prove(ctypes.byref(s), tabs, None, fake, fake, fake, fake, None) == zc.ZC_EINVAL
+    bad = zc.shape(4, 7)
+    assert h.zc_prove(ctypes.byref(bad), tabs, fake, fake, fake, fake, fake, None) == zc.ZC_EUNSUPPORTED
+    mu_bad = zc.shape(31, 0)
+    assert h.zc_prove(ctypes.byref(mu_bad), tabs, fake, fake, fake, fake, fake, None) == zc.ZC_EINVAL
+    # round index out of range
+    assert h.zc_round(ctypes.byref(s), tabs, fake, fake, 0, fake, fake, None) == zc.ZC_EINVAL
+    assert h.zc_round(ctypes.byref(s), tabs, fake, fake, 5, fake, fake, None) == zc.ZC_EINVAL
+    assert h.zc_fold(ctypes.byref(s), tabs, fake, 0, None) == zc.ZC_EINVAL
+    # misaligned workspace
+    assert h.zc_prove(ctypes.byref(s), tabs, fake, ctypes.c_void_p(0x1004), fake, fake, fake,
+                      None) == zc.ZC_EINVAL
+    assert h.zc_pack(None, fake, 4, fake, None) == zc.ZC_EINVAL
+    assert h.zc_unpack(fake, 2, fake, 4, None) == zc.ZC_EINVAL  # pitch < n
+
+
+def test_strerror_covers_every_status():
+    for st in (0, -1, -2, -3, -4, -5):
+        assert zc.strerror(st) and zc.strerror(st) != "unknown status"
+    assert zc.strerror(-99) == "unknown status"

@@ -1,0 +1,156 @@
+"""Parity of the HIP prover with the CPU oracle (GPU).
+
+Small instances are compared with the Python oracle element by element
+(round polynomials, challenges, openings and, through the stepping API,
+every folded table); full-size instances (mu = 20, degree 3 and 9) with the
+C oracle, which itself matches the Python oracle byte for byte.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import c_oracle as C
+from oracle import zc_oracle as O
+from paper_2606_16146_amd import inputs as I
+from tests._helpers import P, R_MONT, dev, gpu_prove, ints_of, limbs_of, same_as_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def zc():
+    from paper_2606_16146_amd import zc as z
+    z.lib()
+    return z
+
+
+SMALL = [(1, 0, 0), (2, 0, 0), (3, 0, 0), (5, 0, 0), (9, 0, 0), (10, 0, 0),
+         (1, 1, 1), (4, 1, 1), (6, 1, 2), (7, 1, 3), (8, 1, 4), (5, 1, 5), (6, 1, 6), (4, 1, 7),
+         (7, 1, 8), (2, 1, 8)]
+
+
+@pytest.mark.parametrize("mu,gate,m", SMALL)
+def test_prove_matches_python_oracle(zc, mu, gate, m):
+    inst = I.make_instance(500 + mu, m, mu, gate, m)
+    res = gpu_prove(inst)
+    assert res["err"] == 0
+    ora = O.prove(mu, gate, m, inst.tables_int(), inst.r_int())
+    same_as_oracle(res, ora)
+
+
+def test_plain12_matches_python_oracle_and_verifies(zc):
+    inst = I.preset_instance("plain12")
+    res = gpu_prove(inst)
+    assert res["err"] == 0
+    ora = O.prove(inst.mu, inst.gate, inst.m, inst.tables_int(), inst.r_int())
+    same_as_oracle(res, ora)
+    ev = [ints_of(res["evals"][i]) for i in range(inst.mu)]
+    assert O.verify(inst.mu, inst.gate, inst.m, inst.r_int(), ev, ints_of(res["alphas"]),
+                    ints_of(res["openings"]))
+
+
+@pytest.mark.parametrize("mu,gate,m", [(6, 0, 0), (5, 1, 4), (4, 1, 8)])
+def test_nonsatisfying_witness_still_matches(zc, mu, gate, m):
+    inst = I.make_instance(77, 0, mu, gate, m, satisfying=False)
+    res = gpu_prove(inst)
+    ora = O.prove(mu, gate, m, inst.tables_int(), inst.r_int())
+    same_as_oracle(res, ora)
+    assert not O.verify(mu, gate, m, inst.r_int(), ora["evals"], ora["alphas"], ora["openings"])
+
+
+@pytest.mark.parametrize("gate,m", [(0, 0), (1, 8), (1, 4)])
+def test_extreme_values_worst_case_extensions(zc, gate, m):
+    """Every pair is (0, p-1) in the internal form: Delta = p-1, the largest extensions."""
+    mu = 5
+    k = 8 if gate == 0 else m + 2
+    n = 1 << mu
+    top = (P - 1) * pow(R_MONT, -1, P) % P  # packs to p-1
+    vals = [0] * (n // 2) + [top] * (n // 2)
+    tables = np.stack([limbs_of(vals) for _ in range(k)])
+    r = limbs_of([P - 1] * mu)
+    inst = I.Instance(0, 0, mu, gate, m, tables, r)
+    res = gpu_prove(inst)
+    ora = O.prove(mu, gate, m, inst.tables_int(), inst.r_int())
+    same_as_oracle(res, ora)
+
+
+@pytest.mark.parametrize("mu,gate,m", [(7, 0, 0), (6, 1, 8), (5, 1, 2)])
+def test_stepping_matches_fused_and_folded_tables(zc, mu, gate, m):
+    inst = I.make_instance(900 + mu, 0, mu, gate, m)
+    fused = gpu_prove(inst)
+    ora = O.prove(mu, gate, m, inst.tables_int(), inst.r_int(), keep_tables=True)
+    s = zc.shape(mu, gate, m)
+    ws = zc.new_workspace(s)
+    tabs = [zc.pack(dev(t), ws) for t in inst.tables]
+    r = dev(inst.r)
+    ev, al, _ = zc.new_outputs(s)
+    n = 1 << mu
+    for i in range(1, mu + 1):
+        zc.round_(s, tabs, r, ws, i, ev, al)
+        zc.fold(s, tabs, ws, i)
+        live = n >> i
+        after = ora["tables_after"][i - 1]
+        for t in range(len(tabs)):
+            assert ints_of(zc.unpack(tabs[t], live)) == after[t], (i, t)
+    assert zc.read_error(ws) == 0
+    assert (ev.cpu().numpy() == fused["evals"]).all()
+    assert (al.cpu().numpy() == fused["alphas"]).all()
+    openings = [ints_of(zc.unpack(t, 1))[0] for t in tabs]
+    assert openings == ints_of(fused["openings"])[:-1]
+
+
+def test_stepping_out_of_order_is_flagged(zc):
+    mu = 4
+    inst = I.make_instance(3, 0, mu, 0, 0)
+    s = zc.shape(mu, 0, 0)
+    ws = zc.new_workspace(s)
+    tabs = [zc.pack(dev(t), ws) for t in inst.tables]
+    r = dev(inst.r)
+    ev, al, _ = zc.new_outputs(s)
+    zc.round_(s, tabs, r, ws, 1, ev, al)
+    zc.round_(s, tabs, r, ws, 2, ev, al)  # fold(1) skipped
+    assert zc.read_error(ws) == zc.ZC_ESTATE
+
+
+def test_pack_flags_noncanonical_and_unpack_roundtrips(zc):
+    s = zc.shape(4, 0)
+    ws = zc.new_workspace(s)
+    vals = [0, 1, P - 1, 12345, P, (1 << 256) - 1]
+    t = zc.pack(dev(limbs_of(vals)), ws)
+    assert zc.read_error(ws) == zc.ZC_ERANGE
+    ok = [0, 1, P - 1, 12345, P // 3]
+    t = zc.pack(dev(limbs_of(ok)), ws)
+    assert ints_of(zc.unpack(t)) == ok
+    # packed form is x * 2^261 mod p, limb-planar
+    planar = t.cpu().numpy()
+    assert ints_of(planar.T.copy()) == [x * R_MONT % P for x in ok]
+
+
+def test_r_not_canonical_is_flagged(zc):
+    inst = I.make_instance(4, 0, 3, 0, 0)
+    inst.r[1] = limbs_of([P])[0]
+    res = gpu_prove(inst)
+    assert res["err"] == zc.ZC_ERANGE
+
+
+def test_repeat_runs_are_identical_and_tables_untouched(zc):
+    inst = I.make_instance(8, 0, 11, 1, 4)
+    res = gpu_prove(inst)
+    before = [t.clone() for t in res["tables"]]
+    again = zc.prove(res["shape"], res["tables"], res["r"], res["ws"])
+    torch.cuda.synchronize()
+    for a, b in zip(before, res["tables"]):
+        assert torch.equal(a, b)
+    assert (again[0].cpu().numpy() == res["evals"]).all()
+    assert (again[2].cpu().numpy() == res["openings"]).all()
+
+
+@pytest.mark.parametrize("name", ["plain20_d3", "plain20_d9"])
+def test_full_size_matches_c_oracle(zc, name):
+    inst = I.preset_instance(name)
+    res = gpu_prove(inst)
+    assert res["err"] == 0
+    ora = C.prove(inst.mu, inst.gate, inst.m, inst.tables, inst.r)
+    assert (res["evals"] == ora["evals"]).all()
+    assert (res["alphas"] == ora["alphas"]).all()
+    assert (res["openings"] == ora["openings"]).all()
