@@ -1,0 +1,220 @@
+#!/usr/bin/env python3
+"""Throughput of the MI355X SumCheck prover for multilinear ZeroCheck.
+
+One step = one whole proof (zc_prove: eq build, mu rounds of fused
+fold + evaluate + on-device challenge, openings) of one synthetic instance
+whose tables are already resident in HBM.  The metric is hypercube points/s
+= 2^mu / proof time.  Default workload: mu = 20 (2^20 points), the degree-3
+vanilla gate over BN254 Fr; the degree-9 product gate at mu = 20 is measured
+the same way and reported under "secondary".
+
+The JSON line also carries
+* "roofline": the fused fold+evaluate round kernel (the dominant kernel),
+  timed with HIP events around each of its launches inside the timed
+  region, against the HBM roofline (algorithmic bytes) and the integer
+  multiply roofline (algorithmic v_mad_u64_u32 count); "bound" names the
+  one closer to its peak, the other is under "roofline_other";
+* "cpu_baseline": the C oracle proving the same instance on the host cores
+  (its outputs are also compared with the GPU's, byte for byte).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+METRIC = "hypercube points/s, ZeroCheck SumCheck mu=20 deg 3 & 9; p50/p99 latency served"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+# v_mad_u64_u32 occupies a SIMD for 4 cycles per wave64 (16 lanes/clock):
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+MAD_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+MADS_PER_MUL = 162  # radix-2^29 Montgomery product: 81 a_i*b_j + 81 m_i*p_j
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def gate_products(gate: int, m: int) -> int:
+    """Field products per evaluation point: gate products + 1 for eq."""
+    return (4 if gate == 0 else m) + 1
+
+
+def round_work(mu, gate, m, k, d, i):
+    """Algorithmic (bytes, field products) of the round-i kernel launch."""
+    K = k + 1
+    q = 1 << (mu - i)
+    evalp = (d + 2) * gate_products(gate, m)
+    if i == 1:
+        return q * 2 * K * 32, q * evalp
+    return q * 6 * K * 32, q * (2 * K + evalp)
+
+
+def run_workload(name, steps, warmup, cpu_baseline):
+    import torch
+
+    from paper_2606_16146_amd import inputs as I
+    from paper_2606_16146_amd import zc
+
+    cfg = I.PRESETS[name]
+    mu, gate, m = cfg["mu"], cfg["gate"], cfg["m"]
+    t0 = time.time()
+    inst = I.preset_instance(name)
+    log(f"[bench] {name}: generated inputs in {time.time() - t0:.1f}s")
+
+    s = zc.shape(mu, gate, m)
+    k, d = zc.table_count(s), zc.degree(s)
+    dev = torch.device("cuda:0")
+    ws = zc.new_workspace(s, dev)
+    tabs = [zc.pack(torch.from_numpy(t).to(dev), ws) for t in inst.tables]
+    r = torch.from_numpy(inst.r).to(dev)
+    outs = zc.new_outputs(s, dev)
+    if zc.read_error(ws) != 0:
+        raise RuntimeError("pack flagged an input")
+    ev = zc.HipEvents(2 * mu * steps)
+
+    for _ in range(warmup):
+        zc.prove(s, tabs, r, ws, outs)
+    torch.cuda.synchronize()
+
+    # timed region: exactly `steps` proofs
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for st in range(steps):
+        zc.prove_profiled(s, tabs, r, ws, ev, outs, first_event=st * 2 * mu)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    err = zc.read_error(ws)
+    if err != 0:
+        raise RuntimeError(f"device error {err}")
+
+    # per-launch durations of the round kernels, from the events.  The dominant
+    # kernel is the fused fold+evaluate round with one thread per pair
+    # (kind 0, rounds >= 2); the lane-split rounds and the tail are reported
+    # separately.
+    kinds = [zc.lib().zc_prove_round_kernel(mu, i) for i in range(1, mu + 1)]
+    fused_t, fused_b, fused_p, first_t, split_t = 0.0, 0, 0, 0.0, 0.0
+    launches = 0
+    for st in range(steps):
+        for i in range(1, mu + 1):
+            a = st * 2 * mu + 2 * (i - 1)
+            dt = ev.elapsed_ms(a, a + 1) * 1e-3
+            b, p = round_work(mu, gate, m, k, d, i)
+            if i == 1:
+                first_t += dt
+            elif kinds[i - 1] == 0:
+                fused_t += dt
+                fused_b += b
+                fused_p += p
+                launches += 1
+            else:
+                split_t += dt
+    avg_launch_s = fused_t / launches
+    gbs = fused_b / fused_t / 1e9
+    tops = fused_p * MADS_PER_MUL / fused_t / 1e12
+    hbm = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None}
+    alu = {"bound": "alu", "achieved": round(tops, 2), "peak": round(MAD_PEAK_TOPS, 2),
+           "unit": "TOP/s (v_mad_u64_u32)", "frac": round(tops / MAD_PEAK_TOPS, 4), "traffic": None}
+    common = {"kernel": f"k_round<{'GateVanilla' if gate == 0 else f'GateProd<{m}>'}, true>",
+              "launches": launches, "avg_launch_us": round(avg_launch_s * 1e6, 2),
+              "algorithmic_bytes_per_launch": fused_b // launches,
+              "algorithmic_mads_per_launch": fused_p * MADS_PER_MUL // launches}
+    hbm.update(common)
+    alu.update(common)
+    bound, other = (alu, hbm) if alu["frac"] >= hbm["frac"] else (hbm, alu)
+
+    points = 1 << mu
+    res = {
+        "value": steps * points / elapsed,
+        "ms_per_step": elapsed / steps * 1e3,
+        "roofline": bound,
+        "roofline_other": other,
+        "round1_avg_us": round(first_t / steps * 1e6, 2),
+        "split_and_tail_avg_us": round(split_t / steps * 1e6, 2),
+        "round_kernels_share": round((fused_t + first_t + split_t) / elapsed, 4),
+        "config": {"workload": name, "mu": mu, "gate": "vanilla" if gate == 0 else f"prod{m}",
+                   "degree": d, "tables": k + 1, "field": "BN254 Fr", "seed": cfg["seed"]},
+    }
+    log(f"[bench] {name}: {res['ms_per_step']:.3f} ms/proof, {res['value'] / 1e6:.1f} M points/s")
+
+    if cpu_baseline:
+        from oracle import c_oracle as C
+        times = []
+        ora = None
+        for _ in range(3):
+            t0 = time.perf_counter()
+            ora = C.prove(mu, gate, m, inst.tables, inst.r)
+            times.append(time.perf_counter() - t0)
+        tmed = statistics.median(times)
+        same = bool((outs[0].cpu().numpy() == ora["evals"]).all()
+                    and (outs[1].cpu().numpy() == ora["alphas"]).all()
+                    and (outs[2].cpu().numpy() == ora["openings"]).all())
+        res["cpu_baseline"] = {"value": points / tmed, "unit": "points/s", "cores": C.max_threads(),
+                               "kind": "oracle",
+                               "sample": f"C oracle (OpenMP), whole {name} proof, median of 3 runs "
+                                         f"({tmed:.2f} s each)"}
+        res["parity_vs_oracle"] = "bit-exact" if same else "MISMATCH"
+        log(f"[bench] {name}: C oracle {tmed:.2f}s on {C.max_threads()} threads, parity={same}")
+        if not same:
+            raise RuntimeError("GPU proof differs from the C oracle")
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="plain20_d3")
+    ap.add_argument("--secondary", default="plain20_d9", help="second workload ('' to skip)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the prover runs on a single MI355X; "
+              "multi-GPU sharding is not part of this build (use --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    from paper_2606_16146_amd import zc
+    zc.lib()  # fail loudly if the HIP library is missing
+
+    main_res = run_workload(args.workload, args.steps, args.warmup, not args.no_cpu_baseline)
+    out = {
+        "metric": METRIC,
+        "value": main_res["value"],
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_res["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": main_res["config"],
+        "roofline": main_res["roofline"],
+        "roofline_other": main_res["roofline_other"],
+    }
+    for key in ("cpu_baseline", "parity_vs_oracle", "round1_avg_us", "split_and_tail_avg_us",
+                "round_kernels_share"):
+        if key in main_res:
+            out[key] = main_res[key]
+    if args.secondary:
+        sec = run_workload(args.secondary, args.steps, args.warmup, not args.no_cpu_baseline)
+        out["secondary"] = {k: v for k, v in sec.items()}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

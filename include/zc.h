@@ -80,7 +80,8 @@ int zc_degree(const zc_shape* shape);
 size_t zc_workspace_bytes(const zc_shape* shape);
 
 /* Convert n canonical elements (canon: uint32[n][8], 16-byte aligned) into the
-   internal limb-planar Montgomery form (mont_planar: uint32[8][n], pitch n).
+   internal limb-planar Montgomery form (mont_planar: uint32[8][n], pitch n),
+   1 <= n <= 2^31.
    Elements >= p are flagged (ZC_ERANGE via zc_read_error); only the control
    block of ws is used, so a workspace of any valid shape will do. */
 int zc_pack(const uint32_t* canon, uint32_t* mont_planar, uint64_t n, void* ws, hipStream_t stream);

@@ -1,5 +1,5 @@
 /*
- * zc_testing.h -- test hooks of libzc (not part of the prover's API).
+ * zc_testing.h -- test and measurement hooks of libzc (not part of the prover's API).
  *
  * They run single device building blocks of the prover on caller buffers so
  * that tests can compare them with Python integers and hashlib: the field
@@ -14,6 +14,8 @@
 #include <stdint.h>
 
 #include <hip/hip_runtime_api.h>
+
+#include "zc.h"
 
 #ifdef __cplusplus
 extern "C" {
@@ -31,6 +33,20 @@ typedef enum {
 
 /* Element-wise op over n elements: a, b, out are uint32[n][8]. */
 int zc_test_field(int op, const uint32_t* a, const uint32_t* b, uint32_t* out, uint64_t n, hipStream_t stream);
+
+/* zc_prove (same launches, same outputs) with a HIP event recorded on
+   `stream` right before and right after the round kernel of every round:
+   events is a host array of 2*mu hipEvent_t, round i bracketed by
+   events[2(i-1)] and events[2(i-1)+1].  For measuring the round kernels. */
+int zc_prove_profiled(const zc_shape* shape, const uint32_t* const* tables, const uint32_t* r, void* ws,
+                      uint32_t* round_evals, uint32_t* challenges, uint32_t* openings, void* events,
+                      hipStream_t stream);
+
+/* Which kernel zc_prove uses for round i of a mu-variable proof:
+   0 one thread per pair, 1 sixteen lanes per pair, 2 sixteen lanes per pair
+   whose last block then runs all later rounds and the openings, 3 a round run
+   inside such a tail.  Negative zc_status for bad arguments. */
+int zc_prove_round_kernel(uint32_t mu, uint32_t i);
 
 /* SHA-256 of len bytes (msg: little-endian packed uint32 words); out: 32 bytes as uint32[8]. */
 int zc_test_sha256(const uint32_t* msg, uint32_t len, uint32_t* out, hipStream_t stream);

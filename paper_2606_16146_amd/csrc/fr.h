@@ -265,6 +265,20 @@ __device__ __forceinline__ Fe fe_mul(const Fe& a, const Fe& b) {
   return r;
 }
 
+// k * a for a small integer k <= 15 and a normalized a < p; result < k p,
+// normalized (each limb product is one v_mad_u64_u32 with the running carry).
+__device__ __forceinline__ Fe fe_mul_small(const Fe& a, uint32_t k) {
+  Fe r;
+  uint64_t c = 0;
+#pragma unroll
+  for (int i = 0; i < NL; ++i) {
+    c = (uint64_t)a.l[i] * k + c;
+    r.l[i] = (i == NL - 1) ? (uint32_t)c : ((uint32_t)c & LM);
+    c >>= 29;
+  }
+  return r;
+}
+
 // canonical x < p  ->  Montgomery form x*R mod p, < p.
 __device__ __forceinline__ Fe fe_to_mont(const Fe& x) { return fe_reduce2(fe_mul(x, fe_const(kR2))); }
 

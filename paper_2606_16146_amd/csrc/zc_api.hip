@@ -6,7 +6,10 @@
 #include <cstdint>
 
 #include "../../include/zc.h"
+#include "../../include/zc_testing.h"
 #include "zc_kernels.h"
+#include "zc_launch.h"
+#include "zc_misc_kernels.h"
 
 using namespace zc;
 
@@ -69,58 +72,42 @@ inline int launch_ok() { return hipGetLastError() == hipSuccess ? ZC_OK : ZC_EHI
 inline Ctrl* ctrl_of(void* ws) { return reinterpret_cast<Ctrl*>(ws); }
 inline uint8_t* bytes(void* ws) { return reinterpret_cast<uint8_t*>(ws); }
 
-template <class Gate>
-int launch_round(bool fold, const TabPtrs& src, const TabPtrs& dst, uint64_t src_pitch, uint64_t dst_pitch,
-                 uint64_t q, const uint32_t* alpha, uint32_t* partials, uint32_t* nblocks, hipStream_t st) {
-  const uint32_t blocks = grid_for(q, kMaxBlocks);
-  *nblocks = blocks;
-  if (fold)
-    hipLaunchKernelGGL((k_round<Gate, true>), dim3(blocks), dim3(kBlock), 0, st, src, dst, src_pitch, dst_pitch,
-                       q, alpha, partials);
-  else
-    hipLaunchKernelGGL((k_round<Gate, false>), dim3(blocks), dim3(kBlock), 0, st, src, dst, src_pitch,
-                       dst_pitch, q, alpha, partials);
-  return launch_ok();
-}
-
-int dispatch_round(const zc_shape* s, bool fold, const TabPtrs& src, const TabPtrs& dst, uint64_t src_pitch,
-                   uint64_t dst_pitch, uint64_t q, const uint32_t* alpha, uint32_t* partials, uint32_t* nblocks,
-                   hipStream_t st) {
-#define ZC_R(G) launch_round<G>(fold, src, dst, src_pitch, dst_pitch, q, alpha, partials, nblocks, st)
-  if (s->gate == ZC_GATE_VANILLA) return ZC_R(GateVanilla);
+int dispatch_round(const zc_shape* s, bool fold, RoundKind kind, const RoundArgs& a, hipStream_t st) {
+  if (s->gate == ZC_GATE_VANILLA) return launch_round_vanilla(fold, kind, a, st);
   switch (s->m) {
-    case 1: return ZC_R(GateProd<1>);
-    case 2: return ZC_R(GateProd<2>);
-    case 3: return ZC_R(GateProd<3>);
-    case 4: return ZC_R(GateProd<4>);
-    case 5: return ZC_R(GateProd<5>);
-    case 6: return ZC_R(GateProd<6>);
-    case 7: return ZC_R(GateProd<7>);
-    case 8: return ZC_R(GateProd<8>);
+    case 1: return launch_round_prod1(fold, kind, a, st);
+    case 2: return launch_round_prod2(fold, kind, a, st);
+    case 3: return launch_round_prod3(fold, kind, a, st);
+    case 4: return launch_round_prod4(fold, kind, a, st);
+    case 5: return launch_round_prod5(fold, kind, a, st);
+    case 6: return launch_round_prod6(fold, kind, a, st);
+    case 7: return launch_round_prod7(fold, kind, a, st);
+    case 8: return launch_round_prod8(fold, kind, a, st);
     default: return ZC_EUNSUPPORTED;
   }
-#undef ZC_R
 }
 
-int launch_finish(uint32_t ne, const uint32_t* partials, uint32_t nparts, Ctrl* ctrl, uint32_t round,
-                  uint32_t* evals_out, uint32_t* alpha_out, hipStream_t st) {
-#define ZC_F(NE)                                                                                              \
-  case NE:                                                                                                    \
-    hipLaunchKernelGGL(k_finish<NE>, dim3(1), dim3(kBlock), 0, st, partials, nparts, ctrl, round, evals_out, \
-                       alpha_out);                                                                            \
-    break;
-  switch (ne) {
-    ZC_F(4) ZC_F(5) ZC_F(6) ZC_F(7) ZC_F(8) ZC_F(9) ZC_F(10) ZC_F(11)
-    default: return ZC_EUNSUPPORTED;
-  }
-#undef ZC_F
-  return launch_ok();
+RoundArgs round_args(const zc_shape* s, const Layout& L, void* ws, const uint32_t* r, uint32_t i,
+                     uint32_t* round_evals, uint32_t* challenges) {
+  RoundArgs a{};
+  a.q = 1ull << (s->mu - i);
+  a.round = i;
+  a.with_t0 = (i == 1) ? 1u : 0u;
+  a.mu = s->mu;
+  a.gate = s->gate;
+  a.m = s->m;
+  a.r = r;
+  a.partials = reinterpret_cast<uint32_t*>(bytes(ws) + L.partials);
+  a.ctrl = ctrl_of(ws);
+  a.evals_out = round_evals + (uint64_t)(i - 1) * (L.d + 2) * 8;
+  a.alpha_out = challenges + (uint64_t)(i - 1) * 8;
+  return a;
 }
 
-// r -> Montgomery, T_0, eq half tables, eq table (pitch 2^mu) in ws.
+// r -> Montgomery, eq half tables, eq table (pitch 2^mu) in ws.
 int launch_setup(const zc_shape* s, const Layout& L, const uint32_t* r, void* ws, hipStream_t st) {
   Ctrl* ctrl = ctrl_of(ws);
-  hipLaunchKernelGGL(k_setup, dim3(1), dim3(64), 0, st, r, s->mu, s->gate, s->m, ctrl);
+  hipLaunchKernelGGL(k_setup, dim3(1), dim3(64), 0, st, r, s->mu, ctrl);
   if (launch_ok() != ZC_OK) return ZC_EHIP;
   uint32_t* hi = reinterpret_cast<uint32_t*>(bytes(ws) + L.hi);
   uint32_t* lo = reinterpret_cast<uint32_t*>(bytes(ws) + L.lo);
@@ -143,6 +130,55 @@ int check_tables(const Layout& L, const uint32_t* const* tables) {
   return ZC_OK;
 }
 
+// Whole proof.  With `ev` (2*mu events) the round kernel of round i is
+// bracketed by ev[2(i-1)] and ev[2(i-1)+1] on the same stream.
+int prove_impl(const zc_shape* shape, const uint32_t* const* tables, const uint32_t* r, void* ws,
+               uint32_t* round_evals, uint32_t* challenges, uint32_t* openings, hipStream_t stream,
+               hipEvent_t* ev) {
+  Layout L;
+  int rc = make_layout(shape, &L);
+  if (rc != ZC_OK) return rc;
+  if ((rc = check_tables(L, tables)) != ZC_OK) return rc;
+  if (!r || !ws || !round_evals || !challenges || !openings || !aligned(ws, 256)) return ZC_EINVAL;
+  const uint32_t mu = shape->mu, K = L.k + 1;
+  const uint64_t n = 1ull << mu;
+  Ctrl* ctrl = ctrl_of(ws);
+  uint32_t* eq = reinterpret_cast<uint32_t*>(bytes(ws) + L.eq);
+  uint32_t* scratch = reinterpret_cast<uint32_t*>(bytes(ws) + L.scratch);
+  const uint64_t half = n / 2;
+
+  TabPtrs orig{}, fold{};
+  for (uint32_t t = 0; t < L.k; ++t) orig.p[t] = const_cast<uint32_t*>(tables[t]);
+  orig.p[L.k] = eq;
+  for (uint32_t t = 0; t < K; ++t) fold.p[t] = scratch + (uint64_t)t * half * 8;
+
+  if ((rc = launch_setup(shape, L, r, ws, stream)) != ZC_OK) return rc;
+  for (uint32_t i = 1; i <= mu; ++i) {
+    const RoundKind kind = prove_round_kind(mu, i);
+    if (kind == kInTail) {  // evaluated inside the tail of an earlier launch
+      if (ev && (hipEventRecord(ev[2 * (i - 1)], stream) != hipSuccess ||
+                 hipEventRecord(ev[2 * (i - 1) + 1], stream) != hipSuccess))
+        return ZC_EHIP;
+      continue;
+    }
+    RoundArgs a = round_args(shape, L, ws, r, i, round_evals, challenges);
+    a.openings = openings;
+    if (i == 1) {
+      a.src = a.dst = orig;
+      a.src_pitch = a.dst_pitch = n;
+    } else {
+      a.src = i == 2 ? orig : fold;
+      a.src_pitch = i == 2 ? n : half;
+      a.dst = fold;
+      a.dst_pitch = half;
+    }
+    if (ev && hipEventRecord(ev[2 * (i - 1)], stream) != hipSuccess) return ZC_EHIP;
+    if ((rc = dispatch_round(shape, i > 1, kind, a, stream)) != ZC_OK) return rc;
+    if (ev && hipEventRecord(ev[2 * (i - 1) + 1], stream) != hipSuccess) return ZC_EHIP;
+  }
+  return ZC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -157,55 +193,30 @@ size_t zc_workspace_bytes(const zc_shape* shape) {
 }
 
 int zc_pack(const uint32_t* canon, uint32_t* mont_planar, uint64_t n, void* ws, hipStream_t stream) {
-  if (!canon || !mont_planar || !ws || n == 0 || !aligned(canon, 16) || !aligned(ws, 256)) return ZC_EINVAL;
+  if (!canon || !mont_planar || !ws || n == 0 || n > (1ull << 31) || !aligned(canon, 16) || !aligned(ws, 256))
+    return ZC_EINVAL;
   hipLaunchKernelGGL(k_pack, dim3(grid_for(n, 8192)), dim3(kBlock), 0, stream, canon, mont_planar, n, n,
                      ctrl_of(ws));
   return launch_ok();
 }
 
 int zc_unpack(const uint32_t* mont_planar, uint64_t pitch, uint32_t* canon, uint64_t n, hipStream_t stream) {
-  if (!canon || !mont_planar || n == 0 || pitch < n || !aligned(canon, 16)) return ZC_EINVAL;
+  if (!canon || !mont_planar || n == 0 || n > (1ull << 31) || pitch < n || !aligned(canon, 16)) return ZC_EINVAL;
   hipLaunchKernelGGL(k_unpack, dim3(grid_for(n, 8192)), dim3(kBlock), 0, stream, mont_planar, pitch, canon, n);
   return launch_ok();
 }
 
 int zc_prove(const zc_shape* shape, const uint32_t* const* tables, const uint32_t* r, void* ws,
              uint32_t* round_evals, uint32_t* challenges, uint32_t* openings, hipStream_t stream) {
-  Layout L;
-  int rc = make_layout(shape, &L);
-  if (rc != ZC_OK) return rc;
-  if ((rc = check_tables(L, tables)) != ZC_OK) return rc;
-  if (!r || !ws || !round_evals || !challenges || !openings || !aligned(ws, 256)) return ZC_EINVAL;
-  const uint32_t mu = shape->mu, ne = L.d + 2, K = L.k + 1;
-  const uint64_t n = 1ull << mu;
-  Ctrl* ctrl = ctrl_of(ws);
-  uint32_t* eq = reinterpret_cast<uint32_t*>(bytes(ws) + L.eq);
-  uint32_t* partials = reinterpret_cast<uint32_t*>(bytes(ws) + L.partials);
-  uint32_t* scratch = reinterpret_cast<uint32_t*>(bytes(ws) + L.scratch);
-  const uint64_t half = n / 2;
+  return prove_impl(shape, tables, r, ws, round_evals, challenges, openings, stream, nullptr);
+}
 
-  TabPtrs orig{}, fold{};
-  for (uint32_t t = 0; t < L.k; ++t) orig.p[t] = const_cast<uint32_t*>(tables[t]);
-  orig.p[L.k] = eq;
-  for (uint32_t t = 0; t < K; ++t) fold.p[t] = scratch + (uint64_t)t * half * 8;
-
-  if ((rc = launch_setup(shape, L, r, ws, stream)) != ZC_OK) return rc;
-  for (uint32_t i = 1; i <= mu; ++i) {
-    const uint64_t q = 1ull << (mu - i);
-    uint32_t nb = 0;
-    if (i == 1)
-      rc = dispatch_round(shape, false, orig, orig, n, n, q, nullptr, partials, &nb, stream);
-    else
-      rc = dispatch_round(shape, true, i == 2 ? orig : fold, fold, i == 2 ? n : half, half, q,
-                          ctrl->alpha_m[i - 2], partials, &nb, stream);
-    if (rc != ZC_OK) return rc;
-    rc = launch_finish(ne, partials, nb, ctrl, i, round_evals + (uint64_t)(i - 1) * ne * 8,
-                       challenges + (uint64_t)(i - 1) * 8, stream);
-    if (rc != ZC_OK) return rc;
-  }
-  hipLaunchKernelGGL(k_openings, dim3(1), dim3(64), 0, stream, mu == 1 ? orig : fold, K, mu == 1 ? n : half, ctrl,
-                     mu, openings);
-  return launch_ok();
+int zc_prove_profiled(const zc_shape* shape, const uint32_t* const* tables, const uint32_t* r, void* ws,
+                      uint32_t* round_evals, uint32_t* challenges, uint32_t* openings, void* events,
+                      hipStream_t stream) {
+  if (!events) return ZC_EINVAL;
+  return prove_impl(shape, tables, r, ws, round_evals, challenges, openings, stream,
+                    reinterpret_cast<hipEvent_t*>(events));
 }
 
 int zc_round(const zc_shape* shape, const uint32_t* const* tables, const uint32_t* r, void* ws, uint32_t i,
@@ -216,10 +227,9 @@ int zc_round(const zc_shape* shape, const uint32_t* const* tables, const uint32_
   if ((rc = check_tables(L, tables)) != ZC_OK) return rc;
   if (!ws || !round_evals || !challenges || !aligned(ws, 256) || i < 1 || i > shape->mu) return ZC_EINVAL;
   if (i == 1 && !r) return ZC_EINVAL;
-  const uint32_t mu = shape->mu, ne = L.d + 2;
+  const uint32_t mu = shape->mu;
   const uint64_t n = 1ull << mu;
   Ctrl* ctrl = ctrl_of(ws);
-  uint32_t* partials = reinterpret_cast<uint32_t*>(bytes(ws) + L.partials);
   TabPtrs cur{};
   for (uint32_t t = 0; t < L.k; ++t) cur.p[t] = const_cast<uint32_t*>(tables[t]);
   cur.p[L.k] = reinterpret_cast<uint32_t*>(bytes(ws) + L.eq);
@@ -229,11 +239,10 @@ int zc_round(const zc_shape* shape, const uint32_t* const* tables, const uint32_
     hipLaunchKernelGGL(k_check_round, dim3(1), dim3(1), 0, stream, ctrl, i);
     if ((rc = launch_ok()) != ZC_OK) return rc;
   }
-  uint32_t nb = 0;
-  rc = dispatch_round(shape, false, cur, cur, n, n, 1ull << (mu - i), nullptr, partials, &nb, stream);
-  if (rc != ZC_OK) return rc;
-  return launch_finish(ne, partials, nb, ctrl, i, round_evals + (uint64_t)(i - 1) * ne * 8,
-                       challenges + (uint64_t)(i - 1) * 8, stream);
+  RoundArgs a = round_args(shape, L, ws, r, i, round_evals, challenges);
+  a.src = a.dst = cur;
+  a.src_pitch = a.dst_pitch = n;
+  return dispatch_round(shape, false, a.q > kSplitQ ? kPerPair : kSplit, a, stream);
 }
 
 int zc_fold(const zc_shape* shape, uint32_t* const* tables, void* ws, uint32_t i, hipStream_t stream) {
@@ -260,6 +269,11 @@ int zc_read_error(void* ws, hipStream_t stream) {
   uint32_t err = 0;
   if (hipMemcpy(&err, &ctrl_of(ws)->err, sizeof(err), hipMemcpyDeviceToHost) != hipSuccess) return ZC_EHIP;
   return (int)(int32_t)err;
+}
+
+int zc_prove_round_kernel(uint32_t mu, uint32_t i) {
+  if (mu < 1 || mu > (uint32_t)kMuMax || i < 1 || i > mu) return ZC_EINVAL;
+  return (int)prove_round_kind(mu, i);
 }
 
 const char* zc_strerror(int status) {

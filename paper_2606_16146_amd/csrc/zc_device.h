@@ -21,7 +21,7 @@ struct Ctrl {
   uint32_t err;         // first device-detected error (negative status), 0 if none
   uint32_t round_done;  // last round whose challenge has been derived
   uint32_t fold_done;   // last round whose fold has been applied
-  uint32_t pad0;
+  uint32_t counter;     // blocks of the running round kernel that have finished
   uint32_t ts[8];                 // transcript digest T_i (little-endian bytes)
   uint32_t alpha_m[kMuMax][8];    // alpha_i, Montgomery form, < p
   uint32_t r_m[kMuMax][8];        // r_i, Montgomery form, < p
@@ -40,19 +40,52 @@ __device__ __forceinline__ void set_error(Ctrl* c, int32_t code) {
 }
 
 // ---- limb-planar element access ----------------------------------------------
+//
+// Limb l of element j lives at base[l * pitch + j].  The plane address
+// base + l * pitch is uniform across the wave (scalar registers) and the
+// per-lane part is the 32-bit byte offset 4j, so each limb is one
+// global_load_dword with a scalar base and a 32-bit vector offset.  Element
+// indices are below 2^30 (tables of at most 2^30 entries).
 
-__device__ __forceinline__ Fe load_el(const uint32_t* __restrict__ base, uint64_t pitch, uint64_t j) {
-  uint32_t w[8];
+__device__ __forceinline__ const uint32_t* plane_ptr(const uint32_t* base, uint64_t pitch, int l) {
+  return base + (uint64_t)l * pitch;
+}
+
+__device__ __forceinline__ void load_words(const uint32_t* __restrict__ base, uint64_t pitch, uint32_t j,
+                                           uint32_t w[8]) {
+  const uint32_t off = j << 2;
 #pragma unroll
-  for (int l = 0; l < 8; ++l) w[l] = base[(uint64_t)l * pitch + j];
+  for (int l = 0; l < 8; ++l)
+    w[l] = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(plane_ptr(base, pitch, l)) + off);
+}
+
+__device__ __forceinline__ Fe load_el(const uint32_t* __restrict__ base, uint64_t pitch, uint32_t j) {
+  uint32_t w[8];
+  load_words(base, pitch, j, w);
   return fe_from_words(w);
 }
 
-__device__ __forceinline__ void store_el(uint32_t* __restrict__ base, uint64_t pitch, uint64_t j, const Fe& a) {
+__device__ __forceinline__ void store_el(uint32_t* __restrict__ base, uint64_t pitch, uint32_t j, const Fe& a) {
   uint32_t w[8];
   fe_to_words(a, w);
+  const uint32_t off = j << 2;
 #pragma unroll
-  for (int l = 0; l < 8; ++l) base[(uint64_t)l * pitch + j] = w[l];
+  for (int l = 0; l < 8; ++l)
+    *reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(base + (uint64_t)l * pitch) + off) = w[l];
+}
+
+// The two entries (j, j + q) of a table, loaded but not yet converted, so that
+// the loads of the next table can be in flight during the current step.
+struct RawPair {
+  uint32_t w0[8], w1[8];
+};
+
+__device__ __forceinline__ RawPair issue_pair(const uint32_t* __restrict__ base, uint64_t pitch, uint32_t j,
+                                              uint32_t q) {
+  RawPair r;
+  load_words(base, pitch, j, r.w0);
+  load_words(base, pitch, j + q, r.w1);
+  return r;
 }
 
 __device__ __forceinline__ Fe load_words_fe(const uint32_t* p) {

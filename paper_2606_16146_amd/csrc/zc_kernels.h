@@ -22,44 +22,185 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "zc_device.h"
+#include "zc_launch.h"
 
 namespace zc {
 
+// ---- compile-time unrolling ------------------------------------------------------
+
+template <int I, int N>
+struct Unroll {
+  template <class F>
+  __device__ __forceinline__ static void run(F& f) {
+    f(std::integral_constant<int, I>{});
+    Unroll<I + 1, N>::run(f);
+  }
+};
+template <int N>
+struct Unroll<N, N> {
+  template <class F>
+  __device__ __forceinline__ static void run(F&) {}
+};
+
+// Converts a loaded pair to (lo, dl) = (t[j], t[j+q] - t[j] mod p).
+__device__ __forceinline__ void cvt_pair(const RawPair& r, Fe& lo, Fe& dl) {
+  lo = fe_from_words(r.w0);
+  dl = fe_submod(fe_from_words(r.w1), lo);
+}
+
+constexpr L9 kP11 = detail::mul_small(kP, 11);
+
 // ---- gates ---------------------------------------------------------------------
 //
-// eval() takes the extensions of the witness tables at one point X
-// (each < (D+2) p) and returns f_M at X, below 11 p.
+// eval() adds f_M(ext(X)) * eq(ext(X)) for X = 0..NE-1 of one pair to acc[X]
+// (kept < 2p).  The extension of a table at X is e(X) = lo + X*dl, built by
+// plain additions, so e(X) < (X+1) p.  The NE products of one step are
+// independent of each other, which keeps the multiply pipeline busy, and the
+// loads of the next table are issued before the current step's products so
+// that their latency is hidden.
 
-// f = qM*a*b + qL*a + qR*b + qO*c + qC, columns [a b c qM qL qR qO qC], degree 3.
+// f = qM*a*b + qL*a + qR*b + qO*c + qC, columns [a b c qM qL qR qO qC], degree 3,
+// evaluated as a*(qM*b + qL) + qR*b + qO*c + qC (four products per point).
 struct GateVanilla {
   static constexpr int K = 8;
   static constexpr int D = 3;
-  __device__ static __forceinline__ Fe eval(const Fe* e) {
-    // e < 5p.  a*(qM*b + qL) + qR*b + qO*c + qC: four products.
-    const Fe t1 = fe_mul(e[3], e[1]);            // < 2p (5*5)
-    const Fe t2 = fe_add(t1, e[4]);              // < 7p
-    const Fe t3 = fe_mul(e[0], t2);              // < 2p (5*7)
-    const Fe t4 = fe_mul(e[5], e[1]);            // < 2p
-    const Fe t5 = fe_mul(e[6], e[2]);            // < 2p
-    return fe_add(fe_add(fe_add(t3, t4), t5), e[7]);  // < 11p
+  static constexpr int NE = D + 2;
+  // f_M at one point from the witness extensions e[0..7] (< 5p); result < 11p.
+  __device__ static __forceinline__ Fe point(const Fe* e) {
+    const Fe t1 = fe_mul(e[3], e[1]);                     // qM*b < 2p
+    const Fe t3 = fe_mul(e[0], fe_add(t1, e[4]));         // a*(qM*b + qL) < 2p (5*7)
+    const Fe t4 = fe_mul(e[5], e[1]);                     // qR*b < 2p
+    const Fe t5 = fe_mul(e[6], e[2]);                     // qO*c < 2p
+    return fe_add(fe_add(fe_add(t3, t4), t5), e[7]);      // < 11p
+  }
+  __device__ static __forceinline__ void eval(const TabPtrs& tp, uint64_t pitch, uint32_t j, uint32_t q,
+                                              Fe (&acc)[NE]) {
+    Fe bx[NE], t[NE], lo, dl, e;
+    RawPair ra = issue_pair(tp.p[1], pitch, j, q);  // b
+    RawPair rb = issue_pair(tp.p[3], pitch, j, q);  // qM
+    cvt_pair(ra, lo, dl);
+    ra = issue_pair(tp.p[4], pitch, j, q);  // qL
+    auto fb = [&](auto x) __attribute__((always_inline)) {
+      bx[x] = (x == 0) ? lo : fe_add(bx[x > 0 ? x - 1 : 0], dl);  // < 5p
+    };
+    Unroll<0, NE>::run(fb);
+    cvt_pair(rb, lo, dl);  // qM
+    rb = issue_pair(tp.p[0], pitch, j, q);  // a
+    e = lo;
+    auto f1 = [&](auto x) __attribute__((always_inline)) {
+      t[x] = fe_mul(e, bx[x]);  // < 2p
+      e = fe_add(e, dl);
+    };
+    Unroll<0, NE>::run(f1);
+    cvt_pair(ra, lo, dl);  // qL
+    ra = issue_pair(tp.p[5], pitch, j, q);  // qR
+    e = lo;
+    auto f2 = [&](auto x) __attribute__((always_inline)) {
+      t[x] = fe_add(t[x], e);  // < 7p
+      e = fe_add(e, dl);
+    };
+    Unroll<0, NE>::run(f2);
+    cvt_pair(rb, lo, dl);  // a
+    rb = issue_pair(tp.p[6], pitch, j, q);  // qO
+    e = lo;
+    auto f3 = [&](auto x) __attribute__((always_inline)) {
+      t[x] = fe_mul(e, t[x]);  // < 2p (5*7)
+      e = fe_add(e, dl);
+    };
+    Unroll<0, NE>::run(f3);
+    cvt_pair(ra, lo, dl);  // qR
+    ra = issue_pair(tp.p[2], pitch, j, q);  // c
+    e = lo;
+    auto f4 = [&](auto x) __attribute__((always_inline)) {
+      t[x] = fe_add(t[x], fe_mul(e, bx[x]));  // < 4p
+      e = fe_add(e, dl);
+    };
+    Unroll<0, NE>::run(f4);
+    Fe lo2, dl2, e2;
+    cvt_pair(rb, lo, dl);    // qO
+    cvt_pair(ra, lo2, dl2);  // c
+    rb = issue_pair(tp.p[7], pitch, j, q);  // qC
+    ra = issue_pair(tp.p[8], pitch, j, q);  // eq
+    e = lo;
+    e2 = lo2;
+    auto f5 = [&](auto x) __attribute__((always_inline)) {
+      t[x] = fe_add(t[x], fe_mul(e, e2));  // < 6p
+      e = fe_add(e, dl);
+      e2 = fe_add(e2, dl2);
+    };
+    Unroll<0, NE>::run(f5);
+    cvt_pair(rb, lo, dl);  // qC
+    e = lo;
+    auto f6 = [&](auto x) __attribute__((always_inline)) {
+      t[x] = fe_add(t[x], e);  // f < 11p
+      e = fe_add(e, dl);
+    };
+    Unroll<0, NE>::run(f6);
+    cvt_pair(ra, lo, dl);  // eq
+    e = lo;
+    auto f7 = [&](auto x) __attribute__((always_inline)) {
+      acc[x] = fe_csub(fe_add(acc[x], fe_mul(t[x], e)), kP2);  // product < 2p (11*5); acc < 2p
+      e = fe_add(e, dl);
+    };
+    Unroll<0, NE>::run(f7);
   }
 };
-
-constexpr L9 kP11 = detail::mul_small(kP, 11);
 
 // f = s*w1*...*wm - o, columns [s w1 .. wm o], degree m+1.
 template <int M>
 struct GateProd {
   static constexpr int K = M + 2;
   static constexpr int D = M + 1;
-  __device__ static __forceinline__ Fe eval(const Fe* e) {
-    // e < (M+3) p <= 11 p.
-    Fe prod = fe_mul(e[0], e[1]);  // < 2p (11*11 <= 121)
-#pragma unroll
-    for (int k = 2; k <= M; ++k) prod = fe_mul(prod, e[k]);  // < 2p (2*11)
-    // prod + 11p - o  in (0, 13p)  ->  < 8p after one conditional subtraction
+  static constexpr int NE = D + 2;
+  // f_M at one point from the witness extensions e[0..K-1] (< 11p); result < 8p.
+  __device__ static __forceinline__ Fe point(const Fe* e) {
+    Fe prod = fe_mul(e[0], e[1]);  // < 2p (11*11)
+    auto f = [&](auto k) __attribute__((always_inline)) { prod = fe_mul(prod, e[k]); };  // < 2p (2*11)
+    Unroll<2, M + 1>::run(f);
     return fe_csub(fe_sub_plus(prod, e[M + 1], kP11), kP8);
+  }
+  __device__ static __forceinline__ void eval(const TabPtrs& tp, uint64_t pitch, uint32_t j, uint32_t q,
+                                              Fe (&acc)[NE]) {
+    // extensions are < (M+3) p <= 11 p
+    Fe pr[NE], lo, dl, e;
+    RawPair cur = issue_pair(tp.p[0], pitch, j, q);  // s
+    RawPair nxt = issue_pair(tp.p[1], pitch, j, q);  // w1
+    cvt_pair(cur, lo, dl);
+    auto f0 = [&](auto x) __attribute__((always_inline)) {
+      pr[x] = (x == 0) ? lo : fe_add(pr[x > 0 ? x - 1 : 0], dl);
+    };
+    Unroll<0, NE>::run(f0);
+#pragma unroll 1
+    for (int k = 1; k <= M; ++k) {  // pr *= w_k  (< 2p after each product: 11*11, then 2*11)
+      cur = nxt;
+      nxt = issue_pair(tp.p[k + 1], pitch, j, q);  // w_{k+1}, or o after the last w
+      cvt_pair(cur, lo, dl);
+      e = lo;
+      auto fk = [&](auto x) __attribute__((always_inline)) {
+        pr[x] = fe_mul(pr[x], e);
+        e = fe_add(e, dl);
+      };
+      Unroll<0, NE>::run(fk);
+    }
+    cur = nxt;                                       // o
+    nxt = issue_pair(tp.p[M + 2], pitch, j, q);      // eq
+    cvt_pair(cur, lo, dl);  // o: pr + 11p - o in (0, 13p) -> < 8p
+    e = lo;
+    auto fo = [&](auto x) __attribute__((always_inline)) {
+      pr[x] = fe_csub(fe_sub_plus(pr[x], e, kP11), kP8);
+      e = fe_add(e, dl);
+    };
+    Unroll<0, NE>::run(fo);
+    cvt_pair(nxt, lo, dl);  // eq
+    e = lo;
+    auto fe_ = [&](auto x) __attribute__((always_inline)) {
+      acc[x] = fe_csub(fe_add(acc[x], fe_mul(pr[x], e)), kP2);  // product < 2p (8*11); acc < 2p
+      e = fe_add(e, dl);
+    };
+    Unroll<0, NE>::run(fe_);
   }
 };
 
@@ -72,25 +213,37 @@ __device__ __forceinline__ Fe shfl_xor_fe(const Fe& a, int mask) {
   return r;
 }
 
-// Sum (mod p) of NV values over the block; values < p on entry.  The block's
-// totals are written by thread 0 to out[v*8 .. v*8+7] as words (< p).
+__device__ __forceinline__ Fe lds_fe(const uint32_t* p) {
+  Fe r;
+#pragma unroll
+  for (int i = 0; i < NL; ++i) r.l[i] = p[i];
+  return r;
+}
+
+__device__ __forceinline__ void lds_put(uint32_t* p, const Fe& a) {
+#pragma unroll
+  for (int i = 0; i < NL; ++i) p[i] = a.l[i];
+}
+
+// Sum (mod p) over the block of NV values per thread (each < p).  Thread x < NV
+// returns the block total of value x; other threads return garbage.
 template <int NV>
-__device__ __forceinline__ void block_reduce_store(Fe (&v)[NV], uint32_t* __restrict__ out) {
+__device__ __forceinline__ Fe block_reduce(Fe (&v)[NV]) {
   __shared__ uint32_t red[kBlock / 64][NV][NL];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int x = 0; x < NV; ++x) {
+  auto f = [&](auto x) __attribute__((always_inline)) {
 #pragma unroll
     for (int s = 32; s >= 1; s >>= 1) v[x] = fe_addmod(v[x], shfl_xor_fe(v[x], s));
     if (lane == 0) {
 #pragma unroll
       for (int i = 0; i < NL; ++i) red[wave][x][i] = v[x].l[i];
     }
-  }
+  };
+  Unroll<0, NV>::run(f);
   __syncthreads();
+  Fe s = fe_zero();
   if (threadIdx.x < NV) {
     const int x = threadIdx.x;
-    Fe s;
 #pragma unroll
     for (int i = 0; i < NL; ++i) s.l[i] = red[0][x][i];
     for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
@@ -99,255 +252,332 @@ __device__ __forceinline__ void block_reduce_store(Fe (&v)[NV], uint32_t* __rest
       for (int i = 0; i < NL; ++i) t.l[i] = red[w][x][i];
       s = fe_addmod(s, t);
     }
-    store_words_fe(out + x * 8, s);
   }
+  return s;
 }
 
 // ---- round kernel ---------------------------------------------------------------
-//
+
+struct RoundArgs {
+  TabPtrs src, dst;
+  uint64_t src_pitch, dst_pitch;
+  uint64_t q;                  // pairs of the evaluated round
+  uint32_t round;              // i (1-based)
+  uint32_t with_t0;            // 1: the last block computes T_0 (first round of a proof)
+  uint32_t mu, gate, m;        // for T_0
+  const uint32_t* r;           // canonical r (for T_0)
+  uint32_t* partials;          // [gridDim.x][NE][8]
+  Ctrl* ctrl;
+  uint32_t* evals_out;         // G_i(0..d+1), canonical
+  uint32_t* alpha_out;         // alpha_i, canonical
+  uint32_t tail;               // 1: the last block also runs rounds round+1..mu and the openings
+  uint32_t* openings;          // tail only: (k+1) x 8 canonical
+};
+
+// Emits G_r and derives alpha_r from the round totals: thread x < NE holds
+// G_r(x) (Montgomery form, < p).  Writes G_r canonical to evals_out, hashes
+// T_{r-1} || G_r(0..d+1) into T_r, stores alpha_r canonical to alpha_out and
+// in Montgomery form to the control block.  All threads of the block call it.
+template <int NE>
+__device__ __forceinline__ void finalize_round(Ctrl* ctrl, uint32_t round, const Fe& tot, uint32_t* evals_out,
+                                               uint32_t* alpha_out) {
+  __shared__ uint32_t msg[8 + 8 * NE];
+  if (threadIdx.x < NE) {
+    uint32_t w[8];
+    fe_to_words(fe_from_mont(tot), w);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      msg[8 + threadIdx.x * 8 + k] = w[k];
+      evals_out[threadIdx.x * 8 + k] = w[k];
+    }
+  }
+  if (threadIdx.x < 8) msg[threadIdx.x] = ctrl->ts[threadIdx.x];
+  __syncthreads();
+  constexpr uint32_t LEN = 32u * (1u + NE);
+  __shared__ uint32_t kw[((LEN + 9u + 63u) / 64u) * 64u];
+  uint32_t dg[8];
+  sha256_fixed_block<LEN>(msg, kw, dg);
+  if (threadIdx.x == 0) {
+    // alpha_r = digest (little-endian 256-bit integer) mod p; digest < 2^256 < 6p
+    Fe al = fe_from_words(dg);
+    al = fe_csub(fe_csub(fe_csub(al, kP4), kP2), kP);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) ctrl->ts[k] = dg[k];
+    store_words_fe(alpha_out, al);
+    store_words_fe(ctrl->alpha_m[round - 1], fe_to_mont(al));
+    ctrl->round_done = round;
+    ctrl->counter = 0;
+  }
+  __syncthreads();
+}
+
+// Sum of the blocks' partials, then finalize_round.  Runs in the last block
+// of a round kernel to finish.  Sixteen lanes own each point x: they stride
+// over the partials and combine with four shuffle steps.
+template <int NE>
+__device__ __forceinline__ void finish_round(const RoundArgs& a, uint32_t nparts) {
+  static_assert(NE * 16 <= kBlock, "16 lanes per point");
+  __shared__ uint32_t tot_lds[NE][NL];
+  const uint32_t x = threadIdx.x / 16, g = threadIdx.x % 16;
+  Fe s = fe_zero();
+  if (x < (uint32_t)NE) {
+    for (uint32_t b = g; b < nparts; b += 16)
+      s = fe_addmod(s, load_words_fe(a.partials + ((uint64_t)b * NE + x) * 8));
+  }
+#pragma unroll
+  for (int m = 8; m >= 1; m >>= 1) s = fe_addmod(s, shfl_xor_fe(s, m));
+  if (x < (uint32_t)NE && g == 0) lds_put(tot_lds[x], s);
+  __syncthreads();
+  Fe tot = fe_zero();
+  if (threadIdx.x < (uint32_t)NE) tot = lds_fe(tot_lds[threadIdx.x]);
+  finalize_round<NE>(a.ctrl, a.round, tot, a.evals_out, a.alpha_out);
+}
+
+// T_0 = SHA-256("ZCv1" || u32 mu || u32 gate || u32 m || enc(r_1..r_mu)).
+__device__ __forceinline__ void transcript_t0(const RoundArgs& a) {
+  __shared__ uint32_t m0[4 + kMuMax * 8];
+  if (threadIdx.x == 0) {
+    m0[0] = 0x3176435au;  // bytes 'Z' 'C' 'v' '1'
+    m0[1] = a.mu;
+    m0[2] = a.gate;
+    m0[3] = a.m;
+  }
+  for (uint32_t i = threadIdx.x; i < a.mu * 8; i += blockDim.x) m0[4 + i] = a.r[i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t dg[8];
+    sha256(m0, 16u + 32u * a.mu, dg);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a.ctrl->ts[k] = dg[k];
+  }
+}
+
 // FOLD = false: evaluate G_i on tables holding 2q live entries (pairs j, j+q).
 // FOLD = true : the tables hold 4q entries; fold them with alpha_{i-1}
 //               (u[j] = t[j] + alpha (t[j+2q] - t[j]), same for j+q), write
 //               u[j], u[j+q] to dst, then evaluate G_i on (u[j], u[j+q]).
-// Every block writes its d+2 partial sums (Montgomery, < p) to partials.
+// Each block stores its d+2 partial sums; the last block to finish sums them,
+// emits G_i and derives alpha_i (no second launch, no host round trip).
 template <class Gate, bool FOLD>
-__global__ __launch_bounds__(kBlock) void k_round(TabPtrs src, TabPtrs dst, uint64_t src_pitch,
-                                                  uint64_t dst_pitch, uint64_t q,
-                                                  const uint32_t* __restrict__ alpha_words,
-                                                  uint32_t* __restrict__ partials) {
+__global__ __launch_bounds__(kBlock) void k_round(RoundArgs a) {
   constexpr int K = Gate::K + 1;  // witness tables + eq (last)
-  constexpr int NE = Gate::D + 2;
+  constexpr int NE = Gate::NE;
+  const uint32_t work_blocks = gridDim.x - (a.with_t0 ? 1u : 0u);
   Fe acc[NE];
-#pragma unroll
-  for (int x = 0; x < NE; ++x) acc[x] = fe_zero();
-  Fe alpha;
-  if (FOLD) alpha = load_words_fe(alpha_words);
+  auto z = [&](auto x) __attribute__((always_inline)) { acc[x] = fe_zero(); };
+  Unroll<0, NE>::run(z);
 
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < q; j += stride) {
-    Fe lo[K], dl[K];
-#pragma unroll
-    for (int t = 0; t < K; ++t) {
-      Fe u0, u1;
+  if (blockIdx.x < work_blocks) {
+    Fe alpha;
+    if (FOLD) alpha = load_words_fe(a.ctrl->alpha_m[a.round - 2]);
+    const uint32_t q = (uint32_t)a.q;
+    const uint32_t stride = work_blocks * blockDim.x;
+    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < q; j += stride) {
       if (FOLD) {
-        const Fe a0 = load_el(src.p[t], src_pitch, j);
-        const Fe a1 = load_el(src.p[t], src_pitch, j + q);
-        const Fe a2 = load_el(src.p[t], src_pitch, j + 2 * q);
-        const Fe a3 = load_el(src.p[t], src_pitch, j + 3 * q);
-        u0 = fe_addmod(a0, fe_reduce2(fe_mul(alpha, fe_submod(a2, a0))));
-        u1 = fe_addmod(a1, fe_reduce2(fe_mul(alpha, fe_submod(a3, a1))));
-        store_el(dst.p[t], dst_pitch, j, u0);
-        store_el(dst.p[t], dst_pitch, j + q, u1);
+        const uint64_t sp = a.src_pitch, dp = a.dst_pitch;
+        // fold table t while the four entries of table t+1 are loading
+        RawPair n01 = issue_pair(a.src.p[0], sp, j, q), n23 = issue_pair(a.src.p[0], sp, j + 2 * q, q);
+#pragma unroll 1
+        for (int t = 0; t < K; ++t) {
+          const RawPair c01 = n01, c23 = n23;
+          if (t + 1 < K) {
+            n01 = issue_pair(a.src.p[t + 1], sp, j, q);
+            n23 = issue_pair(a.src.p[t + 1], sp, j + 2 * q, q);
+          }
+          const Fe a0 = fe_from_words(c01.w0), a1 = fe_from_words(c01.w1);
+          const Fe a2 = fe_from_words(c23.w0), a3 = fe_from_words(c23.w1);
+          const Fe u0 = fe_addmod(a0, fe_reduce2(fe_mul(alpha, fe_submod(a2, a0))));
+          const Fe u1 = fe_addmod(a1, fe_reduce2(fe_mul(alpha, fe_submod(a3, a1))));
+          store_el(a.dst.p[t], dp, j, u0);
+          store_el(a.dst.p[t], dp, j + q, u1);
+        }
+        Gate::eval(a.dst, dp, j, q, acc);
       } else {
-        u0 = load_el(src.p[t], src_pitch, j);
-        u1 = load_el(src.p[t], src_pitch, j + q);
+        Gate::eval(a.src, a.src_pitch, j, q, acc);
       }
-      lo[t] = u0;
-      dl[t] = fe_submod(u1, u0);
     }
-#pragma unroll
-    for (int x = 0; x < NE; ++x) {
-      if (x > 0) {
-#pragma unroll
-        for (int t = 0; t < K; ++t) lo[t] = fe_add(lo[t], dl[t]);  // e(x) < (x+1) p
-      }
-      const Fe f = Gate::eval(lo);                   // < 11p
-      const Fe g = fe_mul(f, lo[K - 1]);              // < 2p
-      acc[x] = fe_csub(fe_add(acc[x], g), kP2);       // < 2p
-    }
+  } else {
+    transcript_t0(a);
   }
-#pragma unroll
-  for (int x = 0; x < NE; ++x) acc[x] = fe_reduce2(acc[x]);
-  block_reduce_store<NE>(acc, partials + (uint64_t)blockIdx.x * NE * 8);
+  auto red = [&](auto x) __attribute__((always_inline)) { acc[x] = fe_reduce2(acc[x]); };
+  Unroll<0, NE>::run(red);
+  const Fe tot = block_reduce<NE>(acc);
+  if (threadIdx.x < NE) store_words_fe(a.partials + ((uint64_t)blockIdx.x * NE + threadIdx.x) * 8, tot);
+
+  // last block done: the block that increments the counter last finishes the round
+  __shared__ uint32_t last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = (atomicAdd(&a.ctrl->counter, 1u) == gridDim.x - 1) ? 1u : 0u;
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  finish_round<NE>(a, gridDim.x);
 }
 
-// ---- finish a round: sum partials, emit G_i, absorb it, derive alpha_i --------
+// ---- lane-split rounds: 16 lanes per pair -------------------------------------------
+//
+// For rounds with few pairs one thread per pair leaves the GPU idle and makes
+// the round as long as one thread's whole pair (fold of every table plus all
+// d+2 points).  Here a group of 16 lanes shares a pair: lane t folds (or
+// loads) table t, the pair goes through LDS, and lane x evaluates point X = x.
 
+constexpr int kGroup = 16;                     // lanes per pair
+constexpr int kSplitPairs = kBlock / kGroup;   // pairs per block
+
+// Contribution f_M(e(X)) * eq(e(X)) of one pair at point X (< 2p), from the
+// pair's tables u0 = lo[t], u1 = hi[t] (< p).  e(X) = u0 + X (u1 - u0) < (X+1) p.
+template <class Gate, class Get>
+__device__ __forceinline__ Fe point_contrib(Get get, uint32_t X) {
+  constexpr int K = Gate::K + 1;
+  Fe e[K];
+  auto f = [&](auto t) __attribute__((always_inline)) {
+    Fe u0, u1;
+    get(t, u0, u1);
+    e[t] = fe_add(u0, fe_mul_small(fe_submod(u1, u0), X));
+  };
+  Unroll<0, K>::run(f);
+  return fe_mul(Gate::point(e), e[K - 1]);  // f < 11p, eq ext < 11p: 121 <= 128
+}
+
+// Block total (mod p) of one value per lane: lane g of every 16-lane group
+// holds the contribution for point g (< p).  Thread x < NE returns the total.
 template <int NE>
-__global__ __launch_bounds__(kBlock) void k_finish(const uint32_t* __restrict__ partials, uint32_t nparts,
-                                                   Ctrl* ctrl, uint32_t round,
-                                                   uint32_t* __restrict__ evals_out,
-                                                   uint32_t* __restrict__ alpha_out) {
-  Fe s[NE];
-#pragma unroll
-  for (int x = 0; x < NE; ++x) s[x] = fe_zero();
-  for (uint32_t b = threadIdx.x; b < nparts; b += blockDim.x) {
-#pragma unroll
-    for (int x = 0; x < NE; ++x) s[x] = fe_addmod(s[x], load_words_fe(partials + ((uint64_t)b * NE + x) * 8));
-  }
-  __shared__ uint32_t tot[NE * 8];
-  block_reduce_store<NE>(s, tot);
+__device__ __forceinline__ Fe group_reduce(Fe c) {
+  __shared__ uint32_t red[kBlock / 64][kGroup][NL];
+  c = fe_addmod(c, shfl_xor_fe(c, 16));
+  c = fe_addmod(c, shfl_xor_fe(c, 32));
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane < kGroup) lds_put(red[wave][lane], c);
   __syncthreads();
-  if (threadIdx.x == 0) {
-    // message = T_{i-1} || enc(G_i(0)) || .. || enc(G_i(d+1)), canonical little-endian
-    uint32_t msg[8 + NE * 8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) msg[k] = ctrl->ts[k];
-#pragma unroll
-    for (int x = 0; x < NE; ++x) {
-      const Fe c = fe_from_mont(load_words_fe(tot + x * 8));
-      store_words_fe(msg + 8 + x * 8, c);
-#pragma unroll
-      for (int k = 0; k < 8; ++k) evals_out[x * 8 + k] = msg[8 + x * 8 + k];
-    }
-    uint32_t dg[8];
-    sha256(msg, 32u * (1u + NE), dg);
-    // alpha_i = digest (little-endian 256-bit integer) mod p; digest < 2^256 < 6p
-    Fe a = fe_from_words(dg);
-    a = fe_csub(fe_csub(fe_csub(a, kP4), kP2), kP);
-#pragma unroll
-    for (int k = 0; k < 8; ++k) ctrl->ts[k] = dg[k];
-    store_words_fe(alpha_out, a);
-    store_words_fe(ctrl->alpha_m[round - 1], fe_to_mont(a));
-    ctrl->round_done = round;
-  }
-}
-
-// ---- setup: r to Montgomery, transcript T_0, eq half tables --------------------
-
-// One block.  T_0 = SHA-256("ZCv1" || u32 mu || u32 gate || u32 m || enc(r_1..r_mu)).
-__global__ __launch_bounds__(64) void k_setup(const uint32_t* __restrict__ r, uint32_t mu, uint32_t gate,
-                                              uint32_t m, Ctrl* ctrl) {
-  __shared__ uint32_t msg[4 + kMuMax * 8];
-  if (threadIdx.x == 0) {
-    msg[0] = 0x3176435au;  // bytes 'Z' 'C' 'v' '1'
-    msg[1] = mu;
-    msg[2] = gate;
-    msg[3] = m;
-    ctrl->err = 0;
-    ctrl->round_done = 0;
-    ctrl->fold_done = 0;
-  }
-  __syncthreads();  // the reset above must precede any error flagged below
-  for (uint32_t i = threadIdx.x; i < mu; i += blockDim.x) {
-    uint32_t w[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      w[k] = r[i * 8 + k];
-      msg[4 + i * 8 + k] = w[k];
-    }
-    if (!words_lt_p(w)) set_error(ctrl, -4);
-    store_words_fe(ctrl->r_m[i], fe_to_mont(fe_from_words(w)));
+  Fe s = fe_zero();
+  if (threadIdx.x < NE) {
+    s = lds_fe(red[0][threadIdx.x]);
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) s = fe_addmod(s, lds_fe(red[w][threadIdx.x]));
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t dg[8];
-    sha256(msg, 16u + 32u * mu, dg);
-#pragma unroll
-    for (int k = 0; k < 8; ++k) ctrl->ts[k] = dg[k];
-  }
+  return s;
 }
 
-// Half tables of eq: hi[y] over x_1..x_hb (y's MSB = x_1), lo[z] over
-// x_{hb+1}..x_mu.  Entry = product of (x ? r_i : 1 - r_i).  Stored as 8 words.
-__global__ __launch_bounds__(kBlock) void k_eq_half(const Ctrl* __restrict__ ctrl, uint32_t mu, uint32_t hb,
-                                                    uint32_t* __restrict__ hi, uint32_t* __restrict__ lo) {
-  const uint32_t lb = mu - hb;
-  const uint32_t nhi = 1u << hb, nlo = 1u << lb;
-  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nhi + nlo) return;
-  const bool is_hi = e < nhi;
-  const uint32_t y = is_hi ? e : e - nhi;
-  const uint32_t nb = is_hi ? hb : lb;
-  const uint32_t first = is_hi ? 0 : hb;
-  const Fe one = fe_const(kOne);
-  Fe acc = one;
-  for (uint32_t k = 0; k < nb; ++k) {
-    const Fe ri = load_words_fe(ctrl->r_m[first + k]);
-    const uint32_t bit = (y >> (nb - 1 - k)) & 1u;
-    const Fe fac = bit ? ri : fe_submod(one, ri);
-    acc = fe_reduce2(fe_mul(acc, fac));
+// The last rounds of a proof inside one block, with the tables in LDS.  On
+// entry round a.round has been finished (alpha_round derived) and the tables
+// at a.dst hold 2q live entries, q = a.q <= 2 kTailQ.  Runs rounds
+// a.round+1 .. mu (fold with the previous challenge, evaluate, finalize)
+// and the final fold, whose values are the openings.
+template <class Gate>
+__device__ __forceinline__ void run_tail(const RoundArgs& a) {
+  constexpr int K = Gate::K + 1;
+  constexpr int NE = Gate::NE;
+  extern __shared__ uint32_t tail_lds[];  // [K][4 kTailQ][NL]
+  constexpr uint32_t CAP = 4 * kTailQ;
+  auto T = [&](int t, uint32_t e) -> uint32_t* { return tail_lds + ((uint32_t)t * CAP + e) * NL; };
+  uint32_t L = 2 * (uint32_t)a.q;
+  for (uint32_t idx = threadIdx.x; idx < K * L; idx += blockDim.x) {
+    const uint32_t t = idx / L, e = idx % L;
+    lds_put(T(t, e), load_el(a.dst.p[t], a.dst_pitch, e));
   }
-  store_words_fe((is_hi ? hi + (uint64_t)y * 8 : lo + (uint64_t)y * 8), acc);
+  __syncthreads();
+  const uint32_t g = threadIdx.x % kGroup, pl = threadIdx.x / kGroup;
+  for (uint32_t r = a.round + 1; r <= a.mu + 1; ++r) {
+    // fold with alpha_{r-1}: L -> L/2 entries
+    const Fe alpha = load_words_fe(a.ctrl->alpha_m[r - 2]);
+    const uint32_t h = L / 2;
+    for (uint32_t idx = threadIdx.x; idx < K * h; idx += blockDim.x) {
+      const uint32_t t = idx / h, e = idx % h;
+      const Fe u0 = lds_fe(T(t, e)), u1 = lds_fe(T(t, e + h));
+      const Fe u = fe_addmod(u0, fe_reduce2(fe_mul(alpha, fe_submod(u1, u0))));
+      lds_put(T(t, e), u);
+    }
+    __syncthreads();
+    L = h;
+    if (r > a.mu) break;  // the final fold: entry 0 of each table is its opening
+    const uint32_t q = L / 2;
+    Fe c = fe_zero();
+    for (uint32_t base = 0; base < q; base += kSplitPairs) {
+      const uint32_t e = base + pl;
+      if (e < q && g < (uint32_t)NE) {
+        auto get = [&](int t, Fe& u0, Fe& u1) __attribute__((always_inline)) {
+          u0 = lds_fe(T(t, e));
+          u1 = lds_fe(T(t, e + q));
+        };
+        c = fe_addmod(c, fe_reduce2(point_contrib<Gate>(get, g)));
+      }
+    }
+    const Fe tot = group_reduce<NE>(c);
+    finalize_round<NE>(a.ctrl, r, tot, a.evals_out + (uint64_t)(r - a.round) * NE * 8,
+                       a.alpha_out + (uint64_t)(r - a.round) * 8);
+  }
+  if (threadIdx.x < K) store_words_fe(a.openings + threadIdx.x * 8, fe_from_mont(lds_fe(T(threadIdx.x, 0))));
 }
 
-// eq[b] = hi[b >> lb] * lo[b & (2^lb - 1)], limb-planar with pitch n.
-__global__ __launch_bounds__(kBlock) void k_build_eq(const uint32_t* __restrict__ hi, const uint32_t* __restrict__ lo,
-                                                     uint32_t lb, uint64_t n, uint32_t* __restrict__ eq) {
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < n; b += stride) {
-    const Fe h = load_words_fe(hi + (b >> lb) * 8);
-    const Fe l = load_words_fe(lo + (b & ((1ull << lb) - 1)) * 8);
-    store_el(eq, n, b, fe_reduce2(fe_mul(h, l)));
+// Round with 16 lanes per pair.  Grid: q / 16 blocks (+1 with T_0).  With
+// a.tail, the last block to finish runs the rest of the proof (run_tail).
+template <class Gate, bool FOLD>
+__global__ __launch_bounds__(kBlock) void k_round_split(RoundArgs a) {
+  constexpr int K = Gate::K + 1;
+  constexpr int NE = Gate::NE;
+  __shared__ uint32_t sh[kSplitPairs][K][2][NL];
+  const uint32_t work_blocks = gridDim.x - (a.with_t0 ? 1u : 0u);
+  const uint32_t g = threadIdx.x % kGroup, pl = threadIdx.x / kGroup;
+  Fe c = fe_zero();
+  if (blockIdx.x < work_blocks) {
+    const uint32_t q = (uint32_t)a.q;
+    const uint64_t stride = (uint64_t)work_blocks * kSplitPairs;
+    for (uint64_t base = (uint64_t)blockIdx.x * kSplitPairs; base < q; base += stride) {
+      const uint32_t j = (uint32_t)(base + pl);
+      if (j < q && g < (uint32_t)K) {
+        // table g's pointers, selected without indexing the argument array per lane
+        const uint32_t* src = a.src.p[0];
+        uint32_t* dst = a.dst.p[0];
+        auto sel = [&](auto t) __attribute__((always_inline)) {
+          if (g == (uint32_t)t) {
+            src = a.src.p[t];
+            dst = a.dst.p[t];
+          }
+        };
+        Unroll<1, K>::run(sel);
+        Fe u0, u1;
+        if (FOLD) {
+          const Fe alpha = load_words_fe(a.ctrl->alpha_m[a.round - 2]);
+          const uint64_t sp = a.src_pitch;
+          const Fe a0 = load_el(src, sp, j), a2 = load_el(src, sp, j + 2 * q);
+          const Fe a1 = load_el(src, sp, j + q), a3 = load_el(src, sp, j + 3 * q);
+          u0 = fe_addmod(a0, fe_reduce2(fe_mul(alpha, fe_submod(a2, a0))));
+          u1 = fe_addmod(a1, fe_reduce2(fe_mul(alpha, fe_submod(a3, a1))));
+          store_el(dst, a.dst_pitch, j, u0);
+          store_el(dst, a.dst_pitch, j + q, u1);
+        } else {
+          u0 = load_el(src, a.src_pitch, j);
+          u1 = load_el(src, a.src_pitch, j + q);
+        }
+        lds_put(sh[pl][g][0], u0);
+        lds_put(sh[pl][g][1], u1);
+      }
+      __syncthreads();
+      if (j < q && g < (uint32_t)NE) {
+        auto get = [&](int t, Fe& u0, Fe& u1) __attribute__((always_inline)) {
+          u0 = lds_fe(sh[pl][t][0]);
+          u1 = lds_fe(sh[pl][t][1]);
+        };
+        c = fe_addmod(c, fe_reduce2(point_contrib<Gate>(get, g)));
+      }
+      __syncthreads();
+    }
+  } else {
+    transcript_t0(a);
   }
-}
+  const Fe tot = group_reduce<NE>(c);
+  if (threadIdx.x < NE) store_words_fe(a.partials + ((uint64_t)blockIdx.x * NE + threadIdx.x) * 8, tot);
 
-// ---- folds -----------------------------------------------------------------------
-
-// In-place fold of every table with alpha_round: t[j] <- t[j] + alpha (t[j+h] - t[j]),
-// j < h.  blockIdx.y selects the table.  With check_state the fold runs only
-// when round `round` has been evaluated and not yet folded.
-__global__ __launch_bounds__(kBlock) void k_fold(TabPtrs tabs, uint32_t ntab, uint64_t pitch, uint64_t h,
-                                                 Ctrl* ctrl, uint32_t round) {
-  if (ctrl->round_done != round || ctrl->fold_done + 1 != round) return;
-  const uint32_t t = blockIdx.y;
-  if (t >= ntab) return;
-  const Fe alpha = load_words_fe(ctrl->alpha_m[round - 1]);
-  uint32_t* base = tabs.p[t];
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < h; j += stride) {
-    const Fe a0 = load_el(base, pitch, j);
-    const Fe a1 = load_el(base, pitch, j + h);
-    store_el(base, pitch, j, fe_addmod(a0, fe_reduce2(fe_mul(alpha, fe_submod(a1, a0)))));
-  }
-}
-
-// Marks round `round` folded (launched after k_fold on the same stream).
-__global__ void k_mark_folded(Ctrl* ctrl, uint32_t round) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    if (ctrl->round_done == round && ctrl->fold_done + 1 == round)
-      ctrl->fold_done = round;
-    else
-      set_error(ctrl, -5);
-  }
-}
-
-// Checks that round `round` may be evaluated now (stepping API).
-__global__ void k_check_round(Ctrl* ctrl, uint32_t round) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    if (!(ctrl->round_done == round - 1 && ctrl->fold_done == round - 1)) set_error(ctrl, -5);
-  }
-}
-
-// Last fold of a whole proof: every table holds 2 entries; write the folded
-// value of each, canonical, to openings[t].
-__global__ void k_openings(TabPtrs tabs, uint32_t ntab, uint64_t pitch, const Ctrl* __restrict__ ctrl,
-                           uint32_t mu, uint32_t* __restrict__ openings) {
-  const uint32_t t = threadIdx.x;
-  if (t >= ntab) return;
-  const Fe alpha = load_words_fe(ctrl->alpha_m[mu - 1]);
-  const Fe a0 = load_el(tabs.p[t], pitch, 0);
-  const Fe a1 = load_el(tabs.p[t], pitch, 1);
-  const Fe u = fe_addmod(a0, fe_reduce2(fe_mul(alpha, fe_submod(a1, a0))));
-  store_words_fe(openings + t * 8, fe_from_mont(u));
-}
-
-// ---- layout conversion ----------------------------------------------------------
-
-// canonical u32[n][8] -> Montgomery limb-planar u32[8][pitch]; flags inputs >= p.
-__global__ __launch_bounds__(kBlock) void k_pack(const uint32_t* __restrict__ canon, uint32_t* __restrict__ planar,
-                                                 uint64_t n, uint64_t pitch, Ctrl* ctrl) {
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride) {
-    const uint4* src = reinterpret_cast<const uint4*>(canon + j * 8);
-    const uint4 x0 = src[0], x1 = src[1];
-    uint32_t w[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
-    if (!words_lt_p(w)) set_error(ctrl, -4);
-    store_el(planar, pitch, j, fe_to_mont(fe_from_words(w)));
-  }
-}
-
-// Montgomery limb-planar (pitch) -> canonical u32[n][8].
-__global__ __launch_bounds__(kBlock) void k_unpack(const uint32_t* __restrict__ planar, uint64_t pitch,
-                                                   uint32_t* __restrict__ canon, uint64_t n) {
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride) {
-    uint32_t w[8];
-    fe_to_words(fe_from_mont(load_el(planar, pitch, j)), w);
-    uint4* dst = reinterpret_cast<uint4*>(canon + j * 8);
-    dst[0] = make_uint4(w[0], w[1], w[2], w[3]);
-    dst[1] = make_uint4(w[4], w[5], w[6], w[7]);
-  }
+  __shared__ uint32_t last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = (atomicAdd(&a.ctrl->counter, 1u) == gridDim.x - 1) ? 1u : 0u;
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  finish_round<NE>(a, gridDim.x);
+  if (a.tail) run_tail<Gate>(a);
 }
 
 }  // namespace zc

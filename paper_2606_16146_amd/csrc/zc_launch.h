@@ -1,0 +1,48 @@
+// Round-kernel launch helpers shared by the host API and the per-gate
+// instantiation units (zc_inst.hip is compiled once per gate so that the
+// large unrolled kernels build in parallel).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "zc_device.h"
+
+namespace zc {
+
+struct RoundArgs;
+
+// Rounds with more pairs than this run one thread per pair (k_round); the
+// others run 16 lanes per pair (k_round_split).
+constexpr uint64_t kSplitQ = 16384;
+constexpr int kTailQ = 32;  // the tail runs rounds with at most this many pairs
+
+enum RoundKind { kPerPair = 0, kSplit = 1, kSplitTail = 2, kInTail = 3 };
+
+// Which kernel evaluates round i of a whole proof (zc_prove).
+inline RoundKind prove_round_kind(uint32_t mu, uint32_t i) {
+  const uint64_t q = 1ull << (mu - i);
+  const uint64_t first_tail_q = 2 * (uint64_t)kTailQ;
+  if (q > kSplitQ) return kPerPair;
+  if (q > first_tail_q) return kSplit;
+  // the first round with q <= 2 kTailQ launches the tail; later rounds run inside it
+  const uint64_t prev_q = q * 2;
+  return (i == 1 || prev_q > first_tail_q) ? kSplitTail : kInTail;
+}
+
+// One launcher per gate instantiation (defined in zc_inst.hip).
+int launch_round_vanilla(bool fold, RoundKind kind, const RoundArgs& a, hipStream_t st);
+#define ZC_DECL_PROD(M) int launch_round_prod##M(bool fold, RoundKind kind, const RoundArgs& a, hipStream_t st);
+ZC_DECL_PROD(1)
+ZC_DECL_PROD(2)
+ZC_DECL_PROD(3)
+ZC_DECL_PROD(4)
+ZC_DECL_PROD(5)
+ZC_DECL_PROD(6)
+ZC_DECL_PROD(7)
+ZC_DECL_PROD(8)
+#undef ZC_DECL_PROD
+
+}  // namespace zc

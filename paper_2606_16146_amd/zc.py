@@ -14,7 +14,8 @@ import re
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libzc.so")
+# ZC_LIB may name another build of the library (e.g. to compare two builds).
+LIB_PATH = os.environ.get("ZC_LIB") or os.path.join(HERE, "libzc.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
 ZC_OK, ZC_EINVAL, ZC_EUNSUPPORTED, ZC_EHIP, ZC_ERANGE, ZC_ESTATE = 0, -1, -2, -3, -4, -5
@@ -46,6 +47,9 @@ _SIGS = {
     "zc_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "zc_test_field": (ctypes.c_int, [ctypes.c_int, _VP, _VP, _VP, ctypes.c_uint64, _VP]),
     "zc_test_sha256": (ctypes.c_int, [_VP, ctypes.c_uint32, _VP, _VP]),
+    "zc_prove_round_kernel": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32]),
+    "zc_prove_profiled": (ctypes.c_int, [ctypes.POINTER(Shape), _VP, _VP, _VP, _VP, _VP, _VP, _VP,
+                                         _VP]),
 }
 
 
@@ -169,6 +173,52 @@ def fold(s: Shape, tables, ws: torch.Tensor, i: int, stream=None):
 
 def read_error(ws: torch.Tensor, stream=None) -> int:
     return lib().zc_read_error(_ptr(ws), _stream(stream))
+
+
+def prove_profiled(s: Shape, tables, r: torch.Tensor, ws: torch.Tensor, events: "HipEvents",
+                   outputs=None, first_event: int = 0, stream=None):
+    """zc_prove with events[first_event .. first_event + 2*mu) around the round kernels."""
+    evals, alphas, openings = outputs if outputs is not None else new_outputs(s, r.device)
+    if first_event + 2 * s.mu > events.n:
+        raise ValueError("not enough events")
+    arr = _table_array(tables)
+    base = ctypes.addressof(events.arr) + first_event * ctypes.sizeof(ctypes.c_void_p)
+    rc = lib().zc_prove_profiled(ctypes.byref(s), arr, _ptr(r), _ptr(ws), _ptr(evals), _ptr(alphas),
+                                 _ptr(openings), ctypes.c_void_p(base), _stream(stream))
+    _check(rc, "zc_prove_profiled")
+    return evals, alphas, openings
+
+
+class HipEvents:
+    """A host array of hipEvent_t created through the HIP runtime (for zc_prove_profiled)."""
+
+    def __init__(self, n: int):
+        self.hip = ctypes.CDLL("libamdhip64.so")
+        self.hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), _VP, _VP]
+        self.hip.hipEventSynchronize.argtypes = [_VP]
+        self.hip.hipEventDestroy.argtypes = [_VP]
+        self.n = n
+        self.arr = (ctypes.c_void_p * n)()
+        base = ctypes.addressof(self.arr)
+        for i in range(n):
+            rc = self.hip.hipEventCreate(ctypes.c_void_p(base + i * ctypes.sizeof(ctypes.c_void_p)))
+            if rc != 0:
+                raise ZcError(ZC_EHIP, "hipEventCreate")
+
+    def elapsed_ms(self, a: int, b: int) -> float:
+        self.hip.hipEventSynchronize(self.arr[b])
+        ms = ctypes.c_float()
+        rc = self.hip.hipEventElapsedTime(ctypes.byref(ms), self.arr[a], self.arr[b])
+        if rc != 0:
+            raise ZcError(ZC_EHIP, "hipEventElapsedTime")
+        return ms.value
+
+    def __del__(self):
+        try:
+            for i in range(self.n):
+                self.hip.hipEventDestroy(self.arr[i])
+        except Exception:
+            pass
 
 
 def test_field(op: int, a: torch.Tensor, b: torch.Tensor, stream=None) -> torch.Tensor:
