@@ -41,19 +41,21 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def gate_products(gate: int, m: int) -> int:
-    """Field products per evaluation point: gate products + 1 for eq."""
-    return (4 if gate == 0 else m) + 1
-
-
 def round_work(mu, gate, m, k, d, i):
-    """Algorithmic (bytes, field products) of the round-i kernel launch."""
-    K = k + 1
+    """Algorithmic (bytes, field products) of the round-i kernel launch.
+
+    Per pair: E_i[j] (one product while i < mu - floor(mu/2)), then at each of
+    the d+1 points the gate's products (vanilla 4, product gate m) and one
+    product with E; rounds >= 2 first fold the k witness tables (two products
+    per table).  Bytes: round 1 reads 2 entries per table, later rounds read 4
+    and write 2 (32 bytes per entry); eq_r is factored and never streamed.
+    """
     q = 1 << (mu - i)
-    evalp = (d + 2) * gate_products(gate, m)
+    g = 4 if gate == 0 else m
+    per_pair = (d + 1) * (g + 1) + (1 if i < mu - mu // 2 else 0)
     if i == 1:
-        return q * 2 * K * 32, q * evalp
-    return q * 6 * K * 32, q * (2 * K + evalp)
+        return q * 2 * k * 32, q * per_pair
+    return q * 6 * k * 32, q * (2 * k + per_pair)
 
 
 def run_workload(name, steps, warmup, cpu_baseline):
@@ -140,7 +142,7 @@ def run_workload(name, steps, warmup, cpu_baseline):
         "split_and_tail_avg_us": round(split_t / steps * 1e6, 2),
         "round_kernels_share": round((fused_t + first_t + split_t) / elapsed, 4),
         "config": {"workload": name, "mu": mu, "gate": "vanilla" if gate == 0 else f"prod{m}",
-                   "degree": d, "tables": k + 1, "field": "BN254 Fr", "seed": cfg["seed"]},
+                   "degree": d, "tables": k, "field": "BN254 Fr", "seed": cfg["seed"]},
     }
     log(f"[bench] {name}: {res['ms_per_step']:.3f} ms/proof, {res['value'] / 1e6:.1f} M points/s")
 

@@ -75,8 +75,9 @@ int zc_table_count(const zc_shape* shape);
 int zc_degree(const zc_shape* shape);
 
 /* Bytes of device workspace a proof of this shape needs (0 for an invalid shape):
-   control block, eq table (2^mu elements), folded copies of all k+1 tables
-   (2^(mu-1) elements each), per-block partial sums.  256-byte alignment required. */
+   control block, the factored eq_r tables (about 4 * 2^(mu/2) elements),
+   folded copies of the k witness tables (2^(mu-1) elements each), per-block
+   partial sums.  256-byte alignment required. */
 size_t zc_workspace_bytes(const zc_shape* shape);
 
 /* Convert n canonical elements (canon: uint32[n][8], 16-byte aligned) into the
@@ -107,14 +108,16 @@ int zc_prove(const zc_shape* shape, const uint32_t* const* tables, const uint32_
    i-1 times (2^(mu-i+1) live entries, pitch 2^mu), writes
    round_evals[(i-1)(d+2)..] and challenges[i-1] (same layout as zc_prove),
    and keeps alpha_i in ws.  zc_round(1) also checks r, starts the
-   transcript and builds the eq table in ws.  Must follow zc_fold(i-1). */
+   transcript and builds the factored eq_r tables in ws.  Must follow
+   zc_fold(i-1). */
 int zc_round(const zc_shape* shape, const uint32_t* const* tables, const uint32_t* r, void* ws, uint32_t i,
              uint32_t* round_evals, uint32_t* challenges, hipStream_t stream);
 
-/* Folds the k caller tables (IN PLACE, pitch 2^mu) and ws's eq table with
-   alpha_i: t[j] <- t[j] + alpha_i (t[j + h] - t[j]) for j < h = 2^(mu-i).
-   Must follow zc_round(i).  After zc_fold(mu) entry 0 of each table is its
-   opening (read it with zc_unpack, pitch 2^mu). */
+/* Folds the k caller tables IN PLACE (pitch 2^mu) with alpha_i:
+   t[j] <- t[j] + alpha_i (t[j + h] - t[j]) for j < h = 2^(mu-i).  eq_r is
+   never materialized (the library keeps it factored), so only the witness
+   tables are folded.  Must follow zc_round(i).  After zc_fold(mu) entry 0 of
+   each table is its opening (read it with zc_unpack, pitch 2^mu). */
 int zc_fold(const zc_shape* shape, uint32_t* const* tables, void* ws, uint32_t i, hipStream_t stream);
 
 /* Synchronizes `stream` and returns the first device-detected error stored in

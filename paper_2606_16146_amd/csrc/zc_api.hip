@@ -18,8 +18,8 @@ namespace {
 struct Layout {
   uint32_t k;       // witness tables
   uint32_t d;       // gate degree
-  uint32_t hb, lb;  // bit split of the eq half tables
-  size_t hi, lo, partials, eq, scratch, total;
+  uint32_t ml, mh;  // split of the variables for the factored eq tables
+  size_t eqrows, partials, scratch, total;
 };
 
 constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -43,20 +43,16 @@ int make_layout(const zc_shape* s, Layout* L) {
   if (s->mu < 1 || s->mu > (uint32_t)kMuMax) return ZC_EINVAL;
   L->k = (uint32_t)k;
   L->d = (uint32_t)shape_d(s);
-  L->lb = s->mu / 2;
-  L->hb = s->mu - L->lb;
+  L->ml = s->mu / 2;
+  L->mh = s->mu - L->ml;
   const size_t n = (size_t)1 << s->mu;
   size_t off = kCtrlBytes;
-  L->hi = off;
-  off = align256(off + ((size_t)32 << L->hb));
-  L->lo = off;
-  off = align256(off + ((size_t)32 << L->lb));
+  L->eqrows = off;  // LO (2^ml rows) + HI heap (2^mh) + SUF heap (2^(ml+1)), 32 bytes each
+  off = align256(off + (((size_t)1 << L->ml) + ((size_t)1 << L->mh) + ((size_t)2 << L->ml)) * 32);
   L->partials = off;
   off = align256(off + (size_t)kMaxBlocks * kMaxEvals * 32);
-  L->eq = off;
-  off = align256(off + n * 32);
-  L->scratch = off;
-  off = align256(off + (size_t)(k + 1) * (n / 2 > 0 ? n / 2 : 1) * 32);
+  L->scratch = off;  // folded copies of the k witness tables, 2^(mu-1) entries each
+  off = align256(off + (size_t)k * (n / 2 > 0 ? n / 2 : 1) * 32);
   L->total = off;
   return ZC_OK;
 }
@@ -101,23 +97,25 @@ RoundArgs round_args(const zc_shape* s, const Layout& L, void* ws, const uint32_
   a.ctrl = ctrl_of(ws);
   a.evals_out = round_evals + (uint64_t)(i - 1) * (L.d + 2) * 8;
   a.alpha_out = challenges + (uint64_t)(i - 1) * 8;
+  const uint32_t* rows = reinterpret_cast<const uint32_t*>(bytes(ws) + L.eqrows);
+  a.eq.lo = rows;
+  a.eq.hi = rows + ((size_t)1 << L.ml) * 8;
+  a.eq.suf = rows + (((size_t)1 << L.ml) + ((size_t)1 << L.mh)) * 8;
+  a.eq.ml = L.ml;
+  a.eq.mh = L.mh;
+  a.eq.mu = s->mu;
   return a;
 }
 
-// r -> Montgomery, eq half tables, eq table (pitch 2^mu) in ws.
+// r -> canonical and Montgomery copies, C_1 and coef_1, the factored eq tables.
 int launch_setup(const zc_shape* s, const Layout& L, const uint32_t* r, void* ws, hipStream_t st) {
   Ctrl* ctrl = ctrl_of(ws);
-  hipLaunchKernelGGL(k_setup, dim3(1), dim3(64), 0, st, r, s->mu, ctrl);
+  hipLaunchKernelGGL(k_setup, dim3(1), dim3(64), 0, st, r, s->mu, L.d + 2, ctrl);
   if (launch_ok() != ZC_OK) return ZC_EHIP;
-  uint32_t* hi = reinterpret_cast<uint32_t*>(bytes(ws) + L.hi);
-  uint32_t* lo = reinterpret_cast<uint32_t*>(bytes(ws) + L.lo);
-  const uint32_t nhalf = (1u << L.hb) + (1u << L.lb);
-  hipLaunchKernelGGL(k_eq_half, dim3((nhalf + kBlock - 1) / kBlock), dim3(kBlock), 0, st, ctrl, s->mu, L.hb, hi,
-                     lo);
-  if (launch_ok() != ZC_OK) return ZC_EHIP;
-  const uint64_t n = 1ull << s->mu;
-  uint32_t* eq = reinterpret_cast<uint32_t*>(bytes(ws) + L.eq);
-  hipLaunchKernelGGL(k_build_eq, dim3(grid_for(n, 8192)), dim3(kBlock), 0, st, hi, lo, L.lb, n, eq);
+  const uint32_t nrows = (1u << L.ml) + (1u << L.mh) + (2u << L.ml);
+  uint32_t* rows = reinterpret_cast<uint32_t*>(bytes(ws) + L.eqrows);
+  hipLaunchKernelGGL(k_eq_tables, dim3((nrows + kBlock - 1) / kBlock), dim3(kBlock), 0, st, ctrl, s->mu, L.ml,
+                     rows);
   return launch_ok();
 }
 
@@ -140,17 +138,16 @@ int prove_impl(const zc_shape* shape, const uint32_t* const* tables, const uint3
   if (rc != ZC_OK) return rc;
   if ((rc = check_tables(L, tables)) != ZC_OK) return rc;
   if (!r || !ws || !round_evals || !challenges || !openings || !aligned(ws, 256)) return ZC_EINVAL;
-  const uint32_t mu = shape->mu, K = L.k + 1;
+  const uint32_t mu = shape->mu;
   const uint64_t n = 1ull << mu;
-  Ctrl* ctrl = ctrl_of(ws);
-  uint32_t* eq = reinterpret_cast<uint32_t*>(bytes(ws) + L.eq);
   uint32_t* scratch = reinterpret_cast<uint32_t*>(bytes(ws) + L.scratch);
   const uint64_t half = n / 2;
 
   TabPtrs orig{}, fold{};
-  for (uint32_t t = 0; t < L.k; ++t) orig.p[t] = const_cast<uint32_t*>(tables[t]);
-  orig.p[L.k] = eq;
-  for (uint32_t t = 0; t < K; ++t) fold.p[t] = scratch + (uint64_t)t * half * 8;
+  for (uint32_t t = 0; t < L.k; ++t) {
+    orig.p[t] = const_cast<uint32_t*>(tables[t]);
+    fold.p[t] = scratch + (uint64_t)t * half * 8;
+  }
 
   if ((rc = launch_setup(shape, L, r, ws, stream)) != ZC_OK) return rc;
   for (uint32_t i = 1; i <= mu; ++i) {
@@ -227,12 +224,10 @@ int zc_round(const zc_shape* shape, const uint32_t* const* tables, const uint32_
   if ((rc = check_tables(L, tables)) != ZC_OK) return rc;
   if (!ws || !round_evals || !challenges || !aligned(ws, 256) || i < 1 || i > shape->mu) return ZC_EINVAL;
   if (i == 1 && !r) return ZC_EINVAL;
-  const uint32_t mu = shape->mu;
-  const uint64_t n = 1ull << mu;
+  const uint64_t n = 1ull << shape->mu;
   Ctrl* ctrl = ctrl_of(ws);
   TabPtrs cur{};
   for (uint32_t t = 0; t < L.k; ++t) cur.p[t] = const_cast<uint32_t*>(tables[t]);
-  cur.p[L.k] = reinterpret_cast<uint32_t*>(bytes(ws) + L.eq);
   if (i == 1) {
     if ((rc = launch_setup(shape, L, r, ws, stream)) != ZC_OK) return rc;
   } else {
@@ -251,13 +246,12 @@ int zc_fold(const zc_shape* shape, uint32_t* const* tables, void* ws, uint32_t i
   if (rc != ZC_OK) return rc;
   if ((rc = check_tables(L, tables)) != ZC_OK) return rc;
   if (!ws || !aligned(ws, 256) || i < 1 || i > shape->mu) return ZC_EINVAL;
-  const uint32_t mu = shape->mu, K = L.k + 1;
+  const uint32_t mu = shape->mu;
   const uint64_t n = 1ull << mu, h = 1ull << (mu - i);
   TabPtrs cur{};
   for (uint32_t t = 0; t < L.k; ++t) cur.p[t] = tables[t];
-  cur.p[L.k] = reinterpret_cast<uint32_t*>(bytes(ws) + L.eq);
   Ctrl* ctrl = ctrl_of(ws);
-  hipLaunchKernelGGL(k_fold, dim3(grid_for(h, 1024), K), dim3(kBlock), 0, stream, cur, K, n, h, ctrl, i);
+  hipLaunchKernelGGL(k_fold, dim3(grid_for(h, 1024), L.k), dim3(kBlock), 0, stream, cur, L.k, n, h, ctrl, i);
   if ((rc = launch_ok()) != ZC_OK) return rc;
   hipLaunchKernelGGL(k_mark_folded, dim3(1), dim3(1), 0, stream, ctrl, i);
   return launch_ok();

@@ -10,22 +10,30 @@
 
 namespace zc {
 
-constexpr int kMaxTables = 12;  // witness tables + eq
+constexpr int kMaxTables = 12;  // witness tables of a gate
 constexpr int kMaxEvals = 12;   // d + 2 for d <= 10
 constexpr int kMuMax = 30;
 constexpr int kBlock = 256;
 constexpr int kMaxBlocks = 2048;
 
 // Control block at the start of the workspace.
+//
+// eq_r is never materialized: it factors as
+//   eq_r(a_1..a_{i-1}, X, x_{>i}) = C_i * eq1(X, r_i) * E_i[x_{>i}],
+// C_i = prod_{k<i} eq1(alpha_k, r_k), E_i = eq over r_{i+1..mu}, so the
+// round kernels accumulate H_i(X) = sum_j E_i[j] f(ext_j(X)) and the round's
+// finisher multiplies by coef_i[X] = C_i * eq1(X, r_i).
 struct Ctrl {
   uint32_t err;         // first device-detected error (negative status), 0 if none
   uint32_t round_done;  // last round whose challenge has been derived
   uint32_t fold_done;   // last round whose fold has been applied
   uint32_t counter;     // blocks of the running round kernel that have finished
-  uint32_t ts[8];                 // transcript digest T_i (little-endian bytes)
-  uint32_t alpha_m[kMuMax][8];    // alpha_i, Montgomery form, < p
-  uint32_t r_m[kMuMax][8];        // r_i, Montgomery form, < p
-  uint32_t pad1[8];
+  uint32_t ts[8];                   // transcript digest T_i (little-endian bytes)
+  uint32_t alpha_m[kMuMax][8];      // alpha_i, Montgomery form, < p
+  uint32_t r_m[kMuMax][8];          // r_i, Montgomery form, < p
+  uint32_t r_c[kMuMax][8];          // r_i, canonical
+  uint32_t c_m[8];                  // C_{round_done+1}, Montgomery form
+  uint32_t coef[kMaxEvals][8];      // C_i * eq1(x, r_i), canonical, i = round_done + 1
 };
 
 constexpr uint32_t kCtrlBytes = 4096;

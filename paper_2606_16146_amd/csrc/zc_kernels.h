@@ -1,21 +1,30 @@
 // Kernels of the ZeroCheck SumCheck prover (gfx950).
 //
 // What is computed follows the multilinear ZeroCheck of Fig. 2 (right) of
-// "When Proofs Meet Hardware": build eq_r once (Sec. 3.3), then for each
-// round i evaluate G_i(X) = sum over the remaining hypercube of
-// f_M(ext(X)) * eq(ext(X)) at X = 0..d+1, derive alpha_i from the
-// transcript, and fold every table (eq included) with alpha_i (Sec. 4.1:
-// update, extend, multiply, accumulate).  Variable x_1 is the most
-// significant index bit, so round i pairs entries j and j + 2^(mu-i) and the
-// fold of a table can be written in place: the thread that owns pair j reads
-// and writes only slots j, j+q, j+2q, j+3q.
+// "When Proofs Meet Hardware": for each round i evaluate
+// G_i(X) = sum over the remaining hypercube of f_M(ext(X)) * eq_r(ext(X)) at
+// X = 0..d+1, derive alpha_i from the transcript, and fold every table with
+// alpha_i (Sec. 4.1: update, extend, multiply, accumulate).  Variable x_1 is
+// the most significant index bit, so round i pairs entries j and
+// j + 2^(mu-i), and the fold of a table can be written in place: the thread
+// that owns pair j reads and writes only slots j, j+q, j+2q, j+3q.
+//
+// eq_r is used in factored form (Sec. 3.3 defines it as a product of one
+// factor per variable): G_i(X) = C_i eq1(X, r_i) H_i(X) with
+// H_i(X) = sum_j E_i[j] f_M(ext_j(X)), E_i the eq table of the variables
+// after x_i and C_i the product of the factors already bound to challenges.
+// H_i has degree d, so each pair contributes at X = 0..d only, and the last
+// value H_i(d+1) is extrapolated once per round.  E_i[j] is one product of
+// two tables of about 2^(mu/2) entries (or a lookup for small rounds), so no
+// 2^mu-entry eq table is built, streamed or folded.  The values sent are the
+// same field elements as with the materialized table.
 //
 // Value bounds (the field code's contract is a product of inputs < A*p and
 // < B*p with A*B <= 128 lands below 2p):
 // * every table entry in memory is fully reduced, < p;
 // * Delta = u1 - u0 mod p is < p, so the extension e(X) = u0 + X*Delta built
-//   by plain additions is < (X+1) p <= (d+2) p <= 11 p;
-// * gate values are kept below 11 p before the product with eq's extension;
+//   by plain additions is < (X+1) p <= (d+1) p <= 10 p;
+// * gate values are kept below 12 p before the product with E (< p);
 // * per-thread sums of products stay below 2p.
 #pragma once
 
@@ -53,40 +62,105 @@ __device__ __forceinline__ void cvt_pair(const RawPair& r, Fe& lo, Fe& dl) {
 
 constexpr L9 kP11 = detail::mul_small(kP, 11);
 
+// ---- the factored eq table --------------------------------------------------------
+//
+// mu variables split into mh high and ml = floor(mu/2) low ones.  For round
+// i < mh, E_i[j] = HI_i[j >> ml] * LO[j mod 2^ml] with HI_i the eq table of
+// variables i+1..mh and LO that of mh+1..mu; for i >= mh, E_i = SUF_i, the
+// eq table of variables i+1..mu.  HI_i (2^(mh-i) entries) and SUF_i
+// (2^(mu-i) entries) are stored heap-style: a table of s entries at rows
+// [s, 2s).  Rows are 8 words, Montgomery form, < p.
+struct EqTabs {
+  const uint32_t* lo;
+  const uint32_t* hi;
+  const uint32_t* suf;
+  uint32_t ml, mh, mu;
+};
+
+__device__ __forceinline__ Fe load_row(const uint32_t* __restrict__ tab, uint32_t row) {
+  const uint4* p = reinterpret_cast<const uint4*>(tab + (uint64_t)row * 8);
+  const uint4 x0 = p[0], x1 = p[1];
+  const uint32_t w[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+  return fe_from_words(w);
+}
+
+// The rows behind E_i[j], loaded but not yet multiplied, so that their
+// latency overlaps the table loads of the pair.
+struct EqRows {
+  uint4 h0, h1, l0, l1;
+  bool split;
+};
+
+__device__ __forceinline__ EqRows issue_eq(const EqTabs& E, uint32_t round, uint32_t j) {
+  EqRows r;
+  r.split = round < E.mh;
+  const uint32_t hrow = r.split ? (1u << (E.mh - round)) + (j >> E.ml) : 0u;
+  const uint32_t lrow = r.split ? (j & ((1u << E.ml) - 1u)) : (1u << (E.mu - round)) + j;
+  const uint4* hp = reinterpret_cast<const uint4*>(E.hi + (uint64_t)hrow * 8);
+  const uint4* lp = reinterpret_cast<const uint4*>((r.split ? E.lo : E.suf) + (uint64_t)lrow * 8);
+  r.l0 = lp[0];
+  r.l1 = lp[1];
+  if (r.split) {
+    r.h0 = hp[0];
+    r.h1 = hp[1];
+  }
+  return r;
+}
+
+__device__ __forceinline__ Fe resolve_eq(const EqRows& r) {
+  const uint32_t wl[8] = {r.l0.x, r.l0.y, r.l0.z, r.l0.w, r.l1.x, r.l1.y, r.l1.z, r.l1.w};
+  const Fe l = fe_from_words(wl);
+  if (!r.split) return l;
+  const uint32_t wh[8] = {r.h0.x, r.h0.y, r.h0.z, r.h0.w, r.h1.x, r.h1.y, r.h1.z, r.h1.w};
+  return fe_reduce2(fe_mul(fe_from_words(wh), l));
+}
+
+// E_i[j] for round i (< p).
+__device__ __forceinline__ Fe eq_factor(const EqTabs& E, uint32_t round, uint32_t j) {
+  if (round < E.mh) {
+    const Fe h = load_row(E.hi, (1u << (E.mh - round)) + (j >> E.ml));
+    const Fe l = load_row(E.lo, j & ((1u << E.ml) - 1u));
+    return fe_reduce2(fe_mul(h, l));
+  }
+  return load_row(E.suf, (1u << (E.mu - round)) + j);
+}
+
 // ---- gates ---------------------------------------------------------------------
 //
-// eval() adds f_M(ext(X)) * eq(ext(X)) for X = 0..NE-1 of one pair to acc[X]
-// (kept < 2p).  The extension of a table at X is e(X) = lo + X*dl, built by
-// plain additions, so e(X) < (X+1) p.  The NE products of one step are
-// independent of each other, which keeps the multiply pipeline busy, and the
-// loads of the next table are issued before the current step's products so
-// that their latency is hidden.
+// eval() adds E * f_M(ext(X)) for X = 0..NH-1 (NH = d+1) of one pair to
+// acc[X] (kept < 2p).  The extension of a table at X is e(X) = lo + X*dl,
+// built by plain additions, so e(X) < (X+1) p.  The NH products of one step
+// are independent of each other, which keeps the multiply pipeline busy, and
+// the loads of the next table are issued before the current step's products
+// so that their latency is hidden.
 
 // f = qM*a*b + qL*a + qR*b + qO*c + qC, columns [a b c qM qL qR qO qC], degree 3,
 // evaluated as a*(qM*b + qL) + qR*b + qO*c + qC (four products per point).
 struct GateVanilla {
   static constexpr int K = 8;
   static constexpr int D = 3;
+  static constexpr int NH = D + 1;
   static constexpr int NE = D + 2;
   // f_M at one point from the witness extensions e[0..7] (< 5p); result < 11p.
   __device__ static __forceinline__ Fe point(const Fe* e) {
-    const Fe t1 = fe_mul(e[3], e[1]);                     // qM*b < 2p
-    const Fe t3 = fe_mul(e[0], fe_add(t1, e[4]));         // a*(qM*b + qL) < 2p (5*7)
-    const Fe t4 = fe_mul(e[5], e[1]);                     // qR*b < 2p
-    const Fe t5 = fe_mul(e[6], e[2]);                     // qO*c < 2p
-    return fe_add(fe_add(fe_add(t3, t4), t5), e[7]);      // < 11p
+    const Fe t1 = fe_mul(e[3], e[1]);                 // qM*b < 2p
+    const Fe t3 = fe_mul(e[0], fe_add(t1, e[4]));     // a*(qM*b + qL) < 2p (5*7)
+    const Fe t4 = fe_mul(e[5], e[1]);                 // qR*b < 2p
+    const Fe t5 = fe_mul(e[6], e[2]);                 // qO*c < 2p
+    return fe_add(fe_add(fe_add(t3, t4), t5), e[7]);  // < 11p
   }
   __device__ static __forceinline__ void eval(const TabPtrs& tp, uint64_t pitch, uint32_t j, uint32_t q,
-                                              Fe (&acc)[NE]) {
-    Fe bx[NE], t[NE], lo, dl, e;
+                                              const EqRows& er, Fe (&acc)[NH]) {
+    // extensions at X <= 3 are < 4p
+    Fe bx[NH], t[NH], lo, dl, e;
     RawPair ra = issue_pair(tp.p[1], pitch, j, q);  // b
     RawPair rb = issue_pair(tp.p[3], pitch, j, q);  // qM
     cvt_pair(ra, lo, dl);
     ra = issue_pair(tp.p[4], pitch, j, q);  // qL
     auto fb = [&](auto x) __attribute__((always_inline)) {
-      bx[x] = (x == 0) ? lo : fe_add(bx[x > 0 ? x - 1 : 0], dl);  // < 5p
+      bx[x] = (x == 0) ? lo : fe_add(bx[x > 0 ? x - 1 : 0], dl);
     };
-    Unroll<0, NE>::run(fb);
+    Unroll<0, NH>::run(fb);
     cvt_pair(rb, lo, dl);  // qM
     rb = issue_pair(tp.p[0], pitch, j, q);  // a
     e = lo;
@@ -94,23 +168,23 @@ struct GateVanilla {
       t[x] = fe_mul(e, bx[x]);  // < 2p
       e = fe_add(e, dl);
     };
-    Unroll<0, NE>::run(f1);
+    Unroll<0, NH>::run(f1);
     cvt_pair(ra, lo, dl);  // qL
     ra = issue_pair(tp.p[5], pitch, j, q);  // qR
     e = lo;
     auto f2 = [&](auto x) __attribute__((always_inline)) {
-      t[x] = fe_add(t[x], e);  // < 7p
+      t[x] = fe_add(t[x], e);  // < 6p
       e = fe_add(e, dl);
     };
-    Unroll<0, NE>::run(f2);
+    Unroll<0, NH>::run(f2);
     cvt_pair(rb, lo, dl);  // a
     rb = issue_pair(tp.p[6], pitch, j, q);  // qO
     e = lo;
     auto f3 = [&](auto x) __attribute__((always_inline)) {
-      t[x] = fe_mul(e, t[x]);  // < 2p (5*7)
+      t[x] = fe_mul(e, t[x]);  // < 2p (4*6)
       e = fe_add(e, dl);
     };
-    Unroll<0, NE>::run(f3);
+    Unroll<0, NH>::run(f3);
     cvt_pair(ra, lo, dl);  // qR
     ra = issue_pair(tp.p[2], pitch, j, q);  // c
     e = lo;
@@ -118,12 +192,11 @@ struct GateVanilla {
       t[x] = fe_add(t[x], fe_mul(e, bx[x]));  // < 4p
       e = fe_add(e, dl);
     };
-    Unroll<0, NE>::run(f4);
+    Unroll<0, NH>::run(f4);
     Fe lo2, dl2, e2;
     cvt_pair(rb, lo, dl);    // qO
     cvt_pair(ra, lo2, dl2);  // c
     rb = issue_pair(tp.p[7], pitch, j, q);  // qC
-    ra = issue_pair(tp.p[8], pitch, j, q);  // eq
     e = lo;
     e2 = lo2;
     auto f5 = [&](auto x) __attribute__((always_inline)) {
@@ -131,21 +204,16 @@ struct GateVanilla {
       e = fe_add(e, dl);
       e2 = fe_add(e2, dl2);
     };
-    Unroll<0, NE>::run(f5);
+    Unroll<0, NH>::run(f5);
     cvt_pair(rb, lo, dl);  // qC
+    const Fe E = resolve_eq(er);
     e = lo;
     auto f6 = [&](auto x) __attribute__((always_inline)) {
-      t[x] = fe_add(t[x], e);  // f < 11p
+      const Fe f = fe_add(t[x], e);                         // f < 10p
+      acc[x] = fe_csub(fe_add(acc[x], fe_mul(f, E)), kP2);  // product < 2p; acc < 2p
       e = fe_add(e, dl);
     };
-    Unroll<0, NE>::run(f6);
-    cvt_pair(ra, lo, dl);  // eq
-    e = lo;
-    auto f7 = [&](auto x) __attribute__((always_inline)) {
-      acc[x] = fe_csub(fe_add(acc[x], fe_mul(t[x], e)), kP2);  // product < 2p (11*5); acc < 2p
-      e = fe_add(e, dl);
-    };
-    Unroll<0, NE>::run(f7);
+    Unroll<0, NH>::run(f6);
   }
 };
 
@@ -154,6 +222,7 @@ template <int M>
 struct GateProd {
   static constexpr int K = M + 2;
   static constexpr int D = M + 1;
+  static constexpr int NH = D + 1;
   static constexpr int NE = D + 2;
   // f_M at one point from the witness extensions e[0..K-1] (< 11p); result < 8p.
   __device__ static __forceinline__ Fe point(const Fe* e) {
@@ -163,18 +232,18 @@ struct GateProd {
     return fe_csub(fe_sub_plus(prod, e[M + 1], kP11), kP8);
   }
   __device__ static __forceinline__ void eval(const TabPtrs& tp, uint64_t pitch, uint32_t j, uint32_t q,
-                                              Fe (&acc)[NE]) {
-    // extensions are < (M+3) p <= 11 p
-    Fe pr[NE], lo, dl, e;
+                                              const EqRows& er, Fe (&acc)[NH]) {
+    // extensions at X <= m+1 are < (m+2) p <= 10 p
+    Fe pr[NH], lo, dl, e;
     RawPair cur = issue_pair(tp.p[0], pitch, j, q);  // s
     RawPair nxt = issue_pair(tp.p[1], pitch, j, q);  // w1
     cvt_pair(cur, lo, dl);
     auto f0 = [&](auto x) __attribute__((always_inline)) {
       pr[x] = (x == 0) ? lo : fe_add(pr[x > 0 ? x - 1 : 0], dl);
     };
-    Unroll<0, NE>::run(f0);
+    Unroll<0, NH>::run(f0);
 #pragma unroll 1
-    for (int k = 1; k <= M; ++k) {  // pr *= w_k  (< 2p after each product: 11*11, then 2*11)
+    for (int k = 1; k <= M; ++k) {  // pr *= w_k  (< 2p after each product: 10*10, then 2*10)
       cur = nxt;
       nxt = issue_pair(tp.p[k + 1], pitch, j, q);  // w_{k+1}, or o after the last w
       cvt_pair(cur, lo, dl);
@@ -183,24 +252,17 @@ struct GateProd {
         pr[x] = fe_mul(pr[x], e);
         e = fe_add(e, dl);
       };
-      Unroll<0, NE>::run(fk);
+      Unroll<0, NH>::run(fk);
     }
-    cur = nxt;                                       // o
-    nxt = issue_pair(tp.p[M + 2], pitch, j, q);      // eq
-    cvt_pair(cur, lo, dl);  // o: pr + 11p - o in (0, 13p) -> < 8p
+    cvt_pair(nxt, lo, dl);  // o: pr + 11p - o in (0, 13p) -> < 8p
+    const Fe E = resolve_eq(er);
     e = lo;
     auto fo = [&](auto x) __attribute__((always_inline)) {
-      pr[x] = fe_csub(fe_sub_plus(pr[x], e, kP11), kP8);
+      const Fe f = fe_csub(fe_sub_plus(pr[x], e, kP11), kP8);
+      acc[x] = fe_csub(fe_add(acc[x], fe_mul(f, E)), kP2);  // product < 2p (8*1); acc < 2p
       e = fe_add(e, dl);
     };
-    Unroll<0, NE>::run(fo);
-    cvt_pair(nxt, lo, dl);  // eq
-    e = lo;
-    auto fe_ = [&](auto x) __attribute__((always_inline)) {
-      acc[x] = fe_csub(fe_add(acc[x], fe_mul(pr[x], e)), kP2);  // product < 2p (8*11); acc < 2p
-      e = fe_add(e, dl);
-    };
-    Unroll<0, NE>::run(fe_);
+    Unroll<0, NH>::run(fo);
   }
 };
 
@@ -226,7 +288,7 @@ __device__ __forceinline__ void lds_put(uint32_t* p, const Fe& a) {
 }
 
 // Sum (mod p) over the block of NV values per thread (each < p).  Thread x < NV
-// returns the block total of value x; other threads return garbage.
+// returns the block total of value x; other threads return 0.
 template <int NV>
 __device__ __forceinline__ Fe block_reduce(Fe (&v)[NV]) {
   __shared__ uint32_t red[kBlock / 64][NV][NL];
@@ -234,29 +296,20 @@ __device__ __forceinline__ Fe block_reduce(Fe (&v)[NV]) {
   auto f = [&](auto x) __attribute__((always_inline)) {
 #pragma unroll
     for (int s = 32; s >= 1; s >>= 1) v[x] = fe_addmod(v[x], shfl_xor_fe(v[x], s));
-    if (lane == 0) {
-#pragma unroll
-      for (int i = 0; i < NL; ++i) red[wave][x][i] = v[x].l[i];
-    }
+    if (lane == 0) lds_put(red[wave][x], v[x]);
   };
   Unroll<0, NV>::run(f);
   __syncthreads();
   Fe s = fe_zero();
   if (threadIdx.x < NV) {
     const int x = threadIdx.x;
-#pragma unroll
-    for (int i = 0; i < NL; ++i) s.l[i] = red[0][x][i];
-    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
-      Fe t;
-#pragma unroll
-      for (int i = 0; i < NL; ++i) t.l[i] = red[w][x][i];
-      s = fe_addmod(s, t);
-    }
+    s = lds_fe(red[0][x]);
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) s = fe_addmod(s, lds_fe(red[w][x]));
   }
   return s;
 }
 
-// ---- round kernel ---------------------------------------------------------------
+// ---- end of a round ------------------------------------------------------------
 
 struct RoundArgs {
   TabPtrs src, dst;
@@ -266,47 +319,116 @@ struct RoundArgs {
   uint32_t with_t0;            // 1: the last block computes T_0 (first round of a proof)
   uint32_t mu, gate, m;        // for T_0
   const uint32_t* r;           // canonical r (for T_0)
-  uint32_t* partials;          // [gridDim.x][NE][8]
+  uint32_t* partials;          // [gridDim.x][NH][8]
   Ctrl* ctrl;
   uint32_t* evals_out;         // G_i(0..d+1), canonical
   uint32_t* alpha_out;         // alpha_i, canonical
   uint32_t tail;               // 1: the last block also runs rounds round+1..mu and the openings
   uint32_t* openings;          // tail only: (k+1) x 8 canonical
+  EqTabs eq;
 };
 
-// Emits G_r and derives alpha_r from the round totals: thread x < NE holds
-// G_r(x) (Montgomery form, < p).  Writes G_r canonical to evals_out, hashes
-// T_{r-1} || G_r(0..d+1) into T_r, stores alpha_r canonical to alpha_out and
-// in Montgomery form to the control block.  All threads of the block call it.
-template <int NE>
-__device__ __forceinline__ void finalize_round(Ctrl* ctrl, uint32_t round, const Fe& tot, uint32_t* evals_out,
-                                               uint32_t* alpha_out) {
-  __shared__ uint32_t msg[8 + 8 * NE];
-  if (threadIdx.x < NE) {
-    uint32_t w[8];
-    fe_to_words(fe_from_mont(tot), w);
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      msg[8 + threadIdx.x * 8 + k] = w[k];
-      evals_out[threadIdx.x * 8 + k] = w[k];
+// (-1)^(d-k) C(d+1, k) in Montgomery form: H(d+1) = sum_k lam_k H(k) for any
+// polynomial H of degree <= d (its (d+1)-th finite difference vanishes).
+template <int D>
+struct Extrap {
+  L9 lam[D + 1];
+  constexpr Extrap() : lam{} {
+    for (int k = 0; k <= D; ++k) {
+      uint64_t c = 1;  // C(D+1, k)
+      for (int t = 0; t < k; ++t) c = c * (uint64_t)(D + 1 - t) / (uint64_t)(t + 1);
+      L9 v{};
+      for (uint64_t t = 0; t < c; ++t) {  // c * R mod p by repeated modular addition
+        v = detail::add(v, kOne);
+        if (detail::geq(v, kP)) v = detail::sub(v, kP);
+      }
+      if ((D - k) % 2 == 1) v = detail::sub(kP, v);  // c > 0 and c R mod p != 0, so p - v < p
+      lam[k] = v;
     }
   }
-  if (threadIdx.x < 8) msg[threadIdx.x] = ctrl->ts[threadIdx.x];
+};
+
+// eq1(x, r) = (1 - r) + x (2r - 1) for a small integer x, canonical r; canonical result.
+__device__ __forceinline__ Fe eq1_small(const Fe& r_c, uint32_t x) {
+  Fe one = fe_zero();
+  one.l[0] = 1;
+  const Fe omr = fe_submod(one, r_c);
+  const Fe step = fe_submod(fe_addmod(r_c, r_c), one);
+  return fe_addmod(omr, fe_reduce32(fe_mul_small(step, x)));
+}
+
+// Emits G_r and derives alpha_r.  On entry thread x < NH holds H_r(x)
+// (Montgomery form, < p).  Extrapolates H_r(d+1), forms
+// G_r(x) = coef_r[x] * H_r(x) (coef canonical, so one Montgomery product gives
+// G_r(x) canonical), writes G_r to evals_out, hashes T_{r-1} || G_r(0..d+1)
+// into T_r, stores alpha_r canonical to alpha_out and in Montgomery form to
+// the control block, and prepares C_{r+1} and coef_{r+1} for the next round.
+// All threads of the block call it.
+template <int D>
+__device__ __forceinline__ void finalize_round(Ctrl* ctrl, uint32_t round, uint32_t mu, const Fe& h,
+                                               uint32_t* evals_out, uint32_t* alpha_out) {
+  constexpr int NH = D + 1, NE = D + 2;
+  constexpr Extrap<D> ex{};
+  __shared__ uint32_t hv[NE][NL];
+  __shared__ uint32_t term[NH][NL];
+  __shared__ uint32_t msg[8 + 8 * NE];
+  __shared__ uint32_t cnext[NL];
+  const uint32_t x = threadIdx.x;
+  if (x < (uint32_t)NH) {
+    lds_put(hv[x], h);
+    Fe lam = fe_zero();
+    auto pick = [&](auto k) __attribute__((always_inline)) {
+      if (x == (uint32_t)k) lam = fe_const(ex.lam[k]);
+    };
+    Unroll<0, NH>::run(pick);
+    lds_put(term[x], fe_reduce2(fe_mul(h, lam)));
+  }
+  if (x < 8) msg[x] = ctrl->ts[x];
+  __syncthreads();
+  if (x == (uint32_t)NH) {
+    Fe s = lds_fe(term[0]);
+    for (int k = 1; k < NH; ++k) s = fe_addmod(s, lds_fe(term[k]));
+    lds_put(hv[NH], s);  // H(d+1)
+  }
+  __syncthreads();
+  if (x < (uint32_t)NE) {
+    uint32_t w[8];
+    fe_to_words(fe_reduce2(fe_mul(load_words_fe(ctrl->coef[x]), lds_fe(hv[x]))), w);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      msg[8 + x * 8 + k] = w[k];
+      evals_out[x * 8 + k] = w[k];
+    }
+  }
   __syncthreads();
   constexpr uint32_t LEN = 32u * (1u + NE);
   __shared__ uint32_t kw[((LEN + 9u + 63u) / 64u) * 64u];
   uint32_t dg[8];
   sha256_fixed_block<LEN>(msg, kw, dg);
-  if (threadIdx.x == 0) {
+  if (x == 0) {
     // alpha_r = digest (little-endian 256-bit integer) mod p; digest < 2^256 < 6p
     Fe al = fe_from_words(dg);
     al = fe_csub(fe_csub(fe_csub(al, kP4), kP2), kP);
 #pragma unroll
     for (int k = 0; k < 8; ++k) ctrl->ts[k] = dg[k];
     store_words_fe(alpha_out, al);
-    store_words_fe(ctrl->alpha_m[round - 1], fe_to_mont(al));
+    const Fe am = fe_to_mont(al);
+    store_words_fe(ctrl->alpha_m[round - 1], am);
+    // C_{r+1} = C_r * eq1(alpha_r, r_r), Montgomery form
+    const Fe one = fe_const(kOne);
+    const Fe rm = load_words_fe(ctrl->r_m[round - 1]);
+    const Fe e1 = fe_addmod(fe_submod(one, rm), fe_reduce2(fe_mul(am, fe_submod(fe_addmod(rm, rm), one))));
+    const Fe c = fe_reduce2(fe_mul(load_words_fe(ctrl->c_m), e1));
+    lds_put(cnext, c);
+    store_words_fe(ctrl->c_m, c);
     ctrl->round_done = round;
     ctrl->counter = 0;
+  }
+  __syncthreads();
+  if (round < mu && x < (uint32_t)NE) {
+    // coef_{r+1}[x] = C_{r+1} * eq1(x, r_{r+1}), canonical
+    const Fe e1 = eq1_small(load_words_fe(ctrl->r_c[round]), x);
+    store_words_fe(ctrl->coef[x], fe_reduce2(fe_mul(lds_fe(cnext), e1)));
   }
   __syncthreads();
 }
@@ -314,23 +436,24 @@ __device__ __forceinline__ void finalize_round(Ctrl* ctrl, uint32_t round, const
 // Sum of the blocks' partials, then finalize_round.  Runs in the last block
 // of a round kernel to finish.  Sixteen lanes own each point x: they stride
 // over the partials and combine with four shuffle steps.
-template <int NE>
+template <int D>
 __device__ __forceinline__ void finish_round(const RoundArgs& a, uint32_t nparts) {
-  static_assert(NE * 16 <= kBlock, "16 lanes per point");
-  __shared__ uint32_t tot_lds[NE][NL];
+  constexpr int NH = D + 1;
+  static_assert(NH * 16 <= kBlock, "16 lanes per point");
+  __shared__ uint32_t tot_lds[NH][NL];
   const uint32_t x = threadIdx.x / 16, g = threadIdx.x % 16;
   Fe s = fe_zero();
-  if (x < (uint32_t)NE) {
+  if (x < (uint32_t)NH) {
     for (uint32_t b = g; b < nparts; b += 16)
-      s = fe_addmod(s, load_words_fe(a.partials + ((uint64_t)b * NE + x) * 8));
+      s = fe_addmod(s, load_words_fe(a.partials + ((uint64_t)b * NH + x) * 8));
   }
 #pragma unroll
-  for (int m = 8; m >= 1; m >>= 1) s = fe_addmod(s, shfl_xor_fe(s, m));
-  if (x < (uint32_t)NE && g == 0) lds_put(tot_lds[x], s);
+  for (int msk = 8; msk >= 1; msk >>= 1) s = fe_addmod(s, shfl_xor_fe(s, msk));
+  if (x < (uint32_t)NH && g == 0) lds_put(tot_lds[x], s);
   __syncthreads();
   Fe tot = fe_zero();
-  if (threadIdx.x < (uint32_t)NE) tot = lds_fe(tot_lds[threadIdx.x]);
-  finalize_round<NE>(a.ctrl, a.round, tot, a.evals_out, a.alpha_out);
+  if (threadIdx.x < (uint32_t)NH) tot = lds_fe(tot_lds[threadIdx.x]);
+  finalize_round<D>(a.ctrl, a.round, a.mu, tot, a.evals_out, a.alpha_out);
 }
 
 // T_0 = SHA-256("ZCv1" || u32 mu || u32 gate || u32 m || enc(r_1..r_mu)).
@@ -352,20 +475,34 @@ __device__ __forceinline__ void transcript_t0(const RoundArgs& a) {
   }
 }
 
-// FOLD = false: evaluate G_i on tables holding 2q live entries (pairs j, j+q).
+// Last-block-done: true in the block that finished the round last (every
+// block has stored its partials before it counts itself).
+__device__ __forceinline__ bool last_block(Ctrl* ctrl) {
+  __shared__ uint32_t last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = (atomicAdd(&ctrl->counter, 1u) == gridDim.x - 1) ? 1u : 0u;
+  __syncthreads();
+  if (last) __threadfence();
+  return last != 0;
+}
+
+// ---- round kernel, one thread per pair ---------------------------------------------
+//
+// FOLD = false: evaluate H_i on tables holding 2q live entries (pairs j, j+q).
 // FOLD = true : the tables hold 4q entries; fold them with alpha_{i-1}
 //               (u[j] = t[j] + alpha (t[j+2q] - t[j]), same for j+q), write
-//               u[j], u[j+q] to dst, then evaluate G_i on (u[j], u[j+q]).
-// Each block stores its d+2 partial sums; the last block to finish sums them,
-// emits G_i and derives alpha_i (no second launch, no host round trip).
+//               u[j], u[j+q] to dst, then evaluate on (u[j], u[j+q]).
+// Each block stores its d+1 partial sums; the last block to finish sums
+// them, emits G_i and derives alpha_i (no second launch, no host round trip).
 template <class Gate, bool FOLD>
 __global__ __launch_bounds__(kBlock) void k_round(RoundArgs a) {
-  constexpr int K = Gate::K + 1;  // witness tables + eq (last)
-  constexpr int NE = Gate::NE;
+  constexpr int K = Gate::K;
+  constexpr int NH = Gate::NH;
   const uint32_t work_blocks = gridDim.x - (a.with_t0 ? 1u : 0u);
-  Fe acc[NE];
+  Fe acc[NH];
   auto z = [&](auto x) __attribute__((always_inline)) { acc[x] = fe_zero(); };
-  Unroll<0, NE>::run(z);
+  Unroll<0, NH>::run(z);
 
   if (blockIdx.x < work_blocks) {
     Fe alpha;
@@ -373,6 +510,7 @@ __global__ __launch_bounds__(kBlock) void k_round(RoundArgs a) {
     const uint32_t q = (uint32_t)a.q;
     const uint32_t stride = work_blocks * blockDim.x;
     for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < q; j += stride) {
+      const EqRows er = issue_eq(a.eq, a.round, j);
       if (FOLD) {
         const uint64_t sp = a.src_pitch, dp = a.dst_pitch;
         // fold table t while the four entries of table t+1 are loading
@@ -391,45 +529,37 @@ __global__ __launch_bounds__(kBlock) void k_round(RoundArgs a) {
           store_el(a.dst.p[t], dp, j, u0);
           store_el(a.dst.p[t], dp, j + q, u1);
         }
-        Gate::eval(a.dst, dp, j, q, acc);
+        Gate::eval(a.dst, dp, j, q, er, acc);
       } else {
-        Gate::eval(a.src, a.src_pitch, j, q, acc);
+        Gate::eval(a.src, a.src_pitch, j, q, er, acc);
       }
     }
   } else {
     transcript_t0(a);
   }
   auto red = [&](auto x) __attribute__((always_inline)) { acc[x] = fe_reduce2(acc[x]); };
-  Unroll<0, NE>::run(red);
-  const Fe tot = block_reduce<NE>(acc);
-  if (threadIdx.x < NE) store_words_fe(a.partials + ((uint64_t)blockIdx.x * NE + threadIdx.x) * 8, tot);
-
-  // last block done: the block that increments the counter last finishes the round
-  __shared__ uint32_t last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) last = (atomicAdd(&a.ctrl->counter, 1u) == gridDim.x - 1) ? 1u : 0u;
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  finish_round<NE>(a, gridDim.x);
+  Unroll<0, NH>::run(red);
+  const Fe tot = block_reduce<NH>(acc);
+  if (threadIdx.x < NH) store_words_fe(a.partials + ((uint64_t)blockIdx.x * NH + threadIdx.x) * 8, tot);
+  if (!last_block(a.ctrl)) return;
+  finish_round<Gate::D>(a, gridDim.x);
 }
 
 // ---- lane-split rounds: 16 lanes per pair -------------------------------------------
 //
 // For rounds with few pairs one thread per pair leaves the GPU idle and makes
 // the round as long as one thread's whole pair (fold of every table plus all
-// d+2 points).  Here a group of 16 lanes shares a pair: lane t folds (or
+// d+1 points).  Here a group of 16 lanes shares a pair: lane t folds (or
 // loads) table t, the pair goes through LDS, and lane x evaluates point X = x.
 
 constexpr int kGroup = 16;                     // lanes per pair
 constexpr int kSplitPairs = kBlock / kGroup;   // pairs per block
 
-// Contribution f_M(e(X)) * eq(e(X)) of one pair at point X (< 2p), from the
-// pair's tables u0 = lo[t], u1 = hi[t] (< p).  e(X) = u0 + X (u1 - u0) < (X+1) p.
+// f_M(e(X)) of one pair at point X (< 11p), from the pair's tables u0, u1
+// (< p).  e(X) = u0 + X (u1 - u0) < (X+1) p.
 template <class Gate, class Get>
-__device__ __forceinline__ Fe point_contrib(Get get, uint32_t X) {
-  constexpr int K = Gate::K + 1;
+__device__ __forceinline__ Fe point_f(Get get, uint32_t X) {
+  constexpr int K = Gate::K;
   Fe e[K];
   auto f = [&](auto t) __attribute__((always_inline)) {
     Fe u0, u1;
@@ -437,12 +567,12 @@ __device__ __forceinline__ Fe point_contrib(Get get, uint32_t X) {
     e[t] = fe_add(u0, fe_mul_small(fe_submod(u1, u0), X));
   };
   Unroll<0, K>::run(f);
-  return fe_mul(Gate::point(e), e[K - 1]);  // f < 11p, eq ext < 11p: 121 <= 128
+  return Gate::point(e);
 }
 
 // Block total (mod p) of one value per lane: lane g of every 16-lane group
-// holds the contribution for point g (< p).  Thread x < NE returns the total.
-template <int NE>
+// holds the contribution for point g (< p).  Thread x < NH returns the total.
+template <int NH>
 __device__ __forceinline__ Fe group_reduce(Fe c) {
   __shared__ uint32_t red[kBlock / 64][kGroup][NL];
   c = fe_addmod(c, shfl_xor_fe(c, 16));
@@ -451,7 +581,7 @@ __device__ __forceinline__ Fe group_reduce(Fe c) {
   if (lane < kGroup) lds_put(red[wave][lane], c);
   __syncthreads();
   Fe s = fe_zero();
-  if (threadIdx.x < NE) {
+  if (threadIdx.x < NH) {
     s = lds_fe(red[0][threadIdx.x]);
     for (int w = 1; w < (int)(blockDim.x >> 6); ++w) s = fe_addmod(s, lds_fe(red[w][threadIdx.x]));
   }
@@ -463,11 +593,12 @@ __device__ __forceinline__ Fe group_reduce(Fe c) {
 // entry round a.round has been finished (alpha_round derived) and the tables
 // at a.dst hold 2q live entries, q = a.q <= 2 kTailQ.  Runs rounds
 // a.round+1 .. mu (fold with the previous challenge, evaluate, finalize)
-// and the final fold, whose values are the openings.
+// and the final fold, whose values are the openings; eq's opening is
+// C_{mu+1} = eq(alpha, r).
 template <class Gate>
 __device__ __forceinline__ void run_tail(const RoundArgs& a) {
-  constexpr int K = Gate::K + 1;
-  constexpr int NE = Gate::NE;
+  constexpr int K = Gate::K;
+  constexpr int NH = Gate::NH;
   extern __shared__ uint32_t tail_lds[];  // [K][4 kTailQ][NL]
   constexpr uint32_t CAP = 4 * kTailQ;
   auto T = [&](int t, uint32_t e) -> uint32_t* { return tail_lds + ((uint32_t)t * CAP + e) * NL; };
@@ -495,27 +626,29 @@ __device__ __forceinline__ void run_tail(const RoundArgs& a) {
     Fe c = fe_zero();
     for (uint32_t base = 0; base < q; base += kSplitPairs) {
       const uint32_t e = base + pl;
-      if (e < q && g < (uint32_t)NE) {
+      if (e < q && g < (uint32_t)NH) {
         auto get = [&](int t, Fe& u0, Fe& u1) __attribute__((always_inline)) {
           u0 = lds_fe(T(t, e));
           u1 = lds_fe(T(t, e + q));
         };
-        c = fe_addmod(c, fe_reduce2(point_contrib<Gate>(get, g)));
+        const Fe E = eq_factor(a.eq, r, e);
+        c = fe_addmod(c, fe_reduce2(fe_mul(point_f<Gate>(get, g), E)));
       }
     }
-    const Fe tot = group_reduce<NE>(c);
-    finalize_round<NE>(a.ctrl, r, tot, a.evals_out + (uint64_t)(r - a.round) * NE * 8,
-                       a.alpha_out + (uint64_t)(r - a.round) * 8);
+    const Fe tot = group_reduce<NH>(c);
+    finalize_round<Gate::D>(a.ctrl, r, a.mu, tot, a.evals_out + (uint64_t)(r - a.round) * Gate::NE * 8,
+                            a.alpha_out + (uint64_t)(r - a.round) * 8);
   }
   if (threadIdx.x < K) store_words_fe(a.openings + threadIdx.x * 8, fe_from_mont(lds_fe(T(threadIdx.x, 0))));
+  if (threadIdx.x == K) store_words_fe(a.openings + K * 8, fe_from_mont(load_words_fe(a.ctrl->c_m)));
 }
 
 // Round with 16 lanes per pair.  Grid: q / 16 blocks (+1 with T_0).  With
 // a.tail, the last block to finish runs the rest of the proof (run_tail).
 template <class Gate, bool FOLD>
 __global__ __launch_bounds__(kBlock) void k_round_split(RoundArgs a) {
-  constexpr int K = Gate::K + 1;
-  constexpr int NE = Gate::NE;
+  constexpr int K = Gate::K;
+  constexpr int NH = Gate::NH;
   __shared__ uint32_t sh[kSplitPairs][K][2][NL];
   const uint32_t work_blocks = gridDim.x - (a.with_t0 ? 1u : 0u);
   const uint32_t g = threadIdx.x % kGroup, pl = threadIdx.x / kGroup;
@@ -554,29 +687,23 @@ __global__ __launch_bounds__(kBlock) void k_round_split(RoundArgs a) {
         lds_put(sh[pl][g][1], u1);
       }
       __syncthreads();
-      if (j < q && g < (uint32_t)NE) {
+      if (j < q && g < (uint32_t)NH) {
         auto get = [&](int t, Fe& u0, Fe& u1) __attribute__((always_inline)) {
           u0 = lds_fe(sh[pl][t][0]);
           u1 = lds_fe(sh[pl][t][1]);
         };
-        c = fe_addmod(c, fe_reduce2(point_contrib<Gate>(get, g)));
+        const Fe E = eq_factor(a.eq, a.round, j);
+        c = fe_addmod(c, fe_reduce2(fe_mul(point_f<Gate>(get, g), E)));
       }
       __syncthreads();
     }
   } else {
     transcript_t0(a);
   }
-  const Fe tot = group_reduce<NE>(c);
-  if (threadIdx.x < NE) store_words_fe(a.partials + ((uint64_t)blockIdx.x * NE + threadIdx.x) * 8, tot);
-
-  __shared__ uint32_t last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) last = (atomicAdd(&a.ctrl->counter, 1u) == gridDim.x - 1) ? 1u : 0u;
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  finish_round<NE>(a, gridDim.x);
+  const Fe tot = group_reduce<NH>(c);
+  if (threadIdx.x < NH) store_words_fe(a.partials + ((uint64_t)blockIdx.x * NH + threadIdx.x) * 8, tot);
+  if (!last_block(a.ctrl)) return;
+  finish_round<Gate::D>(a, gridDim.x);
   if (a.tail) run_tail<Gate>(a);
 }
 

@@ -9,66 +9,91 @@
 
 namespace zc {
 
-// ---- setup: r to Montgomery, eq half tables ---------------------------------------
+// ---- setup: r, the factored eq tables, round-1 coefficients -------------------------
 
-// One block: resets the control block, checks r and converts it to Montgomery
-// form.  (T_0 is hashed by an extra block of the first round kernel.)
-__global__ __launch_bounds__(64) void k_setup(const uint32_t* __restrict__ r, uint32_t mu, Ctrl* ctrl) {
+// One block: resets the control block, checks r, keeps it in canonical and
+// Montgomery form, sets C_1 = 1 and coef_1[x] = eq1(x, r_1) for x < ne.
+// (T_0 is hashed by an extra block of the first round kernel.)
+__global__ __launch_bounds__(64) void k_setup(const uint32_t* __restrict__ r, uint32_t mu, uint32_t ne,
+                                              Ctrl* ctrl) {
   if (threadIdx.x == 0) {
     ctrl->err = 0;
     ctrl->round_done = 0;
     ctrl->fold_done = 0;
     ctrl->counter = 0;
+    store_words_fe(ctrl->c_m, fe_const(kOne));
   }
   __syncthreads();  // the reset above must precede any error flagged below
   for (uint32_t i = threadIdx.x; i < mu; i += blockDim.x) {
     uint32_t w[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) w[k] = r[i * 8 + k];
+    for (int k = 0; k < 8; ++k) {
+      w[k] = r[i * 8 + k];
+      ctrl->r_c[i][k] = w[k];
+    }
     if (!words_lt_p(w)) set_error(ctrl, -4);
     store_words_fe(ctrl->r_m[i], fe_to_mont(fe_from_words(w)));
   }
+  if (threadIdx.x < ne) {
+    // coef_1[x] = C_1 eq1(x, r_1) = (1 - r_1) + x (2 r_1 - 1), canonical
+    uint32_t w[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) w[k] = r[k];
+    Fe rc = fe_from_words(w);
+    if (!words_lt_p(w)) rc = fe_zero();  // flagged above; keep the arithmetic in range
+    Fe one = fe_zero();
+    one.l[0] = 1;
+    const Fe step = fe_submod(fe_addmod(rc, rc), one);
+    const Fe e = fe_addmod(fe_submod(one, rc), fe_reduce32(fe_mul_small(step, threadIdx.x)));
+    store_words_fe(ctrl->coef[threadIdx.x], e);
+  }
 }
 
-// Half tables of eq: hi[y] over x_1..x_hb (y's MSB = x_1), lo[z] over
-// x_{hb+1}..x_mu.  Entry = product of (x ? r_i : 1 - r_i).  Stored as 8 words.
-__global__ __launch_bounds__(kBlock) void k_eq_half(const Ctrl* __restrict__ ctrl, uint32_t mu, uint32_t hb,
-                                                    uint32_t* __restrict__ hi, uint32_t* __restrict__ lo) {
-  const uint32_t lb = mu - hb;
-  const uint32_t nhi = 1u << hb, nlo = 1u << lb;
+// Rows of the factored eq tables (see EqTabs): LO (2^ml rows), the HI heap
+// (2^mh rows, row 0 unused) and the SUF heap (2^(ml+1) rows, row 0 unused),
+// concatenated in that order.  A row holding a table of nb variables whose
+// last variable is v is prod_k (bit ? r : 1 - r) over variables v-nb+1..v,
+// the most significant bit of the row index within the table being the
+// first of them.
+__global__ __launch_bounds__(kBlock) void k_eq_tables(const Ctrl* __restrict__ ctrl, uint32_t mu, uint32_t ml,
+                                                      uint32_t* __restrict__ rows) {
+  const uint32_t mh = mu - ml;
+  const uint32_t nlo = 1u << ml, nhi = 1u << mh, nsuf = 2u << ml;
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nhi + nlo) return;
-  const bool is_hi = e < nhi;
-  const uint32_t y = is_hi ? e : e - nhi;
-  const uint32_t nb = is_hi ? hb : lb;
-  const uint32_t first = is_hi ? 0 : hb;
+  if (e >= nlo + nhi + nsuf) return;
+  uint32_t y, nb, last;
+  if (e < nlo) {
+    y = e;
+    nb = ml;
+    last = mu;
+  } else if (e < nlo + nhi) {
+    const uint32_t hrow = e - nlo;
+    if (hrow == 0) return;
+    nb = 31u - __builtin_clz(hrow);  // table of 2^nb rows at [2^nb, 2^(nb+1))
+    y = hrow - (1u << nb);
+    last = mh;
+  } else {
+    const uint32_t srow = e - nlo - nhi;
+    if (srow == 0) return;
+    nb = 31u - __builtin_clz(srow);
+    y = srow - (1u << nb);
+    last = mu;
+  }
   const Fe one = fe_const(kOne);
   Fe acc = one;
   for (uint32_t k = 0; k < nb; ++k) {
-    const Fe ri = load_words_fe(ctrl->r_m[first + k]);
+    const Fe ri = load_words_fe(ctrl->r_m[last - nb + k]);  // variable last-nb+1+k (1-based)
     const uint32_t bit = (y >> (nb - 1 - k)) & 1u;
-    const Fe fac = bit ? ri : fe_submod(one, ri);
-    acc = fe_reduce2(fe_mul(acc, fac));
+    acc = fe_reduce2(fe_mul(acc, bit ? ri : fe_submod(one, ri)));
   }
-  store_words_fe((is_hi ? hi + (uint64_t)y * 8 : lo + (uint64_t)y * 8), acc);
-}
-
-// eq[b] = hi[b >> lb] * lo[b & (2^lb - 1)], limb-planar with pitch n.
-__global__ __launch_bounds__(kBlock) void k_build_eq(const uint32_t* __restrict__ hi, const uint32_t* __restrict__ lo,
-                                                     uint32_t lb, uint64_t n, uint32_t* __restrict__ eq) {
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < n; b += stride) {
-    const Fe h = load_words_fe(hi + (b >> lb) * 8);
-    const Fe l = load_words_fe(lo + (b & ((1ull << lb) - 1)) * 8);
-    store_el(eq, n, b, fe_reduce2(fe_mul(h, l)));
-  }
+  store_words_fe(rows + (uint64_t)e * 8, acc);
 }
 
 // ---- folds -----------------------------------------------------------------------
 
-// In-place fold of every table with alpha_round: t[j] <- t[j] + alpha (t[j+h] - t[j]),
-// j < h.  blockIdx.y selects the table.  With check_state the fold runs only
-// when round `round` has been evaluated and not yet folded.
+// In-place fold of every witness table with alpha_round:
+// t[j] <- t[j] + alpha (t[j+h] - t[j]), j < h.  blockIdx.y selects the table.
+// The fold runs only when round `round` has been evaluated and not yet folded.
 __global__ __launch_bounds__(kBlock) void k_fold(TabPtrs tabs, uint32_t ntab, uint64_t pitch, uint64_t h,
                                                  Ctrl* ctrl, uint32_t round) {
   if (ctrl->round_done != round || ctrl->fold_done + 1 != round) return;
@@ -99,19 +124,6 @@ __global__ void k_check_round(Ctrl* ctrl, uint32_t round) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     if (!(ctrl->round_done == round - 1 && ctrl->fold_done == round - 1)) set_error(ctrl, -5);
   }
-}
-
-// Last fold of a whole proof: every table holds 2 entries; write the folded
-// value of each, canonical, to openings[t].
-__global__ void k_openings(TabPtrs tabs, uint32_t ntab, uint64_t pitch, const Ctrl* __restrict__ ctrl,
-                           uint32_t mu, uint32_t* __restrict__ openings) {
-  const uint32_t t = threadIdx.x;
-  if (t >= ntab) return;
-  const Fe alpha = load_words_fe(ctrl->alpha_m[mu - 1]);
-  const Fe a0 = load_el(tabs.p[t], pitch, 0);
-  const Fe a1 = load_el(tabs.p[t], pitch, 1);
-  const Fe u = fe_addmod(a0, fe_reduce2(fe_mul(alpha, fe_submod(a1, a0))));
-  store_words_fe(openings + t * 8, fe_from_mont(u));
 }
 
 // ---- layout conversion ----------------------------------------------------------

@@ -24,8 +24,9 @@ def test_shape_queries(mu, gate, m, k, d):
     assert zc.degree(s) == d
     ws = zc.workspace_bytes(s)
     n = 1 << mu
-    # at least eq (n elements) + folded copies of k+1 tables (n/2 each)
-    assert ws >= 32 * n + 32 * (k + 1) * max(n // 2, 1)
+    # at least folded copies of the k witness tables (n/2 entries each) and the
+    # factored eq tables (about 4 * 2^(mu/2) entries)
+    assert ws >= 32 * k * max(n // 2, 1) + 32 * (1 << (mu // 2))
     assert ws % 256 == 0
 
 
