@@ -83,16 +83,12 @@ int dispatch_round(const zc_shape* s, bool fold, RoundKind kind, const RoundArgs
   }
 }
 
-RoundArgs round_args(const zc_shape* s, const Layout& L, void* ws, const uint32_t* r, uint32_t i,
+RoundArgs round_args(const zc_shape* s, const Layout& L, void* ws, uint32_t i,
                      uint32_t* round_evals, uint32_t* challenges) {
   RoundArgs a{};
   a.q = 1ull << (s->mu - i);
   a.round = i;
-  a.with_t0 = (i == 1) ? 1u : 0u;
   a.mu = s->mu;
-  a.gate = s->gate;
-  a.m = s->m;
-  a.r = r;
   a.partials = reinterpret_cast<uint32_t*>(bytes(ws) + L.partials);
   a.ctrl = ctrl_of(ws);
   a.evals_out = round_evals + (uint64_t)(i - 1) * (L.d + 2) * 8;
@@ -110,7 +106,7 @@ RoundArgs round_args(const zc_shape* s, const Layout& L, void* ws, const uint32_
 // r -> canonical and Montgomery copies, C_1 and coef_1, the factored eq tables.
 int launch_setup(const zc_shape* s, const Layout& L, const uint32_t* r, void* ws, hipStream_t st) {
   Ctrl* ctrl = ctrl_of(ws);
-  hipLaunchKernelGGL(k_setup, dim3(1), dim3(64), 0, st, r, s->mu, L.d + 2, ctrl);
+  hipLaunchKernelGGL(k_setup, dim3(1), dim3(64), 0, st, r, s->mu, s->gate, s->m, L.d + 2, ctrl);
   if (launch_ok() != ZC_OK) return ZC_EHIP;
   const uint32_t nrows = (1u << L.ml) + (1u << L.mh) + (2u << L.ml);
   uint32_t* rows = reinterpret_cast<uint32_t*>(bytes(ws) + L.eqrows);
@@ -158,7 +154,7 @@ int prove_impl(const zc_shape* shape, const uint32_t* const* tables, const uint3
         return ZC_EHIP;
       continue;
     }
-    RoundArgs a = round_args(shape, L, ws, r, i, round_evals, challenges);
+    RoundArgs a = round_args(shape, L, ws, i, round_evals, challenges);
     a.openings = openings;
     if (i == 1) {
       a.src = a.dst = orig;
@@ -234,7 +230,7 @@ int zc_round(const zc_shape* shape, const uint32_t* const* tables, const uint32_
     hipLaunchKernelGGL(k_check_round, dim3(1), dim3(1), 0, stream, ctrl, i);
     if ((rc = launch_ok()) != ZC_OK) return rc;
   }
-  RoundArgs a = round_args(shape, L, ws, r, i, round_evals, challenges);
+  RoundArgs a = round_args(shape, L, ws, i, round_evals, challenges);
   a.src = a.dst = cur;
   a.src_pitch = a.dst_pitch = n;
   return dispatch_round(shape, false, a.q > kSplitQ ? kPerPair : kSplit, a, stream);

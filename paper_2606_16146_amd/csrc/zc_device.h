@@ -27,7 +27,7 @@ struct Ctrl {
   uint32_t err;         // first device-detected error (negative status), 0 if none
   uint32_t round_done;  // last round whose challenge has been derived
   uint32_t fold_done;   // last round whose fold has been applied
-  uint32_t counter;     // blocks of the running round kernel that have finished
+  uint32_t reserved;
   uint32_t ts[8];                   // transcript digest T_i (little-endian bytes)
   uint32_t alpha_m[kMuMax][8];      // alpha_i, Montgomery form, < p
   uint32_t r_m[kMuMax][8];          // r_i, Montgomery form, < p

@@ -9,12 +9,6 @@
 namespace zc {
 namespace {
 
-inline uint32_t grid_for(uint64_t work, uint32_t cap) {
-  uint64_t b = (work + kBlock - 1) / kBlock;
-  if (b < 1) b = 1;
-  return (uint32_t)(b < cap ? b : cap);
-}
-
 inline int launch_ok() { return hipGetLastError() == hipSuccess ? 0 : -3; }
 
 template <class Gate>
@@ -22,27 +16,71 @@ size_t tail_lds_bytes() {
   return (size_t)(Gate::K + 1) * 4 * kTailQ * NL * sizeof(uint32_t);
 }
 
-// Launches the round kernel of round a.round.  The grid has one extra block
-// when a.with_t0 is set (it hashes T_0 while the others evaluate).
+// Blocks of `kernel` (kBlock threads, no dynamic LDS) resident per CU; the
+// answer depends only on the compiled kernel, so it is asked once.
+template <class KernelTag>
+int resident_blocks(const void* kernel) {
+  static const int n = [kernel] {
+    int b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kernel, kBlock, 0) != hipSuccess || b < 1) b = 1;
+    return b;
+  }();
+  return n;
+}
+
+template <class Gate, bool FOLD, bool SPLIT>
+struct RoundTag {};
+
+// Grid of a round kernel: enough blocks for the work, at most one resident
+// generation (CUs x resident blocks per CU) and at most kMaxBlocks.
+inline uint32_t round_grid(uint64_t blocks_for_work, int per_cu, int* rc) {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) {
+    *rc = -3;
+    return 0;
+  }
+  uint64_t cap = (uint64_t)cus * (uint64_t)per_cu;
+  if (cap > (uint64_t)kMaxBlocks) cap = kMaxBlocks;
+  if (blocks_for_work < 1) blocks_for_work = 1;
+  return (uint32_t)(blocks_for_work < cap ? blocks_for_work : cap);
+}
+
+// Launches round a.round: the round kernel (partial sums per block), then
+// k_finish (one block: sums, G_i, alpha_i, and with kSplitTail the rest of
+// the proof).
 template <class Gate>
 int launch_round(bool fold, RoundKind kind, RoundArgs a, hipStream_t st) {
-  const uint32_t t0 = a.with_t0 ? 1u : 0u;
+  int rc = 0;
+  uint32_t blocks;
   if (kind == kPerPair) {
-    const uint32_t blocks = grid_for(a.q, kMaxBlocks - 1) + t0;
+    const void* kern = fold ? reinterpret_cast<const void*>(&k_round<Gate, true>)
+                            : reinterpret_cast<const void*>(&k_round<Gate, false>);
+    const int per_cu = fold ? resident_blocks<RoundTag<Gate, true, false>>(kern)
+                            : resident_blocks<RoundTag<Gate, false, false>>(kern);
+    blocks = round_grid((a.q + kBlock - 1) / kBlock, per_cu, &rc);
+    if (rc) return rc;
     if (fold)
       hipLaunchKernelGGL((k_round<Gate, true>), dim3(blocks), dim3(kBlock), 0, st, a);
     else
       hipLaunchKernelGGL((k_round<Gate, false>), dim3(blocks), dim3(kBlock), 0, st, a);
   } else {
-    const uint64_t nb = (a.q + kSplitPairs - 1) / kSplitPairs;
-    const uint32_t blocks = (uint32_t)(nb < (uint64_t)(kMaxBlocks - 1) ? nb : (uint64_t)(kMaxBlocks - 1)) + t0;
-    a.tail = (kind == kSplitTail) ? 1u : 0u;
-    const size_t lds = a.tail ? tail_lds_bytes<Gate>() : 0;
+    const void* kern = fold ? reinterpret_cast<const void*>(&k_round_split<Gate, true>)
+                            : reinterpret_cast<const void*>(&k_round_split<Gate, false>);
+    const int per_cu = fold ? resident_blocks<RoundTag<Gate, true, true>>(kern)
+                            : resident_blocks<RoundTag<Gate, false, true>>(kern);
+    blocks = round_grid((a.q + kSplitPairs - 1) / kSplitPairs, per_cu, &rc);
+    if (rc) return rc;
     if (fold)
-      hipLaunchKernelGGL((k_round_split<Gate, true>), dim3(blocks), dim3(kBlock), lds, st, a);
+      hipLaunchKernelGGL((k_round_split<Gate, true>), dim3(blocks), dim3(kBlock), 0, st, a);
     else
-      hipLaunchKernelGGL((k_round_split<Gate, false>), dim3(blocks), dim3(kBlock), lds, st, a);
+      hipLaunchKernelGGL((k_round_split<Gate, false>), dim3(blocks), dim3(kBlock), 0, st, a);
   }
+  if ((rc = launch_ok()) != 0) return rc;
+  a.nparts = blocks;
+  a.tail = (kind == kSplitTail) ? 1u : 0u;
+  const size_t lds = a.tail ? tail_lds_bytes<Gate>() : 0;
+  hipLaunchKernelGGL((k_finish<Gate>), dim3(1), dim3(kBlock), lds, st, a);
   return launch_ok();
 }
 

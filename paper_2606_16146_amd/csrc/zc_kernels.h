@@ -316,14 +316,13 @@ struct RoundArgs {
   uint64_t src_pitch, dst_pitch;
   uint64_t q;                  // pairs of the evaluated round
   uint32_t round;              // i (1-based)
-  uint32_t with_t0;            // 1: the last block computes T_0 (first round of a proof)
-  uint32_t mu, gate, m;        // for T_0
-  const uint32_t* r;           // canonical r (for T_0)
-  uint32_t* partials;          // [gridDim.x][NH][8]
+  uint32_t mu;
+  uint32_t nparts;             // blocks of the round kernel (partial sums to add up)
+  uint32_t* partials;          // [nparts][NH][8]
   Ctrl* ctrl;
   uint32_t* evals_out;         // G_i(0..d+1), canonical
   uint32_t* alpha_out;         // alpha_i, canonical
-  uint32_t tail;               // 1: the last block also runs rounds round+1..mu and the openings
+  uint32_t tail;               // 1: the finisher also runs rounds round+1..mu and the openings
   uint32_t* openings;          // tail only: (k+1) x 8 canonical
   EqTabs eq;
 };
@@ -422,7 +421,6 @@ __device__ __forceinline__ void finalize_round(Ctrl* ctrl, uint32_t round, uint3
     lds_put(cnext, c);
     store_words_fe(ctrl->c_m, c);
     ctrl->round_done = round;
-    ctrl->counter = 0;
   }
   __syncthreads();
   if (round < mu && x < (uint32_t)NE) {
@@ -433,82 +431,31 @@ __device__ __forceinline__ void finalize_round(Ctrl* ctrl, uint32_t round, uint3
   __syncthreads();
 }
 
-// Sum of the blocks' partials, then finalize_round.  Runs in the last block
-// of a round kernel to finish.  Sixteen lanes own each point x: they stride
-// over the partials and combine with four shuffle steps.
-template <int D>
-__device__ __forceinline__ void finish_round(const RoundArgs& a, uint32_t nparts) {
-  constexpr int NH = D + 1;
-  static_assert(NH * 16 <= kBlock, "16 lanes per point");
-  __shared__ uint32_t tot_lds[NH][NL];
-  const uint32_t x = threadIdx.x / 16, g = threadIdx.x % 16;
-  Fe s = fe_zero();
-  if (x < (uint32_t)NH) {
-    for (uint32_t b = g; b < nparts; b += 16)
-      s = fe_addmod(s, load_words_fe(a.partials + ((uint64_t)b * NH + x) * 8));
-  }
-#pragma unroll
-  for (int msk = 8; msk >= 1; msk >>= 1) s = fe_addmod(s, shfl_xor_fe(s, msk));
-  if (x < (uint32_t)NH && g == 0) lds_put(tot_lds[x], s);
-  __syncthreads();
-  Fe tot = fe_zero();
-  if (threadIdx.x < (uint32_t)NH) tot = lds_fe(tot_lds[threadIdx.x]);
-  finalize_round<D>(a.ctrl, a.round, a.mu, tot, a.evals_out, a.alpha_out);
-}
-
-// T_0 = SHA-256("ZCv1" || u32 mu || u32 gate || u32 m || enc(r_1..r_mu)).
-__device__ __forceinline__ void transcript_t0(const RoundArgs& a) {
-  __shared__ uint32_t m0[4 + kMuMax * 8];
-  if (threadIdx.x == 0) {
-    m0[0] = 0x3176435au;  // bytes 'Z' 'C' 'v' '1'
-    m0[1] = a.mu;
-    m0[2] = a.gate;
-    m0[3] = a.m;
-  }
-  for (uint32_t i = threadIdx.x; i < a.mu * 8; i += blockDim.x) m0[4 + i] = a.r[i];
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t dg[8];
-    sha256(m0, 16u + 32u * a.mu, dg);
-#pragma unroll
-    for (int k = 0; k < 8; ++k) a.ctrl->ts[k] = dg[k];
-  }
-}
-
-// Last-block-done: true in the block that finished the round last (every
-// block has stored its partials before it counts itself).
-__device__ __forceinline__ bool last_block(Ctrl* ctrl) {
-  __shared__ uint32_t last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) last = (atomicAdd(&ctrl->counter, 1u) == gridDim.x - 1) ? 1u : 0u;
-  __syncthreads();
-  if (last) __threadfence();
-  return last != 0;
-}
-
 // ---- round kernel, one thread per pair ---------------------------------------------
 //
 // FOLD = false: evaluate H_i on tables holding 2q live entries (pairs j, j+q).
 // FOLD = true : the tables hold 4q entries; fold them with alpha_{i-1}
 //               (u[j] = t[j] + alpha (t[j+2q] - t[j]), same for j+q), write
 //               u[j], u[j+q] to dst, then evaluate on (u[j], u[j+q]).
-// Each block stores its d+1 partial sums; the last block to finish sums
-// them, emits G_i and derives alpha_i (no second launch, no host round trip).
+// The grid is sized to be resident at once (one generation of blocks, each
+// striding over the pairs).  Each block stores its d+1 partial sums; k_finish
+// adds them up in the next launch, whose start orders it after every block's
+// stores, so no block needs a device-wide fence (on this GPU such a fence
+// writes back and invalidates the L2 and holds the CU for several
+// microseconds).
 template <class Gate, bool FOLD>
 __global__ __launch_bounds__(kBlock) void k_round(RoundArgs a) {
   constexpr int K = Gate::K;
   constexpr int NH = Gate::NH;
-  const uint32_t work_blocks = gridDim.x - (a.with_t0 ? 1u : 0u);
   Fe acc[NH];
   auto z = [&](auto x) __attribute__((always_inline)) { acc[x] = fe_zero(); };
   Unroll<0, NH>::run(z);
 
-  if (blockIdx.x < work_blocks) {
+  {
     Fe alpha;
     if (FOLD) alpha = load_words_fe(a.ctrl->alpha_m[a.round - 2]);
     const uint32_t q = (uint32_t)a.q;
-    const uint32_t stride = work_blocks * blockDim.x;
+    const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < q; j += stride) {
       const EqRows er = issue_eq(a.eq, a.round, j);
       if (FOLD) {
@@ -534,15 +481,11 @@ __global__ __launch_bounds__(kBlock) void k_round(RoundArgs a) {
         Gate::eval(a.src, a.src_pitch, j, q, er, acc);
       }
     }
-  } else {
-    transcript_t0(a);
   }
   auto red = [&](auto x) __attribute__((always_inline)) { acc[x] = fe_reduce2(acc[x]); };
   Unroll<0, NH>::run(red);
   const Fe tot = block_reduce<NH>(acc);
   if (threadIdx.x < NH) store_words_fe(a.partials + ((uint64_t)blockIdx.x * NH + threadIdx.x) * 8, tot);
-  if (!last_block(a.ctrl)) return;
-  finish_round<Gate::D>(a, gridDim.x);
 }
 
 // ---- lane-split rounds: 16 lanes per pair -------------------------------------------
@@ -643,19 +586,18 @@ __device__ __forceinline__ void run_tail(const RoundArgs& a) {
   if (threadIdx.x == K) store_words_fe(a.openings + K * 8, fe_from_mont(load_words_fe(a.ctrl->c_m)));
 }
 
-// Round with 16 lanes per pair.  Grid: q / 16 blocks (+1 with T_0).  With
-// a.tail, the last block to finish runs the rest of the proof (run_tail).
+// Round with 16 lanes per pair; the grid strides over the pairs and is sized
+// like k_round's.
 template <class Gate, bool FOLD>
 __global__ __launch_bounds__(kBlock) void k_round_split(RoundArgs a) {
   constexpr int K = Gate::K;
   constexpr int NH = Gate::NH;
   __shared__ uint32_t sh[kSplitPairs][K][2][NL];
-  const uint32_t work_blocks = gridDim.x - (a.with_t0 ? 1u : 0u);
   const uint32_t g = threadIdx.x % kGroup, pl = threadIdx.x / kGroup;
   Fe c = fe_zero();
-  if (blockIdx.x < work_blocks) {
+  {
     const uint32_t q = (uint32_t)a.q;
-    const uint64_t stride = (uint64_t)work_blocks * kSplitPairs;
+    const uint64_t stride = (uint64_t)gridDim.x * kSplitPairs;
     for (uint64_t base = (uint64_t)blockIdx.x * kSplitPairs; base < q; base += stride) {
       const uint32_t j = (uint32_t)(base + pl);
       if (j < q && g < (uint32_t)K) {
@@ -697,13 +639,32 @@ __global__ __launch_bounds__(kBlock) void k_round_split(RoundArgs a) {
       }
       __syncthreads();
     }
-  } else {
-    transcript_t0(a);
   }
   const Fe tot = group_reduce<NH>(c);
   if (threadIdx.x < NH) store_words_fe(a.partials + ((uint64_t)blockIdx.x * NH + threadIdx.x) * 8, tot);
-  if (!last_block(a.ctrl)) return;
-  finish_round<Gate::D>(a, gridDim.x);
+}
+
+// ---- end of a round: one block -------------------------------------------------------
+//
+// Adds up the round kernel's a.nparts partial sums (every thread takes a
+// strided share, then one block reduction), emits G_i, derives alpha_i and,
+// with a.tail, runs the rest of the proof in LDS (run_tail).  The challenge
+// never leaves the device.
+template <class Gate>
+__global__ __launch_bounds__(kBlock) void k_finish(RoundArgs a) {
+  constexpr int NH = Gate::NH;
+  Fe v[NH];
+  auto z = [&](auto x) __attribute__((always_inline)) { v[x] = fe_zero(); };
+  Unroll<0, NH>::run(z);
+#pragma unroll 2
+  for (uint32_t b = threadIdx.x; b < a.nparts; b += blockDim.x) {
+    auto add = [&](auto x) __attribute__((always_inline)) {
+      v[x] = fe_addmod(v[x], load_words_fe(a.partials + ((uint64_t)b * NH + x) * 8));
+    };
+    Unroll<0, NH>::run(add);
+  }
+  const Fe tot = block_reduce<NH>(v);
+  finalize_round<Gate::D>(a.ctrl, a.round, a.mu, tot, a.evals_out, a.alpha_out);
   if (a.tail) run_tail<Gate>(a);
 }
 

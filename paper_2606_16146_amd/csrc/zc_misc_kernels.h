@@ -12,17 +12,23 @@ namespace zc {
 // ---- setup: r, the factored eq tables, round-1 coefficients -------------------------
 
 // One block: resets the control block, checks r, keeps it in canonical and
-// Montgomery form, sets C_1 = 1 and coef_1[x] = eq1(x, r_1) for x < ne.
-// (T_0 is hashed by an extra block of the first round kernel.)
-__global__ __launch_bounds__(64) void k_setup(const uint32_t* __restrict__ r, uint32_t mu, uint32_t ne,
-                                              Ctrl* ctrl) {
+// Montgomery form, sets C_1 = 1 and coef_1[x] = eq1(x, r_1) for x < ne, and
+// starts the transcript:
+// T_0 = SHA-256("ZCv1" || u32 mu || u32 gate || u32 m || enc(r_1) .. enc(r_mu)).
+__global__ __launch_bounds__(64) void k_setup(const uint32_t* __restrict__ r, uint32_t mu, uint32_t gate,
+                                              uint32_t m, uint32_t ne, Ctrl* ctrl) {
+  __shared__ uint32_t m0[4 + kMuMax * 8];
   if (threadIdx.x == 0) {
     ctrl->err = 0;
     ctrl->round_done = 0;
     ctrl->fold_done = 0;
-    ctrl->counter = 0;
     store_words_fe(ctrl->c_m, fe_const(kOne));
+    m0[0] = 0x3176435au;  // bytes 'Z' 'C' 'v' '1'
+    m0[1] = mu;
+    m0[2] = gate;
+    m0[3] = m;
   }
+  for (uint32_t i = threadIdx.x; i < mu * 8; i += blockDim.x) m0[4 + i] = r[i];
   __syncthreads();  // the reset above must precede any error flagged below
   for (uint32_t i = threadIdx.x; i < mu; i += blockDim.x) {
     uint32_t w[8];
@@ -46,6 +52,13 @@ __global__ __launch_bounds__(64) void k_setup(const uint32_t* __restrict__ r, ui
     const Fe step = fe_submod(fe_addmod(rc, rc), one);
     const Fe e = fe_addmod(fe_submod(one, rc), fe_reduce32(fe_mul_small(step, threadIdx.x)));
     store_words_fe(ctrl->coef[threadIdx.x], e);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t dg[8];
+    sha256(m0, 16u + 32u * mu, dg);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) ctrl->ts[k] = dg[k];
   }
 }
 
