@@ -120,6 +120,8 @@ constexpr L9 kP2 = detail::mul_small(kP, 2);
 constexpr L9 kP4 = detail::mul_small(kP, 4);
 constexpr L9 kP8 = detail::mul_small(kP, 8);
 constexpr L9 kP16 = detail::mul_small(kP, 16);
+constexpr L9 kP32 = detail::mul_small(kP, 32);
+constexpr L9 kP64 = detail::mul_small(kP, 64);
 
 static_assert(((kP.v[0] * kNInv) & LM) == LM, "-p^-1 mod 2^29");
 static_assert(kP.v[8] < (1u << 22), "p < 2^254");
@@ -186,15 +188,20 @@ __device__ __forceinline__ Fe fe_add(const Fe& a, const Fe& b) {
   return r;
 }
 
-// a - C if a >= C, else a (a, C normalized).
+// a - C if a >= C, else a (a, C normalized; top limbs below 2^31).
 __device__ __forceinline__ Fe fe_csub(const Fe& a, const L9& C) {
   Fe d;
   int32_t br = 0;
 #pragma unroll
   for (int i = 0; i < NL; ++i) {
     const int32_t t = (int32_t)a.l[i] - (int32_t)C.v[i] + br;
-    br = t >> 29;  // 0 or -1 (t > -2^30)
-    d.l[i] = (uint32_t)t & LM;
+    if (i < NL - 1) {
+      br = t >> 29;  // 0 or -1 (-2^30 < t < 2^29)
+      d.l[i] = (uint32_t)t & LM;
+    } else {
+      br = t >> 31;  // the sign of a - C
+      d.l[i] = (uint32_t)t;
+    }
   }
 #pragma unroll
   for (int i = 0; i < NL; ++i) d.l[i] = br ? a.l[i] : d.l[i];
@@ -228,6 +235,11 @@ __device__ __forceinline__ Fe fe_reduce2(const Fe& a) { return fe_csub(a, kP); }
 // Reduce a value < 32p into [0, p).
 __device__ __forceinline__ Fe fe_reduce32(const Fe& a) {
   return fe_csub(fe_csub(fe_csub(fe_csub(fe_csub(a, kP16), kP8), kP4), kP2), kP);
+}
+
+// Reduce a value < 128p into [0, p).
+__device__ __forceinline__ Fe fe_reduce128(const Fe& a) {
+  return fe_reduce32(fe_csub(fe_csub(a, kP64), kP32));
 }
 
 // ---- Montgomery product -----------------------------------------------------

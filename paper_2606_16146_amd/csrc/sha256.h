@@ -205,11 +205,11 @@ __device__ __forceinline__ void sha256_compress_kw(uint32_t h[8], const uint32_t
   for (int i = 0; i < 8; ++i) h[i] += v[i];
 }
 
-// SHA-256 of LEN bytes (multiple of 4, compile-time) at msg, computed by the
-// whole block: call from every thread; kw is LDS scratch of NB*64 words.
-// The digest (little-endian byte order, as in sha256) lands in thread 0's out.
+// Message schedules of a LEN-byte message (LEN a multiple of 4, compile-time):
+// lane b < NB of the calling block writes k_t + w_t of block b to kw[64 b + t].
+// Call from every thread; a barrier must follow before the compression.
 template <uint32_t LEN>
-__device__ __forceinline__ void sha256_fixed_block(const uint32_t* msg, uint32_t* kw, uint32_t out[8]) {
+__device__ __forceinline__ void sha256_schedule_block(const uint32_t* msg, uint32_t* kw) {
   static_assert(LEN % 4 == 0, "word-aligned messages only");
   constexpr uint32_t NB = (LEN + 9u + 63u) / 64u;
   constexpr uint32_t TW = NB * 16u;
@@ -224,7 +224,7 @@ __device__ __forceinline__ void sha256_fixed_block(const uint32_t* msg, uint32_t
       if (w * 4u == LEN) x = 0x80000000u;
       if (w == TW - 1) x = LEN << 3;
       W[t] = x;
-      kw[b * 64u + t] = x + kSha256KDev[t];
+      kw[b * 64u + t] = x + kSha256K[t];
     }
 #pragma unroll
     for (int t = 16; t < 64; ++t) {
@@ -232,17 +232,19 @@ __device__ __forceinline__ void sha256_fixed_block(const uint32_t* msg, uint32_t
       const uint32_t s0 = sha_xor3(sha_rotr(w15, 7), sha_rotr(w15, 18), w15 >> 3);
       const uint32_t s1 = sha_xor3(sha_rotr(w2, 17), sha_rotr(w2, 19), w2 >> 10);
       W[t & 15] = W[t & 15] + s0 + W[(t - 7) & 15] + s1;
-      kw[b * 64u + t] = W[t & 15] + kSha256KDev[t];
+      kw[b * 64u + t] = W[t & 15] + kSha256K[t];
     }
   }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t h[8];
-    sha256_init(h);
+}
+
+// The compression of nb blocks whose schedules sha256_schedule_block left
+// in kw; one lane.  The digest is in the byte order of sha256().
+__device__ __forceinline__ void sha256_compress_blocks(const uint32_t* kw, uint32_t nb, uint32_t out[8]) {
+  uint32_t h[8];
+  sha256_init(h);
 #pragma unroll 1
-    for (uint32_t b = 0; b < NB; ++b) sha256_compress_kw(h, kw + b * 64u);
-    sha256_digest(h, out);
-  }
+  for (uint32_t b = 0; b < nb; ++b) sha256_compress_kw(h, kw + b * 64u);
+  sha256_digest(h, out);
 }
 
 }  // namespace zc

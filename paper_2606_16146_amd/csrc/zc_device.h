@@ -22,7 +22,8 @@ constexpr int kMaxBlocks = 2048;
 //   eq_r(a_1..a_{i-1}, X, x_{>i}) = C_i * eq1(X, r_i) * E_i[x_{>i}],
 // C_i = prod_{k<i} eq1(alpha_k, r_k), E_i = eq over r_{i+1..mu}, so the
 // round kernels accumulate H_i(X) = sum_j E_i[j] f(ext_j(X)) and the round's
-// finisher multiplies by coef_i[X] = C_i * eq1(X, r_i).
+// finisher multiplies by coef_i[X] = C_i * eq1(X, r_i).  H_i has degree d, so
+// G_i(d+1) comes from H_i(0..d) through lam_k = (-1)^(d-k) C(d+1, k).
 struct Ctrl {
   uint32_t err;         // first device-detected error (negative status), 0 if none
   uint32_t round_done;  // last round whose challenge has been derived
@@ -34,6 +35,7 @@ struct Ctrl {
   uint32_t r_c[kMuMax][8];          // r_i, canonical
   uint32_t c_m[8];                  // C_{round_done+1}, Montgomery form
   uint32_t coef[kMaxEvals][8];      // C_i * eq1(x, r_i), canonical, i = round_done + 1
+  uint32_t coefl[kMaxEvals][8];     // coef[d+1] * lam_k (k <= d), canonical: G(d+1) = sum_k coefl[k] H(k)
 };
 
 constexpr uint32_t kCtrlBytes = 4096;

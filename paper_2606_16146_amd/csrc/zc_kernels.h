@@ -347,88 +347,207 @@ struct Extrap {
   }
 };
 
-// eq1(x, r) = (1 - r) + x (2r - 1) for a small integer x, canonical r; canonical result.
-__device__ __forceinline__ Fe eq1_small(const Fe& r_c, uint32_t x) {
-  Fe one = fe_zero();
-  one.l[0] = 1;
-  const Fe omr = fe_submod(one, r_c);
-  const Fe step = fe_submod(fe_addmod(r_c, r_c), one);
+// eq1(x, r) = (1 - r) + x (2r - 1) for a small integer x (<= 15).  With
+// one = 1 (r canonical) the result is canonical; with one = R (r in
+// Montgomery form) it is in Montgomery form.
+__device__ __forceinline__ Fe eq1_small(const Fe& r, uint32_t x, const Fe& one) {
+  const Fe omr = fe_submod(one, r);
+  const Fe step = fe_submod(fe_addmod(r, r), one);
   return fe_addmod(omr, fe_reduce32(fe_mul_small(step, x)));
 }
 
-// Emits G_r and derives alpha_r.  On entry thread x < NH holds H_r(x)
-// (Montgomery form, < p).  Extrapolates H_r(d+1), forms
-// G_r(x) = coef_r[x] * H_r(x) (coef canonical, so one Montgomery product gives
-// G_r(x) canonical), writes G_r to evals_out, hashes T_{r-1} || G_r(0..d+1)
-// into T_r, stores alpha_r canonical to alpha_out and in Montgomery form to
-// the control block, and prepares C_{r+1} and coef_{r+1} for the next round.
-// All threads of the block call it.
-template <int D>
-__device__ __forceinline__ void finalize_round(Ctrl* ctrl, uint32_t round, uint32_t mu, const Fe& h,
-                                               uint32_t* evals_out, uint32_t* alpha_out) {
-  constexpr int NH = D + 1, NE = D + 2;
-  constexpr Extrap<D> ex{};
-  __shared__ uint32_t hv[NE][NL];
-  __shared__ uint32_t term[NH][NL];
-  __shared__ uint32_t msg[8 + 8 * NE];
-  __shared__ uint32_t cnext[NL];
-  const uint32_t x = threadIdx.x;
-  if (x < (uint32_t)NH) {
-    lds_put(hv[x], h);
-    Fe lam = fe_zero();
-    auto pick = [&](auto k) __attribute__((always_inline)) {
-      if (x == (uint32_t)k) lam = fe_const(ex.lam[k]);
-    };
-    Unroll<0, NH>::run(pick);
-    lds_put(term[x], fe_reduce2(fe_mul(h, lam)));
-  }
-  if (x < 8) msg[x] = ctrl->ts[x];
-  __syncthreads();
-  if (x == (uint32_t)NH) {
-    Fe s = lds_fe(term[0]);
-    for (int k = 1; k < NH; ++k) s = fe_addmod(s, lds_fe(term[k]));
-    lds_put(hv[NH], s);  // H(d+1)
-  }
-  __syncthreads();
-  if (x < (uint32_t)NE) {
-    uint32_t w[8];
-    fe_to_words(fe_reduce2(fe_mul(load_words_fe(ctrl->coef[x]), lds_fe(hv[x]))), w);
+__device__ __forceinline__ Fe fe_one_plain() {
+  Fe one = fe_zero();
+  one.l[0] = 1;
+  return one;
+}
+
+// Montgomery product reduced below p.
+__device__ __forceinline__ Fe mont(const Fe& a, const Fe& b) { return fe_reduce2(fe_mul(a, b)); }
+
+// The same value, held in vector registers.  A value the compiler can prove
+// uniform across the wave (e.g. read from one LDS or control-block address)
+// would otherwise be multiplied on the scalar unit, where a 32 x 32 -> 64-bit
+// product takes four instructions and the unit is shared by the whole CU.
+__device__ __forceinline__ Fe fe_vgpr(Fe a) {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      msg[8 + x * 8 + k] = w[k];
-      evals_out[x * 8 + k] = w[k];
+  for (int i = 0; i < NL; ++i) asm("" : "+v"(a.l[i]));
+  return a;
+}
+
+// ---- the end of a round ---------------------------------------------------------
+//
+// Round i sends G_i(x) = C_i eq1(x, r_i) H_i(x), x = 0..d+1, where H_i(x)
+// (x <= d) are the block sums and H_i(d+1) = sum_k lam_k H_i(k).  The
+// coefficients coef_i[x] = C_i eq1(x, r_i) (x <= d+1) and
+// coefl_i[k] = coef_i[d+1] lam_k (k <= d) are canonical, so one Montgomery
+// product with H (Montgomery form) gives G canonical.
+//
+// The coefficients of round i+1 depend on alpha_i only through
+// C_{i+1} = C_i eq1(alpha_i, r_i) = P + alpha_i Q, P = C_i (1 - r_i),
+// Q = C_i (2 r_i - 1).  Everything except the final product with alpha_i is
+// computed by an otherwise idle wave while lane 0 runs the SHA-256
+// compression, so after the hash each coefficient costs one product:
+//   coef_{i+1}[x]  = U_x + mont(alpha_i, V_x),  U_x = P e_x,  V_x = (Q e_x) R,
+//   coefl_{i+1}[k] = Ul_k + mont(alpha_i, Vl_k),
+//   C_{i+1} R      = P R + mont(alpha_i, Q R^2),
+// with e_x = eq1(x, r_{i+1}) and alpha_i canonical (mont(a, bR) = ab).
+
+template <int D>
+struct FinLds {
+  static constexpr int NH = D + 1, NE = D + 2, NC = NE + NH;
+  static constexpr uint32_t LEN = 32u * (1u + NE);  // T_{i-1} || G_i(0..d+1)
+  static constexpr uint32_t NB = (LEN + 9u + 63u) / 64u;
+  uint32_t h[NH][NL];       // H_i(x), Montgomery, < p
+  uint32_t cf[NC][NL];      // coef_i[0..d+1], coefl_i[0..d], canonical
+  uint32_t term[NH][NL];    // coefl_i[k] H_i(k)
+  uint32_t u[NC][NL];       // U (canonical) for round i+1
+  uint32_t v[NC][NL];       // V (Montgomery) for round i+1
+  uint32_t pc[NL], q2[NL];  // P R and Q R^2
+  uint32_t cm[NL];          // C_i R; C_{i+1} R after emit_round
+  uint32_t am[NL];          // alpha_i R after emit_round
+  uint32_t ac[8];           // alpha_i canonical words
+  uint32_t msg[LEN / 4];
+  uint32_t dg[8];           // T_i
+  uint32_t kw[NB * 64];
+  uint32_t skip;
+};
+
+// Block state of round `round` from the control block: coefficients, C_i,
+// T_{i-1}.  All threads call it; ends with a barrier.
+template <int D>
+__device__ __forceinline__ void fin_load(const Ctrl* ctrl, FinLds<D>& S) {
+  constexpr int NE = D + 2, NC = FinLds<D>::NC;
+  const uint32_t t = threadIdx.x;
+  if (t < (uint32_t)NC) lds_put(S.cf[t], load_words_fe(t < (uint32_t)NE ? ctrl->coef[t] : ctrl->coefl[t - NE]));
+  if (t == (uint32_t)NC) lds_put(S.cm, load_words_fe(ctrl->c_m));
+  if (t >= 64 && t < 72) S.msg[t - 64] = ctrl->ts[t - 64];
+}
+
+// Emits G_round, derives alpha_round, and prepares the next round (see
+// above).  On entry S.h, S.cf, S.cm and S.msg[0..7] hold round `round`'s
+// state; on exit S.cf, S.cm hold round+1's (S.cm = C_{mu+1} R after the last
+// round, the opening of eq), S.am holds alpha_round R and S.msg[0..7] T_round.
+// The control block is updated the same way; its stores come after the last
+// barrier, so no barrier waits for them.  All threads of the block call it.
+template <int D>
+__device__ __forceinline__ void emit_round(Ctrl* ctrl, uint32_t round, uint32_t mu, FinLds<D>& S,
+                                           uint32_t* evals_out, uint32_t* alpha_out) {
+  constexpr int NH = D + 1, NE = D + 2, NC = FinLds<D>::NC;
+  constexpr uint32_t LEN = FinLds<D>::LEN, NB = FinLds<D>::NB;
+  static_assert(NH <= 16, "one 16-lane group");
+  constexpr Extrap<D> ex{};
+  const uint32_t t = threadIdx.x;
+  // lanes x <= d: G(x) = coef[x] H(x) and the term coefl[x] H(x) of G(d+1)
+  // = sum_x coefl[x] H(x), summed over the 16-lane group by shuffles
+  if (t < 16) {
+    Fe term = fe_zero();
+    if (t < (uint32_t)NH) {
+      const Fe h = lds_fe(S.h[t]);
+      const Fe g = mont(lds_fe(S.cf[t]), h);
+      term = mont(lds_fe(S.cf[NE + t]), h);
+      uint32_t w[8];
+      fe_to_words(g, w);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        S.msg[8 + t * 8 + k] = w[k];
+        evals_out[t * 8 + k] = w[k];
+      }
+    }
+#pragma unroll
+    for (int msk = 8; msk >= 1; msk >>= 1) term = fe_add(term, shfl_xor_fe(term, msk));  // < 16p
+    if (t == 0) {
+      uint32_t w[8];
+      fe_to_words(fe_reduce32(term), w);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        S.msg[8 + NH * 8 + k] = w[k];
+        evals_out[NH * 8 + k] = w[k];
+      }
     }
   }
   __syncthreads();
-  constexpr uint32_t LEN = 32u * (1u + NE);
-  __shared__ uint32_t kw[((LEN + 9u + 63u) / 64u) * 64u];
-  uint32_t dg[8];
-  sha256_fixed_block<LEN>(msg, kw, dg);
-  if (x == 0) {
-    // alpha_r = digest (little-endian 256-bit integer) mod p; digest < 2^256 < 6p
+  sha256_schedule_block<LEN>(S.msg, S.kw);
+  __syncthreads();
+  if (t == 0) {
+    uint32_t dg[8];
+    sha256_compress_blocks(S.kw, NB, dg);
+    // alpha = digest (little-endian 256-bit integer) mod p; digest < 2^256 < 6p
     Fe al = fe_from_words(dg);
     al = fe_csub(fe_csub(fe_csub(al, kP4), kP2), kP);
+    uint32_t w[8];
+    fe_to_words(al, w);
 #pragma unroll
-    for (int k = 0; k < 8; ++k) ctrl->ts[k] = dg[k];
-    store_words_fe(alpha_out, al);
-    const Fe am = fe_to_mont(al);
-    store_words_fe(ctrl->alpha_m[round - 1], am);
-    // C_{r+1} = C_r * eq1(alpha_r, r_r), Montgomery form
-    const Fe one = fe_const(kOne);
+    for (int k = 0; k < 8; ++k) {
+      S.dg[k] = dg[k];
+      S.ac[k] = w[k];
+    }
+  } else if (t >= 192 && t < 192 + (uint32_t)NC + 1) {
+    // next round's precomputation, overlapping the compression
+    const uint32_t l = t - 192;
+    const Fe one_m = fe_const(kOne);
+    const Fe cm = fe_vgpr(lds_fe(S.cm));
     const Fe rm = load_words_fe(ctrl->r_m[round - 1]);
-    const Fe e1 = fe_addmod(fe_submod(one, rm), fe_reduce2(fe_mul(am, fe_submod(fe_addmod(rm, rm), one))));
-    const Fe c = fe_reduce2(fe_mul(load_words_fe(ctrl->c_m), e1));
-    lds_put(cnext, c);
-    store_words_fe(ctrl->c_m, c);
-    ctrl->round_done = round;
+    const Fe P = mont(cm, fe_submod(one_m, rm));
+    const Fe Q = mont(cm, fe_submod(fe_addmod(rm, rm), one_m));
+    if (l == (uint32_t)NC) {
+      lds_put(S.pc, P);
+      lds_put(S.q2, fe_to_mont(Q));
+    } else if (round < mu) {
+      const Fe rn_c = load_words_fe(ctrl->r_c[round]);
+      const Fe rn_m = load_words_fe(ctrl->r_m[round]);
+      const uint32_t x = l < (uint32_t)NE ? l : (uint32_t)(D + 1);
+      Fe U = mont(P, eq1_small(rn_c, x, fe_one_plain()));
+      Fe V = mont(Q, eq1_small(rn_m, x, one_m));
+      if (l >= (uint32_t)NE) {
+        Fe lam = fe_zero();
+        auto pick = [&](auto k) __attribute__((always_inline)) {
+          if (l - NE == (uint32_t)k) lam = fe_const(ex.lam[k]);
+        };
+        Unroll<0, NH>::run(pick);
+        U = mont(U, lam);
+        V = mont(V, lam);
+      }
+      lds_put(S.u[l], U);
+      lds_put(S.v[l], V);
+    }
   }
   __syncthreads();
-  if (round < mu && x < (uint32_t)NE) {
-    // coef_{r+1}[x] = C_{r+1} * eq1(x, r_{r+1}), canonical
-    const Fe e1 = eq1_small(load_words_fe(ctrl->r_c[round]), x);
-    store_words_fe(ctrl->coef[x], fe_reduce2(fe_mul(lds_fe(cnext), e1)));
+  // one product per value with alpha (canonical): coefficients and C of the
+  // next round, alpha R; then T_round heads the next message
+  Fe out = fe_zero();
+  if (t < (uint32_t)NC + 2) {
+    uint32_t w[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) w[k] = S.ac[k];
+    const Fe ac = fe_vgpr(fe_from_words(w));
+    if (t < (uint32_t)NC) {
+      if (round < mu) {
+        out = fe_addmod(lds_fe(S.u[t]), mont(ac, lds_fe(S.v[t])));
+        lds_put(S.cf[t], out);
+      }
+    } else if (t == (uint32_t)NC) {
+      out = fe_addmod(lds_fe(S.pc), mont(ac, lds_fe(S.q2)));
+      lds_put(S.cm, out);
+    } else {
+      out = fe_to_mont(ac);
+      lds_put(S.am, out);
+    }
   }
+  if (t >= 64 && t < 72) S.msg[t - 64] = S.dg[t - 64];
   __syncthreads();
+  // control block and outputs
+  if (t < (uint32_t)NC) {
+    if (round < mu) store_words_fe(t < (uint32_t)NE ? ctrl->coef[t] : ctrl->coefl[t - NE], out);
+  } else if (t == (uint32_t)NC) {
+    store_words_fe(ctrl->c_m, out);
+  } else if (t == (uint32_t)NC + 1) {
+    store_words_fe(ctrl->alpha_m[round - 1], out);
+  } else if (t >= 64 && t < 72) {
+    ctrl->ts[t - 64] = S.dg[t - 64];
+    alpha_out[t - 64] = S.ac[t - 64];
+    if (t == 64) ctrl->round_done = round;
+  }
 }
 
 // ---- round kernel, one thread per pair ---------------------------------------------
@@ -533,57 +652,74 @@ __device__ __forceinline__ Fe group_reduce(Fe c) {
 }
 
 // The last rounds of a proof inside one block, with the tables in LDS.  On
-// entry round a.round has been finished (alpha_round derived) and the tables
-// at a.dst hold 2q live entries, q = a.q <= 2 kTailQ.  Runs rounds
-// a.round+1 .. mu (fold with the previous challenge, evaluate, finalize)
-// and the final fold, whose values are the openings; eq's opening is
-// C_{mu+1} = eq(alpha, r).
+// entry round a.round has been emitted (S holds round a.round+1's state and
+// alpha_{a.round}) and the tables at a.dst hold 2q live entries,
+// q = a.q <= 2 kTailQ.  Runs rounds a.round+1 .. mu (fold with the previous
+// challenge, evaluate, emit) and the final fold, whose values are the
+// openings; eq's opening is C_{mu+1}.
+//
+// Evaluation: point x of pair j is one thread's work (SL point slots, the
+// power of two >= d+1, times PP = kBlock / SL pairs per pass); the PP lanes
+// of a point are adjacent, so their sum is a shuffle reduction in one wave.
 template <class Gate>
-__device__ __forceinline__ void run_tail(const RoundArgs& a) {
+__device__ __forceinline__ void run_tail(const RoundArgs& a, FinLds<Gate::D>& S) {
   constexpr int K = Gate::K;
   constexpr int NH = Gate::NH;
-  extern __shared__ uint32_t tail_lds[];  // [K][4 kTailQ][NL]
+  constexpr uint32_t SL = NH <= 4 ? 4u : (NH <= 8 ? 8u : 16u);
+  constexpr uint32_t PP = kBlock / SL;
+  static_assert(PP <= 64 && SL * PP == kBlock, "point groups within a wave");
+  extern __shared__ uint32_t tail_lds[];  // [K][4 kTailQ][NL] tables, then [2 kTailQ][NL] eq rows
   constexpr uint32_t CAP = 4 * kTailQ;
   auto T = [&](int t, uint32_t e) -> uint32_t* { return tail_lds + ((uint32_t)t * CAP + e) * NL; };
+  uint32_t* eqrow = tail_lds + (uint32_t)K * CAP * NL;
   uint32_t L = 2 * (uint32_t)a.q;
   for (uint32_t idx = threadIdx.x; idx < K * L; idx += blockDim.x) {
     const uint32_t t = idx / L, e = idx % L;
     lds_put(T(t, e), load_el(a.dst.p[t], a.dst_pitch, e));
   }
+  // E_r[j] of every tail round r, heap-style: row 2^(mu-r) + j, rows [1, q)
+  for (uint32_t hrow = threadIdx.x; hrow < (uint32_t)a.q; hrow += blockDim.x) {
+    if (hrow == 0) continue;
+    const uint32_t lg = 31u - __builtin_clz(hrow);
+    lds_put(eqrow + hrow * NL, eq_factor(a.eq, a.mu - lg, hrow - (1u << lg)));
+  }
   __syncthreads();
-  const uint32_t g = threadIdx.x % kGroup, pl = threadIdx.x / kGroup;
+  const uint32_t x = threadIdx.x / PP, pp = threadIdx.x % PP;
   for (uint32_t r = a.round + 1; r <= a.mu + 1; ++r) {
     // fold with alpha_{r-1}: L -> L/2 entries
-    const Fe alpha = load_words_fe(a.ctrl->alpha_m[r - 2]);
+    const Fe alpha = fe_vgpr(lds_fe(S.am));
     const uint32_t h = L / 2;
     for (uint32_t idx = threadIdx.x; idx < K * h; idx += blockDim.x) {
       const uint32_t t = idx / h, e = idx % h;
       const Fe u0 = lds_fe(T(t, e)), u1 = lds_fe(T(t, e + h));
-      const Fe u = fe_addmod(u0, fe_reduce2(fe_mul(alpha, fe_submod(u1, u0))));
-      lds_put(T(t, e), u);
+      lds_put(T(t, e), fe_addmod(u0, mont(alpha, fe_submod(u1, u0))));
     }
     __syncthreads();
     L = h;
     if (r > a.mu) break;  // the final fold: entry 0 of each table is its opening
     const uint32_t q = L / 2;
     Fe c = fe_zero();
-    for (uint32_t base = 0; base < q; base += kSplitPairs) {
-      const uint32_t e = base + pl;
-      if (e < q && g < (uint32_t)NH) {
+    if (x < (uint32_t)NH) {
+      for (uint32_t e = pp; e < q; e += PP) {
+        // keeps the compiler from moving LDS reads across iterations, which
+        // made one pass several times slower
+        asm volatile("" ::: "memory");
         auto get = [&](int t, Fe& u0, Fe& u1) __attribute__((always_inline)) {
           u0 = lds_fe(T(t, e));
           u1 = lds_fe(T(t, e + q));
         };
-        const Fe E = eq_factor(a.eq, r, e);
-        c = fe_addmod(c, fe_reduce2(fe_mul(point_f<Gate>(get, g), E)));
+        c = fe_addmod(c, mont(point_f<Gate>(get, x), lds_fe(eqrow + (q + e) * NL)));
       }
     }
-    const Fe tot = group_reduce<NH>(c);
-    finalize_round<Gate::D>(a.ctrl, r, a.mu, tot, a.evals_out + (uint64_t)(r - a.round) * Gate::NE * 8,
-                            a.alpha_out + (uint64_t)(r - a.round) * 8);
+#pragma unroll
+    for (uint32_t msk = PP / 2; msk >= 1; msk >>= 1) c = fe_addmod(c, shfl_xor_fe(c, (int)msk));
+    if (pp == 0 && x < (uint32_t)NH) lds_put(S.h[x], c);
+    __syncthreads();
+    emit_round<Gate::D>(a.ctrl, r, a.mu, S, a.evals_out + (uint64_t)(r - a.round) * Gate::NE * 8,
+                        a.alpha_out + (uint64_t)(r - a.round) * 8);
   }
   if (threadIdx.x < K) store_words_fe(a.openings + threadIdx.x * 8, fe_from_mont(lds_fe(T(threadIdx.x, 0))));
-  if (threadIdx.x == K) store_words_fe(a.openings + K * 8, fe_from_mont(load_words_fe(a.ctrl->c_m)));
+  if (threadIdx.x == K) store_words_fe(a.openings + K * 8, fe_from_mont(fe_vgpr(lds_fe(S.cm))));
 }
 
 // Round with 16 lanes per pair; the grid strides over the pairs and is sized
@@ -646,26 +782,39 @@ __global__ __launch_bounds__(kBlock) void k_round_split(RoundArgs a) {
 
 // ---- end of a round: one block -------------------------------------------------------
 //
-// Adds up the round kernel's a.nparts partial sums (every thread takes a
-// strided share, then one block reduction), emits G_i, derives alpha_i and,
-// with a.tail, runs the rest of the proof in LDS (run_tail).  The challenge
-// never leaves the device.
+// Adds up the round kernel's a.nparts partial sums, emits G_i, derives
+// alpha_i and, with a.tail, runs the rest of the proof in LDS (run_tail).
+// The challenge never leaves the device.  Runs only when round i-1 has been
+// emitted (ZC_ESTATE otherwise).
 template <class Gate>
 __global__ __launch_bounds__(kBlock) void k_finish(RoundArgs a) {
   constexpr int NH = Gate::NH;
-  Fe v[NH];
-  auto z = [&](auto x) __attribute__((always_inline)) { v[x] = fe_zero(); };
-  Unroll<0, NH>::run(z);
-#pragma unroll 2
-  for (uint32_t b = threadIdx.x; b < a.nparts; b += blockDim.x) {
-    auto add = [&](auto x) __attribute__((always_inline)) {
-      v[x] = fe_addmod(v[x], load_words_fe(a.partials + ((uint64_t)b * NH + x) * 8));
-    };
-    Unroll<0, NH>::run(add);
+  __shared__ FinLds<Gate::D> S;
+  const uint32_t t = threadIdx.x;
+  if (t == 0) {
+    const bool ok = a.ctrl->round_done + 1 == a.round;
+    S.skip = ok ? 0u : 1u;
+    if (!ok) set_error(a.ctrl, -5);
   }
-  const Fe tot = block_reduce<NH>(v);
-  finalize_round<Gate::D>(a.ctrl, a.round, a.mu, tot, a.evals_out, a.alpha_out);
-  if (a.tail) run_tail<Gate>(a);
+  fin_load<Gate::D>(a.ctrl, S);
+  // point x = t / 16: its 16 lanes stride over the partials (each < p),
+  // lazily summed (at most kMaxBlocks / 16 = 128 terms, < 128 p), reduced,
+  // then combined across the group by shuffles
+  static_assert(NH * 16 <= kBlock, "16 lanes per point");
+  const uint32_t x = t >> 4, g = t & 15;
+  Fe v = fe_zero();
+  if (x < (uint32_t)NH) {
+#pragma unroll 4
+    for (uint32_t b = g; b < a.nparts; b += 16) v = fe_add(v, load_words_fe(a.partials + ((uint64_t)b * NH + x) * 8));
+    v = fe_reduce128(v);
+  }
+#pragma unroll
+  for (int msk = 8; msk >= 1; msk >>= 1) v = fe_add(v, shfl_xor_fe(v, msk));  // < 16 p
+  if (x < (uint32_t)NH && g == 0) lds_put(S.h[x], fe_reduce32(v));
+  __syncthreads();
+  if (S.skip) return;
+  emit_round<Gate::D>(a.ctrl, a.round, a.mu, S, a.evals_out, a.alpha_out);
+  if (a.tail) run_tail<Gate>(a, S);
 }
 
 }  // namespace zc

@@ -11,9 +11,21 @@ namespace zc {
 
 // ---- setup: r, the factored eq tables, round-1 coefficients -------------------------
 
+// lam_k = (-1)^(d-k) C(d+1, k) in Montgomery form (d <= 10): the weight of
+// H(k) in H(d+1) = sum_{k<=d} lam_k H(k), exact for H of degree <= d.
+__device__ __forceinline__ Fe lam_mont(uint32_t d, uint32_t k) {
+  uint32_t c = 1;  // C(d+1, k) <= 462
+  for (uint32_t t = 0; t < k; ++t) c = c * (d + 1 - t) / (t + 1);
+  Fe v = fe_zero();
+  v.l[0] = c;
+  v = fe_to_mont(v);
+  if ((d - k) & 1u) v = fe_submod(fe_zero(), v);
+  return v;
+}
+
 // One block: resets the control block, checks r, keeps it in canonical and
-// Montgomery form, sets C_1 = 1 and coef_1[x] = eq1(x, r_1) for x < ne, and
-// starts the transcript:
+// Montgomery form, sets C_1 = 1, coef_1[x] = eq1(x, r_1) for x < ne and
+// coefl_1, and starts the transcript:
 // T_0 = SHA-256("ZCv1" || u32 mu || u32 gate || u32 m || enc(r_1) .. enc(r_mu)).
 __global__ __launch_bounds__(64) void k_setup(const uint32_t* __restrict__ r, uint32_t mu, uint32_t gate,
                                               uint32_t m, uint32_t ne, Ctrl* ctrl) {
@@ -40,8 +52,9 @@ __global__ __launch_bounds__(64) void k_setup(const uint32_t* __restrict__ r, ui
     if (!words_lt_p(w)) set_error(ctrl, -4);
     store_words_fe(ctrl->r_m[i], fe_to_mont(fe_from_words(w)));
   }
-  if (threadIdx.x < ne) {
-    // coef_1[x] = C_1 eq1(x, r_1) = (1 - r_1) + x (2 r_1 - 1), canonical
+  if (threadIdx.x < 2 * ne - 1) {
+    // coef_1[x] = C_1 eq1(x, r_1) = (1 - r_1) + x (2 r_1 - 1) (x < ne), and
+    // coefl_1[k] = coef_1[d+1] lam_k (k <= d), canonical
     uint32_t w[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) w[k] = r[k];
@@ -49,9 +62,15 @@ __global__ __launch_bounds__(64) void k_setup(const uint32_t* __restrict__ r, ui
     if (!words_lt_p(w)) rc = fe_zero();  // flagged above; keep the arithmetic in range
     Fe one = fe_zero();
     one.l[0] = 1;
+    const uint32_t x = threadIdx.x < ne ? threadIdx.x : ne - 1;
     const Fe step = fe_submod(fe_addmod(rc, rc), one);
-    const Fe e = fe_addmod(fe_submod(one, rc), fe_reduce32(fe_mul_small(step, threadIdx.x)));
-    store_words_fe(ctrl->coef[threadIdx.x], e);
+    Fe e = fe_addmod(fe_submod(one, rc), fe_reduce32(fe_mul_small(step, x)));
+    if (threadIdx.x < ne) {
+      store_words_fe(ctrl->coef[threadIdx.x], e);
+    } else {
+      const uint32_t d = ne - 2, k = threadIdx.x - ne;
+      store_words_fe(ctrl->coefl[k], fe_reduce2(fe_mul(e, lam_mont(d, k))));
+    }
   }
   __syncthreads();
   if (threadIdx.x == 0) {
