@@ -96,10 +96,12 @@ def run_workload(name, steps, warmup, cpu_baseline):
     if err != 0:
         raise RuntimeError(f"device error {err}")
 
-    # per-launch durations of the round kernels, from the events.  The dominant
-    # kernel is the fused fold+evaluate round with one thread per pair
-    # (kind 0, rounds >= 2); the lane-split rounds and the tail are reported
-    # separately.
+    # per-launch durations of the round kernels (finishers excluded), from the
+    # events.  The dominant kernel is the fused fold+evaluate round with one
+    # thread per pair (kind 0, rounds >= 2); round 1 and the lane-split rounds
+    # are reported separately, and the rest of a proof (setup, the one-block
+    # finishers with their SHA-256 and the tail) is what round_kernels_share
+    # leaves.
     kinds = [zc.lib().zc_prove_round_kernel(mu, i) for i in range(1, mu + 1)]
     fused_t, fused_b, fused_p, first_t, split_t = 0.0, 0, 0, 0.0, 0.0
     launches = 0
@@ -139,7 +141,7 @@ def run_workload(name, steps, warmup, cpu_baseline):
         "roofline": bound,
         "roofline_other": other,
         "round1_avg_us": round(first_t / steps * 1e6, 2),
-        "split_and_tail_avg_us": round(split_t / steps * 1e6, 2),
+        "split_rounds_us": round(split_t / steps * 1e6, 2),
         "round_kernels_share": round((fused_t + first_t + split_t) / elapsed, 4),
         "config": {"workload": name, "mu": mu, "gate": "vanilla" if gate == 0 else f"prod{m}",
                    "degree": d, "tables": k, "field": "BN254 Fr", "seed": cfg["seed"]},
@@ -177,6 +179,9 @@ def main():
     ap.add_argument("--workload", default="plain20_d3")
     ap.add_argument("--secondary", default="plain20_d9", help="second workload ('' to skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run a plain device copy of MIB MiB three times (the known-size "
+                         "kernel against which profiler byte counters are scaled)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the prover runs on a single MI355X; "
@@ -189,6 +194,16 @@ def main():
         sys.exit(1)
     from paper_2606_16146_amd import zc
     zc.lib()  # fail loudly if the HIP library is missing
+
+    if args.copy_calibration > 0:
+        n = args.copy_calibration << 18  # int32 elements
+        src = torch.ones(n, dtype=torch.int32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: 3 x {args.copy_calibration} MiB device copies")
+        del src, dst
 
     main_res = run_workload(args.workload, args.steps, args.warmup, not args.no_cpu_baseline)
     out = {
@@ -208,7 +223,7 @@ def main():
         "roofline": main_res["roofline"],
         "roofline_other": main_res["roofline_other"],
     }
-    for key in ("cpu_baseline", "parity_vs_oracle", "round1_avg_us", "split_and_tail_avg_us",
+    for key in ("cpu_baseline", "parity_vs_oracle", "round1_avg_us", "split_rounds_us",
                 "round_kernels_share"):
         if key in main_res:
             out[key] = main_res[key]

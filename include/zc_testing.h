@@ -35,17 +35,19 @@ typedef enum {
 int zc_test_field(int op, const uint32_t* a, const uint32_t* b, uint32_t* out, uint64_t n, hipStream_t stream);
 
 /* zc_prove (same launches, same outputs) with a HIP event recorded on
-   `stream` right before and right after the round kernel of every round:
-   events is a host array of 2*mu hipEvent_t, round i bracketed by
-   events[2(i-1)] and events[2(i-1)+1].  For measuring the round kernels. */
+   `stream` right before and right after the round kernel of every round
+   (the one-block finisher that follows it is outside the bracket): events is
+   a host array of 2*mu hipEvent_t, round i bracketed by events[2(i-1)] and
+   events[2(i-1)+1]; rounds run inside the tail get two back-to-back events.
+   For measuring the round kernels. */
 int zc_prove_profiled(const zc_shape* shape, const uint32_t* const* tables, const uint32_t* r, void* ws,
                       uint32_t* round_evals, uint32_t* challenges, uint32_t* openings, void* events,
                       hipStream_t stream);
 
 /* Which kernel zc_prove uses for round i of a mu-variable proof:
    0 one thread per pair, 1 sixteen lanes per pair, 2 sixteen lanes per pair
-   whose last block then runs all later rounds and the openings, 3 a round run
-   inside such a tail.  Negative zc_status for bad arguments. */
+   whose finisher then runs all later rounds and the openings in one block,
+   3 a round run inside such a tail.  Negative zc_status for bad arguments. */
 int zc_prove_round_kernel(uint32_t mu, uint32_t i);
 
 /* SHA-256 of len bytes (msg: little-endian packed uint32 words); out: 32 bytes as uint32[8]. */

@@ -68,17 +68,18 @@ inline int launch_ok() { return hipGetLastError() == hipSuccess ? ZC_OK : ZC_EHI
 inline Ctrl* ctrl_of(void* ws) { return reinterpret_cast<Ctrl*>(ws); }
 inline uint8_t* bytes(void* ws) { return reinterpret_cast<uint8_t*>(ws); }
 
-int dispatch_round(const zc_shape* s, bool fold, RoundKind kind, const RoundArgs& a, hipStream_t st) {
-  if (s->gate == ZC_GATE_VANILLA) return launch_round_vanilla(fold, kind, a, st);
+int dispatch_round(const zc_shape* s, bool fold, RoundKind kind, const RoundArgs& a, hipStream_t st,
+                   hipEvent_t after = nullptr) {
+  if (s->gate == ZC_GATE_VANILLA) return launch_round_vanilla(fold, kind, a, st, after);
   switch (s->m) {
-    case 1: return launch_round_prod1(fold, kind, a, st);
-    case 2: return launch_round_prod2(fold, kind, a, st);
-    case 3: return launch_round_prod3(fold, kind, a, st);
-    case 4: return launch_round_prod4(fold, kind, a, st);
-    case 5: return launch_round_prod5(fold, kind, a, st);
-    case 6: return launch_round_prod6(fold, kind, a, st);
-    case 7: return launch_round_prod7(fold, kind, a, st);
-    case 8: return launch_round_prod8(fold, kind, a, st);
+    case 1: return launch_round_prod1(fold, kind, a, st, after);
+    case 2: return launch_round_prod2(fold, kind, a, st, after);
+    case 3: return launch_round_prod3(fold, kind, a, st, after);
+    case 4: return launch_round_prod4(fold, kind, a, st, after);
+    case 5: return launch_round_prod5(fold, kind, a, st, after);
+    case 6: return launch_round_prod6(fold, kind, a, st, after);
+    case 7: return launch_round_prod7(fold, kind, a, st, after);
+    case 8: return launch_round_prod8(fold, kind, a, st, after);
     default: return ZC_EUNSUPPORTED;
   }
 }
@@ -124,8 +125,8 @@ int check_tables(const Layout& L, const uint32_t* const* tables) {
   return ZC_OK;
 }
 
-// Whole proof.  With `ev` (2*mu events) the round kernel of round i is
-// bracketed by ev[2(i-1)] and ev[2(i-1)+1] on the same stream.
+// Whole proof.  With `ev` (2*mu events) the round kernel of round i (not its
+// finisher) is bracketed by ev[2(i-1)] and ev[2(i-1)+1] on the same stream.
 int prove_impl(const zc_shape* shape, const uint32_t* const* tables, const uint32_t* r, void* ws,
                uint32_t* round_evals, uint32_t* challenges, uint32_t* openings, hipStream_t stream,
                hipEvent_t* ev) {
@@ -166,8 +167,7 @@ int prove_impl(const zc_shape* shape, const uint32_t* const* tables, const uint3
       a.dst_pitch = half;
     }
     if (ev && hipEventRecord(ev[2 * (i - 1)], stream) != hipSuccess) return ZC_EHIP;
-    if ((rc = dispatch_round(shape, i > 1, kind, a, stream)) != ZC_OK) return rc;
-    if (ev && hipEventRecord(ev[2 * (i - 1) + 1], stream) != hipSuccess) return ZC_EHIP;
+    if ((rc = dispatch_round(shape, i > 1, kind, a, stream, ev ? ev[2 * (i - 1) + 1] : nullptr)) != ZC_OK) return rc;
   }
   return ZC_OK;
 }

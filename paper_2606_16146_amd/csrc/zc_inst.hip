@@ -50,7 +50,7 @@ inline uint32_t round_grid(uint64_t blocks_for_work, int per_cu, int* rc) {
 // k_finish (one block: sums, G_i, alpha_i, and with kSplitTail the rest of
 // the proof).
 template <class Gate>
-int launch_round(bool fold, RoundKind kind, RoundArgs a, hipStream_t st) {
+int launch_round(bool fold, RoundKind kind, RoundArgs a, hipStream_t st, hipEvent_t after) {
   int rc = 0;
   uint32_t blocks;
   if (kind == kPerPair) {
@@ -77,6 +77,7 @@ int launch_round(bool fold, RoundKind kind, RoundArgs a, hipStream_t st) {
       hipLaunchKernelGGL((k_round_split<Gate, false>), dim3(blocks), dim3(kBlock), 0, st, a);
   }
   if ((rc = launch_ok()) != 0) return rc;
+  if (after && hipEventRecord(after, st) != hipSuccess) return -3;
   a.nparts = blocks;
   a.tail = (kind == kSplitTail) ? 1u : 0u;
   const size_t lds = a.tail ? tail_lds_bytes<Gate>() : 0;
@@ -87,14 +88,15 @@ int launch_round(bool fold, RoundKind kind, RoundArgs a, hipStream_t st) {
 }  // namespace
 
 #if defined(ZC_INST_VANILLA)
-int launch_round_vanilla(bool fold, RoundKind kind, const RoundArgs& a, hipStream_t st) {
-  return launch_round<GateVanilla>(fold, kind, a, st);
+int launch_round_vanilla(bool fold, RoundKind kind, const RoundArgs& a, hipStream_t st, hipEvent_t after) {
+  return launch_round<GateVanilla>(fold, kind, a, st, after);
 }
 #elif defined(ZC_INST_PROD)
 #define ZC_CAT2(a, b) a##b
 #define ZC_CAT(a, b) ZC_CAT2(a, b)
-int ZC_CAT(launch_round_prod, ZC_INST_PROD)(bool fold, RoundKind kind, const RoundArgs& a, hipStream_t st) {
-  return launch_round<GateProd<ZC_INST_PROD>>(fold, kind, a, st);
+int ZC_CAT(launch_round_prod, ZC_INST_PROD)(bool fold, RoundKind kind, const RoundArgs& a, hipStream_t st,
+                                            hipEvent_t after) {
+  return launch_round<GateProd<ZC_INST_PROD>>(fold, kind, a, st, after);
 }
 #else
 #error "build zc_inst.hip with -DZC_INST_VANILLA or -DZC_INST_PROD=<m>"

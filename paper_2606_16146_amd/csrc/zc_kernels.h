@@ -125,6 +125,49 @@ __device__ __forceinline__ Fe eq_factor(const EqTabs& E, uint32_t round, uint32_
   return load_row(E.suf, (1u << (E.mu - round)) + j);
 }
 
+// ---- where a gate reads its pairs -------------------------------------------------
+//
+// A gate asks for the pair (t[j], t[j+q]) of table t in two steps: issue(t)
+// starts the loads, get() turns them into (lo, dl) = (t[j], t[j+q] - t[j]),
+// so that the loads of the next table are in flight meanwhile.
+
+// Tables already holding the round's 2q live entries.
+struct PairSrc {
+  const TabPtrs& tp;
+  uint64_t pitch;
+  uint32_t j, q;
+  using Raw = RawPair;
+  __device__ __forceinline__ Raw issue(int t) const { return issue_pair(tp.p[t], pitch, j, q); }
+  __device__ __forceinline__ void get(const Raw& r, int, Fe& lo, Fe& dl) const { cvt_pair(r, lo, dl); }
+};
+
+// Tables holding 4q entries, folded on the way with alpha_{i-1}:
+// u[j] = t[j] + alpha (t[j+2q] - t[j]), u[j+q] likewise; u is written to the
+// destination tables (the next round reads it) and used from registers.
+struct FoldSrc {
+  const TabPtrs& src;
+  const TabPtrs& dst;
+  uint64_t sp, dp;
+  uint32_t j, q;
+  Fe alpha;
+  struct Raw {
+    RawPair lo2, hi2;  // (t[j], t[j+q]), (t[j+2q], t[j+3q])
+  };
+  __device__ __forceinline__ Raw issue(int t) const {
+    return Raw{issue_pair(src.p[t], sp, j, q), issue_pair(src.p[t], sp, j + 2 * q, q)};
+  }
+  __device__ __forceinline__ void get(const Raw& r, int t, Fe& lo, Fe& dl) const {
+    const Fe a0 = fe_from_words(r.lo2.w0), a1 = fe_from_words(r.lo2.w1);
+    const Fe a2 = fe_from_words(r.hi2.w0), a3 = fe_from_words(r.hi2.w1);
+    const Fe u0 = fe_addmod(a0, fe_reduce2(fe_mul(alpha, fe_submod(a2, a0))));
+    const Fe u1 = fe_addmod(a1, fe_reduce2(fe_mul(alpha, fe_submod(a3, a1))));
+    store_el(dst.p[t], dp, j, u0);
+    store_el(dst.p[t], dp, j + q, u1);
+    lo = u0;
+    dl = fe_submod(u1, u0);
+  }
+};
+
 // ---- gates ---------------------------------------------------------------------
 //
 // eval() adds E * f_M(ext(X)) for X = 0..NH-1 (NH = d+1) of one pair to
@@ -149,44 +192,44 @@ struct GateVanilla {
     const Fe t5 = fe_mul(e[6], e[2]);                 // qO*c < 2p
     return fe_add(fe_add(fe_add(t3, t4), t5), e[7]);  // < 11p
   }
-  __device__ static __forceinline__ void eval(const TabPtrs& tp, uint64_t pitch, uint32_t j, uint32_t q,
-                                              const EqRows& er, Fe (&acc)[NH]) {
+  template <class Src>
+  __device__ static __forceinline__ void eval(const Src& src, const EqRows& er, Fe (&acc)[NH]) {
     // extensions at X <= 3 are < 4p
     Fe bx[NH], t[NH], lo, dl, e;
-    RawPair ra = issue_pair(tp.p[1], pitch, j, q);  // b
-    RawPair rb = issue_pair(tp.p[3], pitch, j, q);  // qM
-    cvt_pair(ra, lo, dl);
-    ra = issue_pair(tp.p[4], pitch, j, q);  // qL
+    typename Src::Raw ra = src.issue(1);  // b
+    typename Src::Raw rb = src.issue(3);  // qM
+    src.get(ra, 1, lo, dl);
+    ra = src.issue(4);  // qL
     auto fb = [&](auto x) __attribute__((always_inline)) {
       bx[x] = (x == 0) ? lo : fe_add(bx[x > 0 ? x - 1 : 0], dl);
     };
     Unroll<0, NH>::run(fb);
-    cvt_pair(rb, lo, dl);  // qM
-    rb = issue_pair(tp.p[0], pitch, j, q);  // a
+    src.get(rb, 3, lo, dl);  // qM
+    rb = src.issue(0);  // a
     e = lo;
     auto f1 = [&](auto x) __attribute__((always_inline)) {
       t[x] = fe_mul(e, bx[x]);  // < 2p
       e = fe_add(e, dl);
     };
     Unroll<0, NH>::run(f1);
-    cvt_pair(ra, lo, dl);  // qL
-    ra = issue_pair(tp.p[5], pitch, j, q);  // qR
+    src.get(ra, 4, lo, dl);  // qL
+    ra = src.issue(5);  // qR
     e = lo;
     auto f2 = [&](auto x) __attribute__((always_inline)) {
       t[x] = fe_add(t[x], e);  // < 6p
       e = fe_add(e, dl);
     };
     Unroll<0, NH>::run(f2);
-    cvt_pair(rb, lo, dl);  // a
-    rb = issue_pair(tp.p[6], pitch, j, q);  // qO
+    src.get(rb, 0, lo, dl);  // a
+    rb = src.issue(6);  // qO
     e = lo;
     auto f3 = [&](auto x) __attribute__((always_inline)) {
       t[x] = fe_mul(e, t[x]);  // < 2p (4*6)
       e = fe_add(e, dl);
     };
     Unroll<0, NH>::run(f3);
-    cvt_pair(ra, lo, dl);  // qR
-    ra = issue_pair(tp.p[2], pitch, j, q);  // c
+    src.get(ra, 5, lo, dl);  // qR
+    ra = src.issue(2);  // c
     e = lo;
     auto f4 = [&](auto x) __attribute__((always_inline)) {
       t[x] = fe_add(t[x], fe_mul(e, bx[x]));  // < 4p
@@ -194,9 +237,9 @@ struct GateVanilla {
     };
     Unroll<0, NH>::run(f4);
     Fe lo2, dl2, e2;
-    cvt_pair(rb, lo, dl);    // qO
-    cvt_pair(ra, lo2, dl2);  // c
-    rb = issue_pair(tp.p[7], pitch, j, q);  // qC
+    src.get(rb, 6, lo, dl);    // qO
+    src.get(ra, 2, lo2, dl2);  // c
+    rb = src.issue(7);  // qC
     e = lo;
     e2 = lo2;
     auto f5 = [&](auto x) __attribute__((always_inline)) {
@@ -205,7 +248,7 @@ struct GateVanilla {
       e2 = fe_add(e2, dl2);
     };
     Unroll<0, NH>::run(f5);
-    cvt_pair(rb, lo, dl);  // qC
+    src.get(rb, 7, lo, dl);  // qC
     const Fe E = resolve_eq(er);
     e = lo;
     auto f6 = [&](auto x) __attribute__((always_inline)) {
@@ -231,13 +274,13 @@ struct GateProd {
     Unroll<2, M + 1>::run(f);
     return fe_csub(fe_sub_plus(prod, e[M + 1], kP11), kP8);
   }
-  __device__ static __forceinline__ void eval(const TabPtrs& tp, uint64_t pitch, uint32_t j, uint32_t q,
-                                              const EqRows& er, Fe (&acc)[NH]) {
+  template <class Src>
+  __device__ static __forceinline__ void eval(const Src& src, const EqRows& er, Fe (&acc)[NH]) {
     // extensions at X <= m+1 are < (m+2) p <= 10 p
     Fe pr[NH], lo, dl, e;
-    RawPair cur = issue_pair(tp.p[0], pitch, j, q);  // s
-    RawPair nxt = issue_pair(tp.p[1], pitch, j, q);  // w1
-    cvt_pair(cur, lo, dl);
+    typename Src::Raw cur = src.issue(0);  // s
+    typename Src::Raw nxt = src.issue(1);  // w1
+    src.get(cur, 0, lo, dl);
     auto f0 = [&](auto x) __attribute__((always_inline)) {
       pr[x] = (x == 0) ? lo : fe_add(pr[x > 0 ? x - 1 : 0], dl);
     };
@@ -245,8 +288,8 @@ struct GateProd {
 #pragma unroll 1
     for (int k = 1; k <= M; ++k) {  // pr *= w_k  (< 2p after each product: 10*10, then 2*10)
       cur = nxt;
-      nxt = issue_pair(tp.p[k + 1], pitch, j, q);  // w_{k+1}, or o after the last w
-      cvt_pair(cur, lo, dl);
+      nxt = src.issue(k + 1);  // w_{k+1}, or o after the last w
+      src.get(cur, k, lo, dl);
       e = lo;
       auto fk = [&](auto x) __attribute__((always_inline)) {
         pr[x] = fe_mul(pr[x], e);
@@ -254,7 +297,7 @@ struct GateProd {
       };
       Unroll<0, NH>::run(fk);
     }
-    cvt_pair(nxt, lo, dl);  // o: pr + 11p - o in (0, 13p) -> < 8p
+    src.get(nxt, M + 1, lo, dl);  // o: pr + 11p - o in (0, 13p) -> < 8p
     const Fe E = resolve_eq(er);
     e = lo;
     auto fo = [&](auto x) __attribute__((always_inline)) {
@@ -564,7 +607,6 @@ __device__ __forceinline__ void emit_round(Ctrl* ctrl, uint32_t round, uint32_t 
 // microseconds).
 template <class Gate, bool FOLD>
 __global__ __launch_bounds__(kBlock) void k_round(RoundArgs a) {
-  constexpr int K = Gate::K;
   constexpr int NH = Gate::NH;
   Fe acc[NH];
   auto z = [&](auto x) __attribute__((always_inline)) { acc[x] = fe_zero(); };
@@ -577,28 +619,10 @@ __global__ __launch_bounds__(kBlock) void k_round(RoundArgs a) {
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < q; j += stride) {
       const EqRows er = issue_eq(a.eq, a.round, j);
-      if (FOLD) {
-        const uint64_t sp = a.src_pitch, dp = a.dst_pitch;
-        // fold table t while the four entries of table t+1 are loading
-        RawPair n01 = issue_pair(a.src.p[0], sp, j, q), n23 = issue_pair(a.src.p[0], sp, j + 2 * q, q);
-#pragma unroll 1
-        for (int t = 0; t < K; ++t) {
-          const RawPair c01 = n01, c23 = n23;
-          if (t + 1 < K) {
-            n01 = issue_pair(a.src.p[t + 1], sp, j, q);
-            n23 = issue_pair(a.src.p[t + 1], sp, j + 2 * q, q);
-          }
-          const Fe a0 = fe_from_words(c01.w0), a1 = fe_from_words(c01.w1);
-          const Fe a2 = fe_from_words(c23.w0), a3 = fe_from_words(c23.w1);
-          const Fe u0 = fe_addmod(a0, fe_reduce2(fe_mul(alpha, fe_submod(a2, a0))));
-          const Fe u1 = fe_addmod(a1, fe_reduce2(fe_mul(alpha, fe_submod(a3, a1))));
-          store_el(a.dst.p[t], dp, j, u0);
-          store_el(a.dst.p[t], dp, j + q, u1);
-        }
-        Gate::eval(a.dst, dp, j, q, er, acc);
-      } else {
-        Gate::eval(a.src, a.src_pitch, j, q, er, acc);
-      }
+      if (FOLD)
+        Gate::eval(FoldSrc{a.src, a.dst, a.src_pitch, a.dst_pitch, j, q, alpha}, er, acc);
+      else
+        Gate::eval(PairSrc{a.src, a.src_pitch, j, q}, er, acc);
     }
   }
   auto red = [&](auto x) __attribute__((always_inline)) { acc[x] = fe_reduce2(acc[x]); };

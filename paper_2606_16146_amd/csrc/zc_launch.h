@@ -32,9 +32,12 @@ inline RoundKind prove_round_kind(uint32_t mu, uint32_t i) {
   return (i == 1 || prev_q > first_tail_q) ? kSplitTail : kInTail;
 }
 
-// One launcher per gate instantiation (defined in zc_inst.hip).
-int launch_round_vanilla(bool fold, RoundKind kind, const RoundArgs& a, hipStream_t st);
-#define ZC_DECL_PROD(M) int launch_round_prod##M(bool fold, RoundKind kind, const RoundArgs& a, hipStream_t st);
+// One launcher per gate instantiation (defined in zc_inst.hip).  `after`, if
+// not null, is recorded on the stream between the round kernel and its
+// finisher (profiling).
+int launch_round_vanilla(bool fold, RoundKind kind, const RoundArgs& a, hipStream_t st, hipEvent_t after);
+#define ZC_DECL_PROD(M) \
+  int launch_round_prod##M(bool fold, RoundKind kind, const RoundArgs& a, hipStream_t st, hipEvent_t after);
 ZC_DECL_PROD(1)
 ZC_DECL_PROD(2)
 ZC_DECL_PROD(3)
