@@ -36,6 +36,31 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 MAD_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 MADS_PER_MUL = 162  # radix-2^29 Montgomery product: 81 a_i*b_j + 81 m_i*p_j
 
+# HBM bytes per launch of the dominant kernel from the PMC byte counters
+# (FETCH_SIZE and WRITE_SIZE, each scaled by what it reads for a 512 MiB copy),
+# averaged over its launches like `achieved`; see
+# profiles/k_round_fused_hbm_traffic.md.  Valid only for the kernel sources
+# they were taken on (fingerprint below); otherwise traffic is reported null.
+MEASURED_TRAFFIC = {
+    "fingerprint": "9b4e5fddf7cbe063",
+    "plain20_d3": 192641749,
+    "plain20_d9": 238647130,
+}
+
+
+def kernel_fingerprint():
+    """Short hash of the HIP sources the measured traffic belongs to."""
+    import hashlib
+
+    d = os.path.join(HERE, "paper_2606_16146_amd", "csrc")
+    h = hashlib.sha256()
+    for n in sorted(os.listdir(d)):
+        if n.endswith((".h", ".hip")):
+            h.update(n.encode())
+            with open(os.path.join(d, n), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()[:16]
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -122,11 +147,15 @@ def run_workload(name, steps, warmup, cpu_baseline):
     avg_launch_s = fused_t / launches
     gbs = fused_b / fused_t / 1e9
     tops = fused_p * MADS_PER_MUL / fused_t / 1e12
+    traffic = None
+    if MEASURED_TRAFFIC.get(name) and kernel_fingerprint() == MEASURED_TRAFFIC["fingerprint"]:
+        traffic = MEASURED_TRAFFIC[name]
     hbm = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None}
+           "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic}
     alu = {"bound": "alu", "achieved": round(tops, 2), "peak": round(MAD_PEAK_TOPS, 2),
-           "unit": "TOP/s (v_mad_u64_u32)", "frac": round(tops / MAD_PEAK_TOPS, 4), "traffic": None}
+           "unit": "TOP/s (v_mad_u64_u32)", "frac": round(tops / MAD_PEAK_TOPS, 4), "traffic": traffic}
     common = {"kernel": f"k_round<{'GateVanilla' if gate == 0 else f'GateProd<{m}>'}, true>",
+              "traffic_unit": "HBM bytes per launch (PMC, copy-calibrated)",
               "launches": launches, "avg_launch_us": round(avg_launch_s * 1e6, 2),
               "algorithmic_bytes_per_launch": fused_b // launches,
               "algorithmic_mads_per_launch": fused_p * MADS_PER_MUL // launches}
@@ -162,8 +191,9 @@ def run_workload(name, steps, warmup, cpu_baseline):
                     and (outs[2].cpu().numpy() == ora["openings"]).all())
         res["cpu_baseline"] = {"value": points / tmed, "unit": "points/s", "cores": C.max_threads(),
                                "kind": "oracle",
-                               "sample": f"C oracle (OpenMP), whole {name} proof, median of 3 runs "
-                                         f"({tmed:.2f} s each)"}
+                               "sample": f"C oracle (OpenMP), whole {name} proof on the same inputs, "
+                                         f"median of 3 runs ({tmed:.2f} s each, about "
+                                         f"{3 * tmed * C.max_threads():.0f} core-seconds in all)"}
         res["parity_vs_oracle"] = "bit-exact" if same else "MISMATCH"
         log(f"[bench] {name}: C oracle {tmed:.2f}s on {C.max_threads()} threads, parity={same}")
         if not same:
@@ -196,14 +226,18 @@ def main():
     zc.lib()  # fail loudly if the HIP library is missing
 
     if args.copy_calibration > 0:
+        # the source is written first and then pushed out of the caches by an
+        # unrelated 2 GiB fill, so each copy reads it from HBM
         n = args.copy_calibration << 18  # int32 elements
         src = torch.ones(n, dtype=torch.int32, device="cuda:0")
         dst = torch.empty_like(src)
+        flush = torch.empty(1 << 29, dtype=torch.int32, device="cuda:0")
         for _ in range(3):
+            flush.fill_(0)
             dst.copy_(src)
         torch.cuda.synchronize()
         log(f"[bench] copy calibration: 3 x {args.copy_calibration} MiB device copies")
-        del src, dst
+        del src, dst, flush
 
     main_res = run_workload(args.workload, args.steps, args.warmup, not args.no_cpu_baseline)
     out = {
