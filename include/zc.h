@@ -120,6 +120,46 @@ int zc_round(const zc_shape* shape, const uint32_t* const* tables, const uint32_
    each table is its opening (read it with zc_unpack, pitch 2^mu). */
 int zc_fold(const zc_shape* shape, uint32_t* const* tables, void* ws, uint32_t i, hipStream_t stream);
 
+/* ---- batches (many independent instances, one lockstep launch sequence) ----
+
+   Each instance is a whole proof exactly as zc_prove would make it (same
+   arguments, its own workspace of zc_workspace_bytes(&shape) bytes, same
+   output bytes).  The instances may differ in mu and gate.  They advance
+   round by round together: one round kernel per gate and step for all the
+   instances of that gate, then one finisher block per instance, so that the
+   per-round serial work of the instances (sum of partials, SHA-256,
+   challenge) overlaps.  tile = pairs per thread in the round kernels (0
+   means 4); it changes the launch shapes, not the bytes. */
+typedef struct {
+  zc_shape shape;
+  const uint32_t* const* tables; /* host array of k device pointers, read only */
+  const uint32_t* r;             /* device, mu x 8 canonical */
+  void* ws;                      /* device, zc_workspace_bytes(&shape), 256-byte aligned */
+  uint32_t* round_evals;         /* device outputs, as zc_prove */
+  uint32_t* challenges;
+  uint32_t* openings;
+  uint32_t tile;
+} zc_instance;
+
+/* Bytes of device batch workspace (instance descriptors and launch
+   schedule) for n instances, 1 <= n <= 65536; 0 if n is out of range. */
+size_t zc_batch_workspace_bytes(uint32_t n);
+
+/* Writes the descriptors and schedule of the n instances (host array) into
+   batch_ws and synchronizes `stream`.  Checks every instance like zc_prove
+   (negative zc_status, nothing written, on the first bad one). */
+int zc_batch_upload(uint32_t n, const zc_instance* inst, void* batch_ws, hipStream_t stream);
+
+/* Enqueues the batched proof of the n instances last uploaded to batch_ws
+   (pass the same host array).  Only kernel launches: the sequence may be
+   captured into a HIP graph and replayed while the instances' inputs stay
+   where they are.  Device-detected conditions land in each instance's
+   workspace (zc_read_error). */
+int zc_batch_launch(uint32_t n, const zc_instance* inst, void* batch_ws, hipStream_t stream);
+
+/* zc_batch_upload followed by zc_batch_launch. */
+int zc_batch_prove(uint32_t n, const zc_instance* inst, void* batch_ws, hipStream_t stream);
+
 /* Synchronizes `stream` and returns the first device-detected error stored in
    ws (ZC_OK if none), or ZC_EHIP if the synchronization fails.  The error word
    is cleared when zc_prove or zc_round(1) starts; a workspace that has run

@@ -2,8 +2,10 @@
 // workspace layout and the launch sequence of a proof.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 #include "../../include/zc.h"
 #include "../../include/zc_testing.h"
@@ -68,18 +70,18 @@ inline int launch_ok() { return hipGetLastError() == hipSuccess ? ZC_OK : ZC_EHI
 inline Ctrl* ctrl_of(void* ws) { return reinterpret_cast<Ctrl*>(ws); }
 inline uint8_t* bytes(void* ws) { return reinterpret_cast<uint8_t*>(ws); }
 
-int dispatch_round(const zc_shape* s, bool fold, RoundKind kind, const RoundArgs& a, hipStream_t st,
-                   hipEvent_t after = nullptr) {
-  if (s->gate == ZC_GATE_VANILLA) return launch_round_vanilla(fold, kind, a, st, after);
+int dispatch_round(const zc_shape* s, bool fold, RoundKind kind, const RoundArgs& a, const TabPtrs& src,
+                   const TabPtrs& dst, hipStream_t st, hipEvent_t after = nullptr) {
+  if (s->gate == ZC_GATE_VANILLA) return launch_round_vanilla(fold, kind, a, src, dst, st, after);
   switch (s->m) {
-    case 1: return launch_round_prod1(fold, kind, a, st, after);
-    case 2: return launch_round_prod2(fold, kind, a, st, after);
-    case 3: return launch_round_prod3(fold, kind, a, st, after);
-    case 4: return launch_round_prod4(fold, kind, a, st, after);
-    case 5: return launch_round_prod5(fold, kind, a, st, after);
-    case 6: return launch_round_prod6(fold, kind, a, st, after);
-    case 7: return launch_round_prod7(fold, kind, a, st, after);
-    case 8: return launch_round_prod8(fold, kind, a, st, after);
+    case 1: return launch_round_prod1(fold, kind, a, src, dst, st, after);
+    case 2: return launch_round_prod2(fold, kind, a, src, dst, st, after);
+    case 3: return launch_round_prod3(fold, kind, a, src, dst, st, after);
+    case 4: return launch_round_prod4(fold, kind, a, src, dst, st, after);
+    case 5: return launch_round_prod5(fold, kind, a, src, dst, st, after);
+    case 6: return launch_round_prod6(fold, kind, a, src, dst, st, after);
+    case 7: return launch_round_prod7(fold, kind, a, src, dst, st, after);
+    case 8: return launch_round_prod8(fold, kind, a, src, dst, st, after);
     default: return ZC_EUNSUPPORTED;
   }
 }
@@ -157,19 +159,147 @@ int prove_impl(const zc_shape* shape, const uint32_t* const* tables, const uint3
     }
     RoundArgs a = round_args(shape, L, ws, i, round_evals, challenges);
     a.openings = openings;
-    if (i == 1) {
-      a.src = a.dst = orig;
-      a.src_pitch = a.dst_pitch = n;
-    } else {
-      a.src = i == 2 ? orig : fold;
-      a.src_pitch = i == 2 ? n : half;
-      a.dst = fold;
-      a.dst_pitch = half;
-    }
+    a.src_pitch = i <= 2 ? n : half;
+    a.dst_pitch = i == 1 ? n : half;
+    const TabPtrs& src = i <= 2 ? orig : fold;
+    const TabPtrs& dst = i == 1 ? orig : fold;
     if (ev && hipEventRecord(ev[2 * (i - 1)], stream) != hipSuccess) return ZC_EHIP;
-    if ((rc = dispatch_round(shape, i > 1, kind, a, stream, ev ? ev[2 * (i - 1) + 1] : nullptr)) != ZC_OK) return rc;
+    if ((rc = dispatch_round(shape, i > 1, kind, a, src, dst, stream, ev ? ev[2 * (i - 1) + 1] : nullptr)) != ZC_OK)
+      return rc;
   }
   return ZC_OK;
+}
+
+// ---- batches -----------------------------------------------------------------
+
+__global__ __launch_bounds__(64) void k_batch_setup(const InstDesc* __restrict__ descs) {
+  const InstDesc& d = descs[blockIdx.x];
+  setup_body(d.r, d.mu, d.gate, d.m, d.ne, d.ctrl);
+}
+
+__global__ __launch_bounds__(kBlock) void k_batch_eq(const InstDesc* __restrict__ descs) {
+  const InstDesc& d = descs[blockIdx.y];
+  eq_row_body(d.ctrl, d.mu, d.eq.ml, const_cast<uint32_t*>(d.eq.lo), blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+constexpr uint32_t kBatchMax = 65536;
+constexpr uint32_t kGateKeys = 9;  // 0 vanilla, m = 1..8 product gate
+
+// Host-side schedule of a batch, recomputed identically by upload and launch.
+struct BatchSeg {
+  uint32_t key, step, count, blocks;
+  bool tail;
+  size_t inst_off, prefix_off;  // in u32 words within the schedule array
+};
+
+struct BatchPlan {
+  std::vector<Layout> L;
+  std::vector<uint32_t> last;
+  std::vector<BatchSeg> segs;
+  std::vector<uint32_t> words;  // the schedule array (instance lists, block prefixes)
+  uint32_t max_eq_rows = 0;
+};
+
+size_t desc_bytes(uint32_t n) { return align256((size_t)n * sizeof(InstDesc)); }
+
+size_t sched_words_max(uint32_t n) { return (size_t)kMuMax * (2 * (size_t)n + kGateKeys); }
+
+uint32_t gate_key(const zc_shape& s) { return s.gate == ZC_GATE_VANILLA ? 0u : s.m; }
+
+int check_instance(const zc_instance& in, Layout* L) {
+  int rc = make_layout(&in.shape, L);
+  if (rc != ZC_OK) return rc;
+  if ((rc = check_tables(*L, in.tables)) != ZC_OK) return rc;
+  if (!in.r || !in.ws || !in.round_evals || !in.challenges || !in.openings || !aligned(in.ws, 256))
+    return ZC_EINVAL;
+  return ZC_OK;
+}
+
+int make_plan(uint32_t n, const zc_instance* inst, BatchPlan* P) {
+  if (!inst || n < 1 || n > kBatchMax) return ZC_EINVAL;
+  P->L.resize(n);
+  P->last.resize(n);
+  uint32_t steps = 0;
+  for (uint32_t i = 0; i < n; ++i) {
+    const int rc = check_instance(inst[i], &P->L[i]);
+    if (rc != ZC_OK) return rc;
+    const uint32_t mu = inst[i].shape.mu;
+    // the first round with at most 2 kTailQ pairs launches the tail
+    P->last[i] = mu <= 6 ? 1u : mu - 6;
+    steps = std::max(steps, P->last[i]);
+    const Layout& L = P->L[i];
+    P->max_eq_rows = std::max(P->max_eq_rows, (1u << L.ml) + (1u << L.mh) + (2u << L.ml));
+  }
+  for (uint32_t s = 0; s < steps; ++s) {
+    for (uint32_t key = 0; key < kGateKeys; ++key) {
+      BatchSeg g{key, s, 0, 0, false, P->words.size(), 0};
+      std::vector<uint32_t> prefix{0};
+      for (uint32_t i = 0; i < n; ++i) {
+        if (gate_key(inst[i].shape) != key || s + 1 > P->last[i]) continue;
+        const uint64_t q = 1ull << (inst[i].shape.mu - (s + 1));
+        const uint64_t tile = inst[i].tile ? inst[i].tile : 4;
+        uint64_t b = (q + kBlock * tile - 1) / (kBlock * tile);
+        b = std::min<uint64_t>(std::max<uint64_t>(b, 1), kMaxBlocks);
+        P->words.push_back(i);
+        prefix.push_back(prefix.back() + (uint32_t)b);
+        if (s + 1 == P->last[i]) g.tail = true;
+        ++g.count;
+      }
+      if (g.count == 0) {
+        P->words.resize(g.inst_off);
+        continue;
+      }
+      g.blocks = prefix.back();
+      g.prefix_off = P->words.size();
+      P->words.insert(P->words.end(), prefix.begin(), prefix.end());
+      P->segs.push_back(g);
+    }
+  }
+  return P->words.size() <= sched_words_max(n) ? ZC_OK : ZC_EINVAL;
+}
+
+InstDesc make_desc(const zc_instance& in, const Layout& L, uint32_t last) {
+  InstDesc d{};
+  const uint64_t n = 1ull << in.shape.mu, half = n / 2;
+  uint8_t* w = bytes(in.ws);
+  for (uint32_t t = 0; t < L.k; ++t) {
+    d.orig.p[t] = const_cast<uint32_t*>(in.tables[t]);
+    d.fold.p[t] = reinterpret_cast<uint32_t*>(w + L.scratch) + (uint64_t)t * half * 8;
+  }
+  const uint32_t* rows = reinterpret_cast<const uint32_t*>(w + L.eqrows);
+  d.eq.lo = rows;
+  d.eq.hi = rows + ((size_t)1 << L.ml) * 8;
+  d.eq.suf = rows + (((size_t)1 << L.ml) + ((size_t)1 << L.mh)) * 8;
+  d.eq.ml = L.ml;
+  d.eq.mh = L.mh;
+  d.eq.mu = in.shape.mu;
+  d.ctrl = ctrl_of(in.ws);
+  d.partials = reinterpret_cast<uint32_t*>(w + L.partials);
+  d.evals = in.round_evals;
+  d.alphas = in.challenges;
+  d.openings = in.openings;
+  d.r = in.r;
+  d.mu = in.shape.mu;
+  d.gate = in.shape.gate;
+  d.m = in.shape.m;
+  d.ne = L.d + 2;
+  d.last = last;
+  return d;
+}
+
+int launch_batch_key(uint32_t key, const BatchStep& bs, uint32_t blocks, bool fold, bool tail, hipStream_t st) {
+  switch (key) {
+    case 0: return launch_batch_vanilla(bs, blocks, fold, tail, st);
+    case 1: return launch_batch_prod1(bs, blocks, fold, tail, st);
+    case 2: return launch_batch_prod2(bs, blocks, fold, tail, st);
+    case 3: return launch_batch_prod3(bs, blocks, fold, tail, st);
+    case 4: return launch_batch_prod4(bs, blocks, fold, tail, st);
+    case 5: return launch_batch_prod5(bs, blocks, fold, tail, st);
+    case 6: return launch_batch_prod6(bs, blocks, fold, tail, st);
+    case 7: return launch_batch_prod7(bs, blocks, fold, tail, st);
+    case 8: return launch_batch_prod8(bs, blocks, fold, tail, st);
+    default: return ZC_EUNSUPPORTED;
+  }
 }
 
 }  // namespace
@@ -231,9 +361,8 @@ int zc_round(const zc_shape* shape, const uint32_t* const* tables, const uint32_
     if ((rc = launch_ok()) != ZC_OK) return rc;
   }
   RoundArgs a = round_args(shape, L, ws, i, round_evals, challenges);
-  a.src = a.dst = cur;
   a.src_pitch = a.dst_pitch = n;
-  return dispatch_round(shape, false, a.q > kSplitQ ? kPerPair : kSplit, a, stream);
+  return dispatch_round(shape, false, a.q > kSplitQ ? kPerPair : kSplit, a, cur, cur, stream);
 }
 
 int zc_fold(const zc_shape* shape, uint32_t* const* tables, void* ws, uint32_t i, hipStream_t stream) {
@@ -251,6 +380,49 @@ int zc_fold(const zc_shape* shape, uint32_t* const* tables, void* ws, uint32_t i
   if ((rc = launch_ok()) != ZC_OK) return rc;
   hipLaunchKernelGGL(k_mark_folded, dim3(1), dim3(1), 0, stream, ctrl, i);
   return launch_ok();
+}
+
+size_t zc_batch_workspace_bytes(uint32_t n) {
+  if (n < 1 || n > kBatchMax) return 0;
+  return desc_bytes(n) + align256(sched_words_max(n) * sizeof(uint32_t));
+}
+
+int zc_batch_upload(uint32_t n, const zc_instance* inst, void* batch_ws, hipStream_t stream) {
+  if (!batch_ws || !aligned(batch_ws, 256)) return ZC_EINVAL;
+  BatchPlan P;
+  const int rc = make_plan(n, inst, &P);
+  if (rc != ZC_OK) return rc;
+  std::vector<uint8_t> host(desc_bytes(n) + P.words.size() * sizeof(uint32_t), 0);
+  InstDesc* d = reinterpret_cast<InstDesc*>(host.data());
+  for (uint32_t i = 0; i < n; ++i) d[i] = make_desc(inst[i], P.L[i], P.last[i]);
+  std::copy(P.words.begin(), P.words.end(), reinterpret_cast<uint32_t*>(host.data() + desc_bytes(n)));
+  if (hipMemcpyAsync(batch_ws, host.data(), host.size(), hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess)
+    return ZC_EHIP;
+  return ZC_OK;
+}
+
+int zc_batch_launch(uint32_t n, const zc_instance* inst, void* batch_ws, hipStream_t stream) {
+  if (!batch_ws || !aligned(batch_ws, 256)) return ZC_EINVAL;
+  BatchPlan P;
+  int rc = make_plan(n, inst, &P);
+  if (rc != ZC_OK) return rc;
+  const InstDesc* descs = reinterpret_cast<const InstDesc*>(batch_ws);
+  const uint32_t* words = reinterpret_cast<const uint32_t*>(bytes(batch_ws) + desc_bytes(n));
+  hipLaunchKernelGGL(k_batch_setup, dim3(n), dim3(64), 0, stream, descs);
+  if ((rc = launch_ok()) != ZC_OK) return rc;
+  hipLaunchKernelGGL(k_batch_eq, dim3((P.max_eq_rows + kBlock - 1) / kBlock, n), dim3(kBlock), 0, stream, descs);
+  if ((rc = launch_ok()) != ZC_OK) return rc;
+  for (const BatchSeg& g : P.segs) {
+    BatchStep bs{descs, words + g.inst_off, words + g.prefix_off, g.count, g.step};
+    if ((rc = launch_batch_key(g.key, bs, g.blocks, g.step > 0, g.tail, stream)) != ZC_OK) return rc;
+  }
+  return ZC_OK;
+}
+
+int zc_batch_prove(uint32_t n, const zc_instance* inst, void* batch_ws, hipStream_t stream) {
+  const int rc = zc_batch_upload(n, inst, batch_ws, stream);
+  return rc != ZC_OK ? rc : zc_batch_launch(n, inst, batch_ws, stream);
 }
 
 int zc_read_error(void* ws, hipStream_t stream) {

@@ -50,7 +50,8 @@ inline uint32_t round_grid(uint64_t blocks_for_work, int per_cu, int* rc) {
 // k_finish (one block: sums, G_i, alpha_i, and with kSplitTail the rest of
 // the proof).
 template <class Gate>
-int launch_round(bool fold, RoundKind kind, RoundArgs a, hipStream_t st, hipEvent_t after) {
+int launch_round(bool fold, RoundKind kind, RoundArgs a, const TabPtrs& src, const TabPtrs& dst, hipStream_t st,
+                 hipEvent_t after) {
   int rc = 0;
   uint32_t blocks;
   if (kind == kPerPair) {
@@ -61,9 +62,9 @@ int launch_round(bool fold, RoundKind kind, RoundArgs a, hipStream_t st, hipEven
     blocks = round_grid((a.q + kBlock - 1) / kBlock, per_cu, &rc);
     if (rc) return rc;
     if (fold)
-      hipLaunchKernelGGL((k_round<Gate, true>), dim3(blocks), dim3(kBlock), 0, st, a);
+      hipLaunchKernelGGL((k_round<Gate, true>), dim3(blocks), dim3(kBlock), 0, st, a, src, dst);
     else
-      hipLaunchKernelGGL((k_round<Gate, false>), dim3(blocks), dim3(kBlock), 0, st, a);
+      hipLaunchKernelGGL((k_round<Gate, false>), dim3(blocks), dim3(kBlock), 0, st, a, src, dst);
   } else {
     const void* kern = fold ? reinterpret_cast<const void*>(&k_round_split<Gate, true>)
                             : reinterpret_cast<const void*>(&k_round_split<Gate, false>);
@@ -72,31 +73,52 @@ int launch_round(bool fold, RoundKind kind, RoundArgs a, hipStream_t st, hipEven
     blocks = round_grid((a.q + kSplitPairs - 1) / kSplitPairs, per_cu, &rc);
     if (rc) return rc;
     if (fold)
-      hipLaunchKernelGGL((k_round_split<Gate, true>), dim3(blocks), dim3(kBlock), 0, st, a);
+      hipLaunchKernelGGL((k_round_split<Gate, true>), dim3(blocks), dim3(kBlock), 0, st, a, src, dst);
     else
-      hipLaunchKernelGGL((k_round_split<Gate, false>), dim3(blocks), dim3(kBlock), 0, st, a);
+      hipLaunchKernelGGL((k_round_split<Gate, false>), dim3(blocks), dim3(kBlock), 0, st, a, src, dst);
   }
   if ((rc = launch_ok()) != 0) return rc;
   if (after && hipEventRecord(after, st) != hipSuccess) return -3;
   a.nparts = blocks;
   a.tail = (kind == kSplitTail) ? 1u : 0u;
   const size_t lds = a.tail ? tail_lds_bytes<Gate>() : 0;
-  hipLaunchKernelGGL((k_finish<Gate>), dim3(1), dim3(kBlock), lds, st, a);
+  hipLaunchKernelGGL((k_finish<Gate>), dim3(1), dim3(kBlock), lds, st, a, dst);
+  return launch_ok();
+}
+
+template <class Gate>
+int launch_batch(const BatchStep& bs, uint32_t blocks, bool fold, bool tail, hipStream_t st) {
+  if (bs.count == 0) return 0;
+  if (fold)
+    hipLaunchKernelGGL((k_batch_round<Gate, true>), dim3(blocks), dim3(kBlock), 0, st, bs);
+  else
+    hipLaunchKernelGGL((k_batch_round<Gate, false>), dim3(blocks), dim3(kBlock), 0, st, bs);
+  int rc = launch_ok();
+  if (rc != 0) return rc;
+  hipLaunchKernelGGL((k_batch_finish<Gate>), dim3(bs.count), dim3(kBlock), tail ? tail_lds_bytes<Gate>() : 0, st, bs);
   return launch_ok();
 }
 
 }  // namespace
 
 #if defined(ZC_INST_VANILLA)
-int launch_round_vanilla(bool fold, RoundKind kind, const RoundArgs& a, hipStream_t st, hipEvent_t after) {
-  return launch_round<GateVanilla>(fold, kind, a, st, after);
+int launch_round_vanilla(bool fold, RoundKind kind, const RoundArgs& a, const TabPtrs& src, const TabPtrs& dst,
+                         hipStream_t st, hipEvent_t after) {
+  return launch_round<GateVanilla>(fold, kind, a, src, dst, st, after);
+}
+int launch_batch_vanilla(const BatchStep& bs, uint32_t blocks, bool fold, bool tail, hipStream_t st) {
+  return launch_batch<GateVanilla>(bs, blocks, fold, tail, st);
 }
 #elif defined(ZC_INST_PROD)
 #define ZC_CAT2(a, b) a##b
 #define ZC_CAT(a, b) ZC_CAT2(a, b)
-int ZC_CAT(launch_round_prod, ZC_INST_PROD)(bool fold, RoundKind kind, const RoundArgs& a, hipStream_t st,
-                                            hipEvent_t after) {
-  return launch_round<GateProd<ZC_INST_PROD>>(fold, kind, a, st, after);
+int ZC_CAT(launch_round_prod, ZC_INST_PROD)(bool fold, RoundKind kind, const RoundArgs& a, const TabPtrs& src,
+                                            const TabPtrs& dst, hipStream_t st, hipEvent_t after) {
+  return launch_round<GateProd<ZC_INST_PROD>>(fold, kind, a, src, dst, st, after);
+}
+int ZC_CAT(launch_batch_prod, ZC_INST_PROD)(const BatchStep& bs, uint32_t blocks, bool fold, bool tail,
+                                            hipStream_t st) {
+  return launch_batch<GateProd<ZC_INST_PROD>>(bs, blocks, fold, tail, st);
 }
 #else
 #error "build zc_inst.hip with -DZC_INST_VANILLA or -DZC_INST_PROD=<m>"

@@ -354,8 +354,9 @@ __device__ __forceinline__ Fe block_reduce(Fe (&v)[NV]) {
 
 // ---- end of a round ------------------------------------------------------------
 
+// The scalars of one round; the tables travel beside it (TabPtrs), as kernel
+// arguments or from a batch descriptor.
 struct RoundArgs {
-  TabPtrs src, dst;
   uint64_t src_pitch, dst_pitch;
   uint64_t q;                  // pairs of the evaluated round
   uint32_t round;              // i (1-based)
@@ -605,8 +606,12 @@ __device__ __forceinline__ void emit_round(Ctrl* ctrl, uint32_t round, uint32_t 
 // stores, so no block needs a device-wide fence (on this GPU such a fence
 // writes back and invalidates the L2 and holds the CU for several
 // microseconds).
+//
+// The body is shared with the batched kernel: block `blk` of the `nblk`
+// blocks working on this round.
 template <class Gate, bool FOLD>
-__global__ __launch_bounds__(kBlock) void k_round(RoundArgs a) {
+__device__ __forceinline__ void round_body(const RoundArgs& a, const TabPtrs& src, const TabPtrs& dst, uint32_t blk,
+                                           uint32_t nblk) {
   constexpr int NH = Gate::NH;
   Fe acc[NH];
   auto z = [&](auto x) __attribute__((always_inline)) { acc[x] = fe_zero(); };
@@ -616,19 +621,24 @@ __global__ __launch_bounds__(kBlock) void k_round(RoundArgs a) {
     Fe alpha;
     if (FOLD) alpha = load_words_fe(a.ctrl->alpha_m[a.round - 2]);
     const uint32_t q = (uint32_t)a.q;
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < q; j += stride) {
+    const uint32_t stride = nblk * blockDim.x;
+    for (uint32_t j = blk * blockDim.x + threadIdx.x; j < q; j += stride) {
       const EqRows er = issue_eq(a.eq, a.round, j);
       if (FOLD)
-        Gate::eval(FoldSrc{a.src, a.dst, a.src_pitch, a.dst_pitch, j, q, alpha}, er, acc);
+        Gate::eval(FoldSrc{src, dst, a.src_pitch, a.dst_pitch, j, q, alpha}, er, acc);
       else
-        Gate::eval(PairSrc{a.src, a.src_pitch, j, q}, er, acc);
+        Gate::eval(PairSrc{src, a.src_pitch, j, q}, er, acc);
     }
   }
   auto red = [&](auto x) __attribute__((always_inline)) { acc[x] = fe_reduce2(acc[x]); };
   Unroll<0, NH>::run(red);
   const Fe tot = block_reduce<NH>(acc);
-  if (threadIdx.x < NH) store_words_fe(a.partials + ((uint64_t)blockIdx.x * NH + threadIdx.x) * 8, tot);
+  if (threadIdx.x < NH) store_words_fe(a.partials + ((uint64_t)blk * NH + threadIdx.x) * 8, tot);
+}
+
+template <class Gate, bool FOLD>
+__global__ __launch_bounds__(kBlock) void k_round(RoundArgs a, TabPtrs src, TabPtrs dst) {
+  round_body<Gate, FOLD>(a, src, dst, blockIdx.x, gridDim.x);
 }
 
 // ---- lane-split rounds: 16 lanes per pair -------------------------------------------
@@ -677,7 +687,7 @@ __device__ __forceinline__ Fe group_reduce(Fe c) {
 
 // The last rounds of a proof inside one block, with the tables in LDS.  On
 // entry round a.round has been emitted (S holds round a.round+1's state and
-// alpha_{a.round}) and the tables at a.dst hold 2q live entries,
+// alpha_{a.round}) and the tables at dst hold 2q live entries,
 // q = a.q <= 2 kTailQ.  Runs rounds a.round+1 .. mu (fold with the previous
 // challenge, evaluate, emit) and the final fold, whose values are the
 // openings; eq's opening is C_{mu+1}.
@@ -686,7 +696,7 @@ __device__ __forceinline__ Fe group_reduce(Fe c) {
 // power of two >= d+1, times PP = kBlock / SL pairs per pass); the PP lanes
 // of a point are adjacent, so their sum is a shuffle reduction in one wave.
 template <class Gate>
-__device__ __forceinline__ void run_tail(const RoundArgs& a, FinLds<Gate::D>& S) {
+__device__ __forceinline__ void run_tail(const RoundArgs& a, const TabPtrs& dst, FinLds<Gate::D>& S) {
   constexpr int K = Gate::K;
   constexpr int NH = Gate::NH;
   constexpr uint32_t SL = NH <= 4 ? 4u : (NH <= 8 ? 8u : 16u);
@@ -699,7 +709,7 @@ __device__ __forceinline__ void run_tail(const RoundArgs& a, FinLds<Gate::D>& S)
   uint32_t L = 2 * (uint32_t)a.q;
   for (uint32_t idx = threadIdx.x; idx < K * L; idx += blockDim.x) {
     const uint32_t t = idx / L, e = idx % L;
-    lds_put(T(t, e), load_el(a.dst.p[t], a.dst_pitch, e));
+    lds_put(T(t, e), load_el(dst.p[t], a.dst_pitch, e));
   }
   // E_r[j] of every tail round r, heap-style: row 2^(mu-r) + j, rows [1, q)
   for (uint32_t hrow = threadIdx.x; hrow < (uint32_t)a.q; hrow += blockDim.x) {
@@ -749,7 +759,7 @@ __device__ __forceinline__ void run_tail(const RoundArgs& a, FinLds<Gate::D>& S)
 // Round with 16 lanes per pair; the grid strides over the pairs and is sized
 // like k_round's.
 template <class Gate, bool FOLD>
-__global__ __launch_bounds__(kBlock) void k_round_split(RoundArgs a) {
+__global__ __launch_bounds__(kBlock) void k_round_split(RoundArgs a, TabPtrs srct, TabPtrs dstt) {
   constexpr int K = Gate::K;
   constexpr int NH = Gate::NH;
   __shared__ uint32_t sh[kSplitPairs][K][2][NL];
@@ -762,12 +772,12 @@ __global__ __launch_bounds__(kBlock) void k_round_split(RoundArgs a) {
       const uint32_t j = (uint32_t)(base + pl);
       if (j < q && g < (uint32_t)K) {
         // table g's pointers, selected without indexing the argument array per lane
-        const uint32_t* src = a.src.p[0];
-        uint32_t* dst = a.dst.p[0];
+        const uint32_t* src = srct.p[0];
+        uint32_t* dst = dstt.p[0];
         auto sel = [&](auto t) __attribute__((always_inline)) {
           if (g == (uint32_t)t) {
-            src = a.src.p[t];
-            dst = a.dst.p[t];
+            src = srct.p[t];
+            dst = dstt.p[t];
           }
         };
         Unroll<1, K>::run(sel);
@@ -810,8 +820,10 @@ __global__ __launch_bounds__(kBlock) void k_round_split(RoundArgs a) {
 // alpha_i and, with a.tail, runs the rest of the proof in LDS (run_tail).
 // The challenge never leaves the device.  Runs only when round i-1 has been
 // emitted (ZC_ESTATE otherwise).
+// (Body shared with the batched finisher; `dst` holds the tables the tail
+// starts from.)
 template <class Gate>
-__global__ __launch_bounds__(kBlock) void k_finish(RoundArgs a) {
+__device__ __forceinline__ void finish_body(const RoundArgs& a, const TabPtrs& dst) {
   constexpr int NH = Gate::NH;
   __shared__ FinLds<Gate::D> S;
   const uint32_t t = threadIdx.x;
@@ -838,7 +850,95 @@ __global__ __launch_bounds__(kBlock) void k_finish(RoundArgs a) {
   __syncthreads();
   if (S.skip) return;
   emit_round<Gate::D>(a.ctrl, a.round, a.mu, S, a.evals_out, a.alpha_out);
-  if (a.tail) run_tail<Gate>(a, S);
+  if (a.tail) run_tail<Gate>(a, dst, S);
+}
+
+template <class Gate>
+__global__ __launch_bounds__(kBlock) void k_finish(RoundArgs a, TabPtrs dst) {
+  finish_body<Gate>(a, dst);
+}
+
+// ---- batches: many instances, round by round in lockstep ------------------------------
+//
+// Instance n of a batch is described once (InstDesc) and proves exactly as a
+// single zc_prove would, with its own workspace, so its bytes are the same.
+// At step s every instance with a round-kernel round left runs its round
+// s+1; the blocks of one launch are shared out by a prefix sum over the
+// instances of one gate, and one finisher block per instance then emits the
+// round (and, at the instance's last launched round, runs its tail).  The
+// per-round serial work of the instances (reduction, SHA-256, challenge)
+// thereby overlaps instead of adding up.
+
+struct InstDesc {
+  TabPtrs orig;      // caller tables (read only), pitch 2^mu
+  TabPtrs fold;      // folded copies in the instance workspace, pitch 2^(mu-1)
+  EqTabs eq;
+  Ctrl* ctrl;
+  uint32_t* partials;
+  uint32_t* evals;     // mu x (d+2) x 8
+  uint32_t* alphas;    // mu x 8
+  uint32_t* openings;  // (k+1) x 8
+  const uint32_t* r;
+  uint32_t mu, gate, m, ne;
+  uint32_t last;       // last round with a round kernel; its finisher runs the tail
+  uint32_t pad[3];
+};
+
+// One gate's share of a step: instances inst[0..count) (indices into descs)
+// with block ranges [prefix[i], prefix[i+1]).
+struct BatchStep {
+  const InstDesc* descs;
+  const uint32_t* inst;
+  const uint32_t* prefix;
+  uint32_t count;
+  uint32_t step;  // the instances run round step + 1
+};
+
+__device__ __forceinline__ RoundArgs batch_round_args(const InstDesc& d, uint32_t round, uint32_t nparts) {
+  RoundArgs a;
+  const uint64_t n = 1ull << d.mu;
+  a.src_pitch = round <= 2 ? n : n / 2;
+  a.dst_pitch = round == 1 ? n : n / 2;
+  a.q = 1ull << (d.mu - round);
+  a.round = round;
+  a.mu = d.mu;
+  a.nparts = nparts;
+  a.partials = d.partials;
+  a.ctrl = d.ctrl;
+  a.evals_out = d.evals + (uint64_t)(round - 1) * d.ne * 8;
+  a.alpha_out = d.alphas + (uint64_t)(round - 1) * 8;
+  a.tail = round == d.last ? 1u : 0u;
+  a.openings = d.openings;
+  a.eq = d.eq;
+  return a;
+}
+
+// Index i with prefix[i] <= b < prefix[i+1] (prefix[0] = 0, count >= 1).
+__device__ __forceinline__ uint32_t batch_find(const uint32_t* prefix, uint32_t count, uint32_t b) {
+  uint32_t lo = 0, hi = count;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (prefix[mid] <= b) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+template <class Gate, bool FOLD>
+__global__ __launch_bounds__(kBlock) void k_batch_round(BatchStep bs) {
+  const uint32_t i = batch_find(bs.prefix, bs.count, blockIdx.x);
+  const InstDesc& d = bs.descs[bs.inst[i]];
+  const uint32_t round = bs.step + 1;
+  const uint32_t p0 = bs.prefix[i], nblk = bs.prefix[i + 1] - p0;
+  const RoundArgs a = batch_round_args(d, round, nblk);
+  round_body<Gate, FOLD>(a, round <= 2 ? d.orig : d.fold, round == 1 ? d.orig : d.fold, blockIdx.x - p0, nblk);
+}
+
+template <class Gate>
+__global__ __launch_bounds__(kBlock) void k_batch_finish(BatchStep bs) {
+  const InstDesc& d = bs.descs[bs.inst[blockIdx.x]];
+  const uint32_t round = bs.step + 1;
+  const RoundArgs a = batch_round_args(d, round, bs.prefix[blockIdx.x + 1] - bs.prefix[blockIdx.x]);
+  finish_body<Gate>(a, round == 1 ? d.orig : d.fold);
 }
 
 }  // namespace zc

@@ -13,6 +13,7 @@
 namespace zc {
 
 struct RoundArgs;
+struct BatchStep;
 
 // Rounds with more pairs than this run one thread per pair (k_round); the
 // others run 16 lanes per pair (k_round_split).
@@ -35,9 +36,11 @@ inline RoundKind prove_round_kind(uint32_t mu, uint32_t i) {
 // One launcher per gate instantiation (defined in zc_inst.hip).  `after`, if
 // not null, is recorded on the stream between the round kernel and its
 // finisher (profiling).
-int launch_round_vanilla(bool fold, RoundKind kind, const RoundArgs& a, hipStream_t st, hipEvent_t after);
-#define ZC_DECL_PROD(M) \
-  int launch_round_prod##M(bool fold, RoundKind kind, const RoundArgs& a, hipStream_t st, hipEvent_t after);
+int launch_round_vanilla(bool fold, RoundKind kind, const RoundArgs& a, const TabPtrs& src, const TabPtrs& dst,
+                         hipStream_t st, hipEvent_t after);
+#define ZC_DECL_PROD(M)                                                                                      \
+  int launch_round_prod##M(bool fold, RoundKind kind, const RoundArgs& a, const TabPtrs& src, const TabPtrs& dst, \
+                           hipStream_t st, hipEvent_t after);
 ZC_DECL_PROD(1)
 ZC_DECL_PROD(2)
 ZC_DECL_PROD(3)
@@ -47,5 +50,20 @@ ZC_DECL_PROD(6)
 ZC_DECL_PROD(7)
 ZC_DECL_PROD(8)
 #undef ZC_DECL_PROD
+
+// One gate's share of one batch step: the round kernel over `blocks` blocks,
+// then one finisher block per instance (with tail LDS when `tail` is set).
+int launch_batch_vanilla(const BatchStep& bs, uint32_t blocks, bool fold, bool tail, hipStream_t st);
+#define ZC_DECL_BPROD(M) \
+  int launch_batch_prod##M(const BatchStep& bs, uint32_t blocks, bool fold, bool tail, hipStream_t st);
+ZC_DECL_BPROD(1)
+ZC_DECL_BPROD(2)
+ZC_DECL_BPROD(3)
+ZC_DECL_BPROD(4)
+ZC_DECL_BPROD(5)
+ZC_DECL_BPROD(6)
+ZC_DECL_BPROD(7)
+ZC_DECL_BPROD(8)
+#undef ZC_DECL_BPROD
 
 }  // namespace zc

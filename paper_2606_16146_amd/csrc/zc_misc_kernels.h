@@ -27,8 +27,8 @@ __device__ __forceinline__ Fe lam_mont(uint32_t d, uint32_t k) {
 // Montgomery form, sets C_1 = 1, coef_1[x] = eq1(x, r_1) for x < ne and
 // coefl_1, and starts the transcript:
 // T_0 = SHA-256("ZCv1" || u32 mu || u32 gate || u32 m || enc(r_1) .. enc(r_mu)).
-__global__ __launch_bounds__(64) void k_setup(const uint32_t* __restrict__ r, uint32_t mu, uint32_t gate,
-                                              uint32_t m, uint32_t ne, Ctrl* ctrl) {
+__device__ __forceinline__ void setup_body(const uint32_t* __restrict__ r, uint32_t mu, uint32_t gate, uint32_t m,
+                                           uint32_t ne, Ctrl* ctrl) {
   __shared__ uint32_t m0[4 + kMuMax * 8];
   if (threadIdx.x == 0) {
     ctrl->err = 0;
@@ -81,17 +81,21 @@ __global__ __launch_bounds__(64) void k_setup(const uint32_t* __restrict__ r, ui
   }
 }
 
+__global__ __launch_bounds__(64) void k_setup(const uint32_t* __restrict__ r, uint32_t mu, uint32_t gate,
+                                              uint32_t m, uint32_t ne, Ctrl* ctrl) {
+  setup_body(r, mu, gate, m, ne, ctrl);
+}
+
 // Rows of the factored eq tables (see EqTabs): LO (2^ml rows), the HI heap
 // (2^mh rows, row 0 unused) and the SUF heap (2^(ml+1) rows, row 0 unused),
 // concatenated in that order.  A row holding a table of nb variables whose
 // last variable is v is prod_k (bit ? r : 1 - r) over variables v-nb+1..v,
 // the most significant bit of the row index within the table being the
 // first of them.
-__global__ __launch_bounds__(kBlock) void k_eq_tables(const Ctrl* __restrict__ ctrl, uint32_t mu, uint32_t ml,
-                                                      uint32_t* __restrict__ rows) {
+__device__ __forceinline__ void eq_row_body(const Ctrl* __restrict__ ctrl, uint32_t mu, uint32_t ml,
+                                            uint32_t* __restrict__ rows, uint32_t e) {
   const uint32_t mh = mu - ml;
   const uint32_t nlo = 1u << ml, nhi = 1u << mh, nsuf = 2u << ml;
-  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nlo + nhi + nsuf) return;
   uint32_t y, nb, last;
   if (e < nlo) {
@@ -119,6 +123,11 @@ __global__ __launch_bounds__(kBlock) void k_eq_tables(const Ctrl* __restrict__ c
     acc = fe_reduce2(fe_mul(acc, bit ? ri : fe_submod(one, ri)));
   }
   store_words_fe(rows + (uint64_t)e * 8, acc);
+}
+
+__global__ __launch_bounds__(kBlock) void k_eq_tables(const Ctrl* __restrict__ ctrl, uint32_t mu, uint32_t ml,
+                                                      uint32_t* __restrict__ rows) {
+  eq_row_body(ctrl, mu, ml, rows, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // ---- folds -----------------------------------------------------------------------

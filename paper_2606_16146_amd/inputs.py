@@ -174,3 +174,39 @@ PRESETS = {
 def preset_instance(name: str, inst: int = 0) -> Instance:
     cfg = PRESETS[name]
     return make_instance(cfg["seed"], inst, cfg["mu"], cfg["gate"], cfg["m"])
+
+
+# ---- batches of independent instances --------------------------------------------------
+
+# Gate of each degree in a mixed batch: 3 the vanilla gate, otherwise the
+# product gate s*w1*...*wm - o of degree m + 1.
+DEGREE_GATES = {3: (GATE_VANILLA, 0), 5: (GATE_PROD, 4), 9: (GATE_PROD, 8)}
+BATCH_TABLE_ID = 0xFFFE  # stream of the batch's shape draws
+
+BATCH_PRESETS = {
+    # 256 instances, mu uniform in 10..18, degree uniform in {3, 5, 9}
+    "batch256": dict(seed=4, n=256, mu_lo=10, mu_hi=18, degrees=(3, 5, 9)),
+}
+
+
+def batch_specs(seed: int, n: int, mu_lo: int, mu_hi: int, degrees) -> list[tuple[int, int, int]]:
+    """(mu, gate, m) of each instance of a batch, drawn from the batch's own stream."""
+    rng = _stream(seed, 0, BATCH_TABLE_ID)
+    mus = rng.integers(mu_lo, mu_hi + 1, size=n)
+    degs = rng.choice(np.array(degrees), size=n)
+    return [(int(mu), *DEGREE_GATES[int(d)]) for mu, d in zip(mus, degs)]
+
+
+def _make_batch_item(args):
+    seed, i, mu, gate, m = args
+    return make_instance(seed, i, mu, gate, m)
+
+
+def make_batch(seed: int, specs, workers: int = 1) -> list[Instance]:
+    """Instance i of a batch is make_instance(seed, i, *specs[i])."""
+    jobs = [(seed, i, mu, gate, m) for i, (mu, gate, m) in enumerate(specs)]
+    if workers <= 1:
+        return [_make_batch_item(j) for j in jobs]
+    from concurrent.futures import ProcessPoolExecutor
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(_make_batch_item, jobs, chunksize=4))

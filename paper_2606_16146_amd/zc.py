@@ -26,6 +26,13 @@ class Shape(ctypes.Structure):
     _fields_ = [("mu", ctypes.c_uint32), ("gate", ctypes.c_uint32), ("m", ctypes.c_uint32)]
 
 
+class Instance(ctypes.Structure):
+    """zc_instance: one proof of a batch."""
+    _fields_ = [("shape", Shape), ("tables", ctypes.c_void_p), ("r", ctypes.c_void_p), ("ws", ctypes.c_void_p),
+                ("round_evals", ctypes.c_void_p), ("challenges", ctypes.c_void_p),
+                ("openings", ctypes.c_void_p), ("tile", ctypes.c_uint32)]
+
+
 class ZcError(RuntimeError):
     def __init__(self, status: int, what: str):
         super().__init__(f"{what}: {status} ({strerror(status)})")
@@ -50,6 +57,10 @@ _SIGS = {
     "zc_prove_round_kernel": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32]),
     "zc_prove_profiled": (ctypes.c_int, [ctypes.POINTER(Shape), _VP, _VP, _VP, _VP, _VP, _VP, _VP,
                                          _VP]),
+    "zc_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_uint32]),
+    "zc_batch_upload": (ctypes.c_int, [ctypes.c_uint32, _VP, _VP, _VP]),
+    "zc_batch_launch": (ctypes.c_int, [ctypes.c_uint32, _VP, _VP, _VP]),
+    "zc_batch_prove": (ctypes.c_int, [ctypes.c_uint32, _VP, _VP, _VP]),
 }
 
 
@@ -187,6 +198,38 @@ def prove_profiled(s: Shape, tables, r: torch.Tensor, ws: torch.Tensor, events: 
                                  _ptr(openings), ctypes.c_void_p(base), _stream(stream))
     _check(rc, "zc_prove_profiled")
     return evals, alphas, openings
+
+
+class Batch:
+    """Instances proved together (zc_batch_*).
+
+    items: sequence of (shape, tables, r, ws, outputs, tile), each as for
+    prove(); outputs from new_outputs(shape).  Keeps the ctypes arrays the
+    library reads alive and owns the batch workspace.
+    """
+
+    def __init__(self, items, device="cuda"):
+        self.items = list(items)
+        self.n = len(self.items)
+        self._tabs = [_table_array(it[1]) for it in self.items]
+        self.arr = (Instance * self.n)()
+        for i, (s, tables, r, ws, outs, tile) in enumerate(self.items):
+            ev, al, op = outs
+            self.arr[i] = Instance(s, ctypes.cast(self._tabs[i], ctypes.c_void_p), r.data_ptr(), ws.data_ptr(),
+                                   ev.data_ptr(), al.data_ptr(), op.data_ptr(), tile)
+        nb = lib().zc_batch_workspace_bytes(self.n)
+        if nb == 0:
+            raise ZcError(ZC_EINVAL, "batch workspace size")
+        self.ws = torch.empty(nb, dtype=torch.uint8, device=device)
+
+    def upload(self, stream=None):
+        _check(lib().zc_batch_upload(self.n, self.arr, _ptr(self.ws), _stream(stream)), "zc_batch_upload")
+
+    def launch(self, stream=None):
+        _check(lib().zc_batch_launch(self.n, self.arr, _ptr(self.ws), _stream(stream)), "zc_batch_launch")
+
+    def prove(self, stream=None):
+        _check(lib().zc_batch_prove(self.n, self.arr, _ptr(self.ws), _stream(stream)), "zc_batch_prove")
 
 
 class HipEvents:

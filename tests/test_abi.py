@@ -80,3 +80,29 @@ def test_round_kernel_schedule_is_consistent():
         # thread-per-pair rounds come first (largest q), then lane-split rounds
         assert kinds[:t] == sorted(kinds[:t]), (mu, kinds)
     assert h.zc_prove_round_kernel(0, 1) < 0 and h.zc_prove_round_kernel(5, 6) < 0
+
+
+def test_batch_host_validation_without_gpu():
+    h = zc.lib()
+    assert h.zc_batch_workspace_bytes(0) == 0
+    assert h.zc_batch_workspace_bytes(65537) == 0
+    assert h.zc_batch_workspace_bytes(1) >= ctypes.sizeof(zc.Instance)  # descriptors + schedule
+    assert h.zc_batch_workspace_bytes(256) > h.zc_batch_workspace_bytes(1)
+    fake = 0x1000  # never dereferenced: validation fails first
+    tabs = (ctypes.c_void_p * 8)(*([fake] * 8))
+    good = zc.Instance(zc.shape(4, 0), ctypes.cast(tabs, ctypes.c_void_p), fake, fake, fake, fake, fake, 0)
+    bad_shape = zc.Instance(zc.shape(4, 7), ctypes.cast(tabs, ctypes.c_void_p), fake, fake, fake, fake, fake, 0)
+    no_r = zc.Instance(zc.shape(4, 0), ctypes.cast(tabs, ctypes.c_void_p), None, fake, fake, fake, fake, 0)
+    misaligned_ws = zc.Instance(zc.shape(4, 0), ctypes.cast(tabs, ctypes.c_void_p), fake, fake + 4, fake, fake,
+                                fake, 0)
+    arr = (zc.Instance * 3)(good, bad_shape, good)
+    bws = ctypes.c_void_p(0x100000)
+    assert h.zc_batch_upload(0, arr, bws, None) == zc.ZC_EINVAL
+    assert h.zc_batch_upload(3, None, bws, None) == zc.ZC_EINVAL
+    assert h.zc_batch_upload(3, arr, None, None) == zc.ZC_EINVAL
+    assert h.zc_batch_upload(1, arr, ctypes.c_void_p(0x100004), None) == zc.ZC_EINVAL  # misaligned batch ws
+    assert h.zc_batch_upload(3, arr, bws, None) == zc.ZC_EUNSUPPORTED  # the second instance's gate
+    assert h.zc_batch_launch(3, arr, bws, None) == zc.ZC_EUNSUPPORTED
+    for one in (no_r, misaligned_ws):
+        a1 = (zc.Instance * 1)(one)
+        assert h.zc_batch_prove(1, a1, bws, None) == zc.ZC_EINVAL
