@@ -201,6 +201,86 @@ def run_workload(name, steps, warmup, cpu_baseline):
     return res
 
 
+def run_batch(name, steps, warmup, tune=True):
+    """Throughput of the batched prover on a preset batch (all instances
+    resident in HBM), against proving the same instances one after another
+    with zc_prove.  One step = one batched proof of every instance, replayed
+    from a HIP graph of the whole launch sequence."""
+    import torch
+
+    from paper_2606_16146_amd import autotune
+    from paper_2606_16146_amd import inputs as I
+    from paper_2606_16146_amd import zc
+
+    cfg = I.BATCH_PRESETS[name]
+    specs = I.batch_specs(cfg["seed"], cfg["n"], cfg["mu_lo"], cfg["mu_hi"], cfg["degrees"])
+    t0 = time.time()
+    insts = I.make_batch(cfg["seed"], specs, workers=min(16, os.cpu_count() or 1))
+    log(f"[bench] {name}: generated {len(insts)} instances in {time.time() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    items = []
+    for inst in insts:
+        s = zc.shape(inst.mu, inst.gate, inst.m)
+        ws = zc.new_workspace(s, dev)
+        tabs = [zc.pack(torch.from_numpy(t).to(dev), ws) for t in inst.tables]
+        items.append((s, tabs, torch.from_numpy(inst.r).to(dev), ws, zc.new_outputs(s, dev), 0))
+    torch.cuda.synchronize()
+    points = sum(1 << inst.mu for inst in insts)
+    b = zc.Batch(items, dev)
+    tiles = autotune.tune(b, log=log) if tune else None
+    if not tune:
+        b.upload()
+
+    # plain form: the same instances, one zc_prove after another
+    plain_outs = [zc.new_outputs(it[0], dev) for it in items]
+    for _ in range(max(1, warmup)):
+        for it, po in zip(items, plain_outs):
+            zc.prove(it[0], it[1], it[2], it[3], po)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for it, po in zip(items, plain_outs):
+        zc.prove(it[0], it[1], it[2], it[3], po)
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t0
+
+    # batched form, captured once into a graph
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        b.launch(stream=side)  # warm outside the capture
+        with torch.cuda.graph(g, stream=side):
+            b.launch(stream=side)
+    torch.cuda.current_stream().wait_stream(side)
+    for _ in range(warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.replay()
+    torch.cuda.synchronize()
+    batch_s = (time.perf_counter() - t0) / steps
+    errs = sum(zc.read_error(it[3]) != 0 for it in items)
+    same = all(torch.equal(a, c) for it, po in zip(items, plain_outs) for a, c in zip(it[4], po))
+    res = {
+        "metric": "hypercube points/s (aggregate over the batch)",
+        "value": points / batch_s,
+        "ms_per_step": batch_s * 1e3,
+        "plain_serial_value": points / plain_s,
+        "speedup_vs_plain": plain_s / batch_s,
+        "parity_vs_plain": "bit-exact" if same and errs == 0 else "MISMATCH",
+        "config": {"workload": name, "instances": len(insts), "points": points,
+                   "mu": [cfg["mu_lo"], cfg["mu_hi"]], "degrees": list(cfg["degrees"]),
+                   "seed": cfg["seed"], "field": "BN254 Fr"},
+        "tiles": {f"gate{k[0]}_m{k[1]}_{'large' if k[2] else 'small'}": v for k, v in (tiles or {}).items()},
+    }
+    log(f"[bench] {name}: batched {batch_s * 1e3:.2f} ms ({res['value'] / 1e6:.1f} M points/s), "
+        f"plain serial {plain_s * 1e3:.2f} ms ({res['plain_serial_value'] / 1e6:.1f} M points/s)")
+    if res["parity_vs_plain"] != "bit-exact":
+        raise RuntimeError("batched proof differs from the plain proofs")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -208,6 +288,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="plain20_d3")
     ap.add_argument("--secondary", default="plain20_d9", help="second workload ('' to skip)")
+    ap.add_argument("--batch", default="batch256", help="batched workload ('' to skip)")
+    ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB three times (the known-size "
@@ -264,6 +346,8 @@ def main():
     if args.secondary:
         sec = run_workload(args.secondary, args.steps, args.warmup, not args.no_cpu_baseline)
         out["secondary"] = {k: v for k, v in sec.items()}
+    if args.batch:
+        out["batched"] = run_batch(args.batch, args.batch_steps, min(args.warmup, 2))
     print(json.dumps(out), flush=True)
 
 
