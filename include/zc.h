@@ -160,6 +160,34 @@ int zc_batch_launch(uint32_t n, const zc_instance* inst, void* batch_ws, hipStre
 /* zc_batch_upload followed by zc_batch_launch. */
 int zc_batch_prove(uint32_t n, const zc_instance* inst, void* batch_ws, hipStream_t stream);
 
+/* ---- serving: instance slots advanced one round per step ----
+
+   A pool of `slots` instance slots in device memory (zc_serve_pool_bytes).
+   zc_serve_admit puts an instance into a free slot and launches its setup.
+   zc_serve_step then runs one round of each listed instance, each at its
+   own round, all instances of one gate sharing each launch. The step that
+   runs an instance's round zc_serve_rounds(shape) also runs the rest of its
+   proof; after it the outputs are complete.  The caller owns the schedule:
+   instance i of a step runs rounds[i], and rounds 1..zc_serve_rounds(shape)
+   of an instance must be run in order, one per step, on one stream.  A slot
+   may be reused after its instance's last step (same stream, so ordered).
+   Only kernel launches; no copies.  Results are the bytes zc_prove gives. */
+
+/* Bytes of a pool of `slots` slots (1 <= slots <= 65535), 0 otherwise. */
+size_t zc_serve_pool_bytes(uint32_t slots);
+
+/* Steps (rounds run by zc_serve_step) an instance of this shape needs, or a
+   negative zc_status. */
+int zc_serve_rounds(const zc_shape* shape);
+
+/* Checks the instance like zc_prove and enqueues its admission into `slot`. */
+int zc_serve_admit(void* pool, uint32_t slots, uint32_t slot, const zc_instance* inst, hipStream_t stream);
+
+/* One step for n admitted instances: slot_ids[i], rounds[i] (host arrays)
+   and inst[i] (the host description the slot was admitted with). */
+int zc_serve_step(void* pool, uint32_t slots, uint32_t n, const uint32_t* slot_ids, const uint32_t* rounds,
+                  const zc_instance* inst, hipStream_t stream);
+
 /* Synchronizes `stream` and returns the first device-detected error stored in
    ws (ZC_OK if none), or ZC_EHIP if the synchronization fails.  The error word
    is cleared when zc_prove or zc_round(1) starts; a workspace that has run

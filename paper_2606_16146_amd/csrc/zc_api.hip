@@ -302,6 +302,43 @@ int launch_batch_key(uint32_t key, const BatchStep& bs, uint32_t blocks, bool fo
   }
 }
 
+// ---- serving -------------------------------------------------------------------
+
+constexpr uint32_t kServeSlots = 65535;  // slot ids travel as u16
+
+__global__ __launch_bounds__(64) void k_serve_setup(InstDesc* __restrict__ pool, uint32_t slot, InstDesc d) {
+  if (threadIdx.x == 0) pool[slot] = d;
+  setup_body(d.r, d.mu, d.gate, d.m, d.ne, d.ctrl);
+}
+
+__global__ __launch_bounds__(kBlock) void k_serve_eq(InstDesc d) {
+  eq_row_body(d.ctrl, d.mu, d.eq.ml, const_cast<uint32_t*>(d.eq.lo), blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+uint32_t last_round(uint32_t mu) { return mu <= 6 ? 1u : mu - 6; }
+
+uint32_t tile_blocks(uint32_t mu, uint32_t round, uint32_t tile) {
+  const uint64_t q = 1ull << (mu - round);
+  const uint64_t t = tile ? tile : 4;
+  const uint64_t b = (q + kBlock * t - 1) / (kBlock * t);
+  return (uint32_t)std::min<uint64_t>(std::max<uint64_t>(b, 1), kMaxBlocks);
+}
+
+int launch_serve_key(uint32_t key, const ServeStep& ss, uint32_t blocks, bool fold, bool tail, hipStream_t st) {
+  switch (key) {
+    case 0: return launch_serve_vanilla(ss, blocks, fold, tail, st);
+    case 1: return launch_serve_prod1(ss, blocks, fold, tail, st);
+    case 2: return launch_serve_prod2(ss, blocks, fold, tail, st);
+    case 3: return launch_serve_prod3(ss, blocks, fold, tail, st);
+    case 4: return launch_serve_prod4(ss, blocks, fold, tail, st);
+    case 5: return launch_serve_prod5(ss, blocks, fold, tail, st);
+    case 6: return launch_serve_prod6(ss, blocks, fold, tail, st);
+    case 7: return launch_serve_prod7(ss, blocks, fold, tail, st);
+    case 8: return launch_serve_prod8(ss, blocks, fold, tail, st);
+    default: return ZC_EUNSUPPORTED;
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -423,6 +460,73 @@ int zc_batch_launch(uint32_t n, const zc_instance* inst, void* batch_ws, hipStre
 int zc_batch_prove(uint32_t n, const zc_instance* inst, void* batch_ws, hipStream_t stream) {
   const int rc = zc_batch_upload(n, inst, batch_ws, stream);
   return rc != ZC_OK ? rc : zc_batch_launch(n, inst, batch_ws, stream);
+}
+
+size_t zc_serve_pool_bytes(uint32_t slots) {
+  if (slots < 1 || slots > kServeSlots) return 0;
+  return align256((size_t)slots * sizeof(InstDesc));
+}
+
+int zc_serve_rounds(const zc_shape* shape) {
+  Layout L;
+  const int rc = make_layout(shape, &L);
+  return rc != ZC_OK ? rc : (int)last_round(shape->mu);
+}
+
+int zc_serve_admit(void* pool, uint32_t slots, uint32_t slot, const zc_instance* inst, hipStream_t stream) {
+  if (!pool || !inst || !aligned(pool, 256) || slots < 1 || slots > kServeSlots || slot >= slots) return ZC_EINVAL;
+  Layout L;
+  int rc = check_instance(*inst, &L);
+  if (rc != ZC_OK) return rc;
+  const InstDesc d = make_desc(*inst, L, last_round(inst->shape.mu));
+  hipLaunchKernelGGL(k_serve_setup, dim3(1), dim3(64), 0, stream, reinterpret_cast<InstDesc*>(pool), slot, d);
+  if ((rc = launch_ok()) != ZC_OK) return rc;
+  const uint32_t nrows = (1u << L.ml) + (1u << L.mh) + (2u << L.ml);
+  hipLaunchKernelGGL(k_serve_eq, dim3((nrows + kBlock - 1) / kBlock), dim3(kBlock), 0, stream, d);
+  return launch_ok();
+}
+
+int zc_serve_step(void* pool, uint32_t slots, uint32_t n, const uint32_t* slot_ids, const uint32_t* rounds,
+                  const zc_instance* inst, hipStream_t stream) {
+  if (!pool || !aligned(pool, 256) || slots < 1 || slots > kServeSlots) return ZC_EINVAL;
+  if (n == 0) return ZC_OK;
+  if (!slot_ids || !rounds || !inst) return ZC_EINVAL;
+  for (uint32_t i = 0; i < n; ++i) {
+    Layout L;
+    const int rc = make_layout(&inst[i].shape, &L);
+    if (rc != ZC_OK) return rc;
+    if (slot_ids[i] >= slots || rounds[i] < 1 || rounds[i] > last_round(inst[i].shape.mu)) return ZC_EINVAL;
+  }
+  // one launch pair per (gate, fold) group and per kServeMax instances
+  for (uint32_t key = 0; key < kGateKeys; ++key) {
+    for (int fold = 0; fold < 2; ++fold) {
+      ServeStep ss{};
+      ss.pool = reinterpret_cast<const InstDesc*>(pool);
+      bool tail = false;
+      auto flush = [&]() -> int {
+        if (ss.count == 0) return ZC_OK;
+        const int rc = launch_serve_key(key, ss, ss.prefix[ss.count], fold != 0, tail, stream);
+        ss.count = 0;
+        tail = false;
+        return rc;
+      };
+      for (uint32_t i = 0; i < n; ++i) {
+        if (gate_key(inst[i].shape) != key || (rounds[i] > 1) != (fold != 0)) continue;
+        const uint32_t c = ss.count;
+        ss.slot[c] = (uint16_t)slot_ids[i];
+        ss.rnd[c] = (uint8_t)rounds[i];
+        ss.prefix[c + 1] = ss.prefix[c] + tile_blocks(inst[i].shape.mu, rounds[i], inst[i].tile);
+        if (rounds[i] == last_round(inst[i].shape.mu)) tail = true;
+        if (++ss.count == (uint32_t)kServeMax) {
+          const int rc = flush();
+          if (rc != ZC_OK) return rc;
+        }
+      }
+      const int rc = flush();
+      if (rc != ZC_OK) return rc;
+    }
+  }
+  return ZC_OK;
 }
 
 int zc_read_error(void* ws, hipStream_t stream) {

@@ -99,6 +99,19 @@ int launch_batch(const BatchStep& bs, uint32_t blocks, bool fold, bool tail, hip
   return launch_ok();
 }
 
+template <class Gate>
+int launch_serve(const ServeStep& ss, uint32_t blocks, bool fold, bool tail, hipStream_t st) {
+  if (ss.count == 0) return 0;
+  if (fold)
+    hipLaunchKernelGGL((k_serve_round<Gate, true>), dim3(blocks), dim3(kBlock), 0, st, ss);
+  else
+    hipLaunchKernelGGL((k_serve_round<Gate, false>), dim3(blocks), dim3(kBlock), 0, st, ss);
+  int rc = launch_ok();
+  if (rc != 0) return rc;
+  hipLaunchKernelGGL((k_serve_finish<Gate>), dim3(ss.count), dim3(kBlock), tail ? tail_lds_bytes<Gate>() : 0, st, ss);
+  return launch_ok();
+}
+
 }  // namespace
 
 #if defined(ZC_INST_VANILLA)
@@ -108,6 +121,9 @@ int launch_round_vanilla(bool fold, RoundKind kind, const RoundArgs& a, const Ta
 }
 int launch_batch_vanilla(const BatchStep& bs, uint32_t blocks, bool fold, bool tail, hipStream_t st) {
   return launch_batch<GateVanilla>(bs, blocks, fold, tail, st);
+}
+int launch_serve_vanilla(const ServeStep& ss, uint32_t blocks, bool fold, bool tail, hipStream_t st) {
+  return launch_serve<GateVanilla>(ss, blocks, fold, tail, st);
 }
 #elif defined(ZC_INST_PROD)
 #define ZC_CAT2(a, b) a##b
@@ -119,6 +135,10 @@ int ZC_CAT(launch_round_prod, ZC_INST_PROD)(bool fold, RoundKind kind, const Rou
 int ZC_CAT(launch_batch_prod, ZC_INST_PROD)(const BatchStep& bs, uint32_t blocks, bool fold, bool tail,
                                             hipStream_t st) {
   return launch_batch<GateProd<ZC_INST_PROD>>(bs, blocks, fold, tail, st);
+}
+int ZC_CAT(launch_serve_prod, ZC_INST_PROD)(const ServeStep& ss, uint32_t blocks, bool fold, bool tail,
+                                            hipStream_t st) {
+  return launch_serve<GateProd<ZC_INST_PROD>>(ss, blocks, fold, tail, st);
 }
 #else
 #error "build zc_inst.hip with -DZC_INST_VANILLA or -DZC_INST_PROD=<m>"

@@ -885,14 +885,34 @@ struct InstDesc {
 };
 
 // One gate's share of a step: instances inst[0..count) (indices into descs)
-// with block ranges [prefix[i], prefix[i+1]).
+// with block ranges [prefix[i], prefix[i+1]), all running round step + 1.
 struct BatchStep {
   const InstDesc* descs;
   const uint32_t* inst;
   const uint32_t* prefix;
   uint32_t count;
-  uint32_t step;  // the instances run round step + 1
+  uint32_t step;
+  __device__ __forceinline__ uint32_t n() const { return count; }
+  __device__ __forceinline__ uint32_t pre(uint32_t i) const { return prefix[i]; }
+  __device__ __forceinline__ const InstDesc& desc(uint32_t i) const { return descs[inst[i]]; }
+  __device__ __forceinline__ uint32_t round(uint32_t) const { return step + 1; }
 };
+
+// One gate's share of a serving step: up to kServeMax instances, each at its
+// own round, carried whole in the kernel arguments (no copy per step).
+constexpr int kServeMax = 256;
+struct ServeStep {
+  const InstDesc* pool;
+  uint32_t count;
+  uint32_t prefix[kServeMax + 1];
+  uint16_t slot[kServeMax];
+  uint8_t rnd[kServeMax];
+  __device__ __forceinline__ uint32_t n() const { return count; }
+  __device__ __forceinline__ uint32_t pre(uint32_t i) const { return prefix[i]; }
+  __device__ __forceinline__ const InstDesc& desc(uint32_t i) const { return pool[slot[i]]; }
+  __device__ __forceinline__ uint32_t round(uint32_t i) const { return rnd[i]; }
+};
+static_assert(sizeof(ServeStep) <= 4096 - 64, "kernel argument size");
 
 __device__ __forceinline__ RoundArgs batch_round_args(const InstDesc& d, uint32_t round, uint32_t nparts) {
   RoundArgs a;
@@ -913,32 +933,53 @@ __device__ __forceinline__ RoundArgs batch_round_args(const InstDesc& d, uint32_
   return a;
 }
 
-// Index i with prefix[i] <= b < prefix[i+1] (prefix[0] = 0, count >= 1).
-__device__ __forceinline__ uint32_t batch_find(const uint32_t* prefix, uint32_t count, uint32_t b) {
-  uint32_t lo = 0, hi = count;
+// Index i with pre(i) <= b < pre(i+1) (pre(0) = 0, n() >= 1).
+template <class Step>
+__device__ __forceinline__ uint32_t batch_find(const Step& st, uint32_t b) {
+  uint32_t lo = 0, hi = st.n();
   while (hi - lo > 1) {
     const uint32_t mid = (lo + hi) >> 1;
-    if (prefix[mid] <= b) lo = mid; else hi = mid;
+    if (st.pre(mid) <= b) lo = mid; else hi = mid;
   }
   return lo;
 }
 
-template <class Gate, bool FOLD>
-__global__ __launch_bounds__(kBlock) void k_batch_round(BatchStep bs) {
-  const uint32_t i = batch_find(bs.prefix, bs.count, blockIdx.x);
-  const InstDesc& d = bs.descs[bs.inst[i]];
-  const uint32_t round = bs.step + 1;
-  const uint32_t p0 = bs.prefix[i], nblk = bs.prefix[i + 1] - p0;
+template <class Gate, bool FOLD, class Step>
+__device__ __forceinline__ void batch_round_body(const Step& st) {
+  const uint32_t i = batch_find(st, blockIdx.x);
+  const InstDesc& d = st.desc(i);
+  const uint32_t round = st.round(i);
+  const uint32_t p0 = st.pre(i), nblk = st.pre(i + 1) - p0;
   const RoundArgs a = batch_round_args(d, round, nblk);
   round_body<Gate, FOLD>(a, round <= 2 ? d.orig : d.fold, round == 1 ? d.orig : d.fold, blockIdx.x - p0, nblk);
 }
 
+template <class Gate, class Step>
+__device__ __forceinline__ void batch_finish_body(const Step& st) {
+  const InstDesc& d = st.desc(blockIdx.x);
+  const uint32_t round = st.round(blockIdx.x);
+  const RoundArgs a = batch_round_args(d, round, st.pre(blockIdx.x + 1) - st.pre(blockIdx.x));
+  finish_body<Gate>(a, round == 1 ? d.orig : d.fold);
+}
+
+template <class Gate, bool FOLD>
+__global__ __launch_bounds__(kBlock) void k_batch_round(BatchStep bs) {
+  batch_round_body<Gate, FOLD>(bs);
+}
+
 template <class Gate>
 __global__ __launch_bounds__(kBlock) void k_batch_finish(BatchStep bs) {
-  const InstDesc& d = bs.descs[bs.inst[blockIdx.x]];
-  const uint32_t round = bs.step + 1;
-  const RoundArgs a = batch_round_args(d, round, bs.prefix[blockIdx.x + 1] - bs.prefix[blockIdx.x]);
-  finish_body<Gate>(a, round == 1 ? d.orig : d.fold);
+  batch_finish_body<Gate>(bs);
+}
+
+template <class Gate, bool FOLD>
+__global__ __launch_bounds__(kBlock) void k_serve_round(ServeStep ss) {
+  batch_round_body<Gate, FOLD>(ss);
+}
+
+template <class Gate>
+__global__ __launch_bounds__(kBlock) void k_serve_finish(ServeStep ss) {
+  batch_finish_body<Gate>(ss);
 }
 
 }  // namespace zc

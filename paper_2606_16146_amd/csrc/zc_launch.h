@@ -14,6 +14,7 @@ namespace zc {
 
 struct RoundArgs;
 struct BatchStep;
+struct ServeStep;
 
 // Rounds with more pairs than this run one thread per pair (k_round); the
 // others run 16 lanes per pair (k_round_split).
@@ -65,5 +66,19 @@ ZC_DECL_BPROD(6)
 ZC_DECL_BPROD(7)
 ZC_DECL_BPROD(8)
 #undef ZC_DECL_BPROD
+
+// The same for a serving step (instances at their own rounds).
+int launch_serve_vanilla(const ServeStep& ss, uint32_t blocks, bool fold, bool tail, hipStream_t st);
+#define ZC_DECL_SPROD(M) \
+  int launch_serve_prod##M(const ServeStep& ss, uint32_t blocks, bool fold, bool tail, hipStream_t st);
+ZC_DECL_SPROD(1)
+ZC_DECL_SPROD(2)
+ZC_DECL_SPROD(3)
+ZC_DECL_SPROD(4)
+ZC_DECL_SPROD(5)
+ZC_DECL_SPROD(6)
+ZC_DECL_SPROD(7)
+ZC_DECL_SPROD(8)
+#undef ZC_DECL_SPROD
 
 }  // namespace zc

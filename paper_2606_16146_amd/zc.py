@@ -61,6 +61,10 @@ _SIGS = {
     "zc_batch_upload": (ctypes.c_int, [ctypes.c_uint32, _VP, _VP, _VP]),
     "zc_batch_launch": (ctypes.c_int, [ctypes.c_uint32, _VP, _VP, _VP]),
     "zc_batch_prove": (ctypes.c_int, [ctypes.c_uint32, _VP, _VP, _VP]),
+    "zc_serve_pool_bytes": (ctypes.c_size_t, [ctypes.c_uint32]),
+    "zc_serve_rounds": (ctypes.c_int, [ctypes.POINTER(Shape)]),
+    "zc_serve_admit": (ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.c_uint32, _VP, _VP]),
+    "zc_serve_step": (ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.c_uint32, _VP, _VP, _VP, _VP]),
 }
 
 
@@ -230,6 +234,34 @@ class Batch:
 
     def prove(self, stream=None):
         _check(lib().zc_batch_prove(self.n, self.arr, _ptr(self.ws), _stream(stream)), "zc_batch_prove")
+
+
+def serve_rounds(s: Shape) -> int:
+    n = lib().zc_serve_rounds(ctypes.byref(s))
+    _check(min(n, 0), "zc_serve_rounds")
+    return n
+
+
+class ServePool:
+    """zc_serve_*: a device pool of instance slots advanced one round per step."""
+
+    def __init__(self, slots: int, device="cuda"):
+        nb = lib().zc_serve_pool_bytes(slots)
+        if nb == 0:
+            raise ZcError(ZC_EINVAL, "serve pool size")
+        self.slots = slots
+        self.mem = torch.empty(nb, dtype=torch.uint8, device=device)
+
+    def admit(self, slot: int, inst: Instance, stream=None):
+        _check(lib().zc_serve_admit(_ptr(self.mem), self.slots, slot, ctypes.byref(inst), _stream(stream)),
+               "zc_serve_admit")
+
+    def step(self, slot_ids, rounds, insts, stream=None):
+        n = len(slot_ids)
+        sl = (ctypes.c_uint32 * n)(*slot_ids)
+        rd = (ctypes.c_uint32 * n)(*rounds)
+        arr = (Instance * n)(*insts)
+        _check(lib().zc_serve_step(_ptr(self.mem), self.slots, n, sl, rd, arr, _stream(stream)), "zc_serve_step")
 
 
 class HipEvents:

@@ -1,0 +1,76 @@
+"""Serving loop (zc_serve_* through paper_2606_16146_amd.serve): requests of
+mixed size and gate that arrive while others are on the GPU are admitted as
+slots and memory free up and share each step's launches; every result must
+be byte-identical to the same proof made alone with zc_prove (which the
+GPU parity tests tie to the oracle)."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2606_16146_amd import inputs as I
+from paper_2606_16146_amd import serve as S
+from paper_2606_16146_amd import zc
+from tests._helpers import dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _requests(specs, seed=31, host_tables=False):
+    reqs, insts = [], []
+    for i, (mu, gate, m, arrival) in enumerate(specs):
+        inst = I.make_instance(seed, i, mu, gate, m)
+        s = zc.shape(mu, gate, m)
+        ws = zc.new_workspace(s)
+        tabs = [zc.pack(dev(t), ws) for t in inst.tables]
+        if host_tables:
+            tabs = [t.cpu().pin_memory() for t in tabs]
+        reqs.append(S.Request(i, arrival, s, tabs, dev(inst.r), tile=i % 3, host_tables=host_tables))
+        insts.append(inst)
+    torch.cuda.synchronize()
+    return reqs, insts
+
+
+def _alone(inst):
+    s = zc.shape(inst.mu, inst.gate, inst.m)
+    ws = zc.new_workspace(s)
+    tabs = [zc.pack(dev(t), ws) for t in inst.tables]
+    out = zc.prove(s, tabs, dev(inst.r), ws)
+    assert zc.read_error(ws) == 0
+    return [o.cpu().numpy() for o in out]
+
+
+SPECS = [  # (mu, gate, m, arrival seconds): staggered, overlapping, several gates and tails
+    (9, 0, 0, 0.0), (12, 1, 8, 0.0), (5, 1, 4, 0.0005), (14, 0, 0, 0.001), (7, 1, 2, 0.001),
+    (11, 0, 0, 0.002), (3, 1, 8, 0.002), (13, 1, 4, 0.003), (8, 0, 0, 0.004), (1, 1, 1, 0.004),
+]
+
+
+def test_served_results_equal_alone():
+    reqs, insts = _requests(SPECS)
+    stats = S.Server(slots=8).run(reqs)
+    assert stats["errors"] == 0 and stats["requests"] == len(SPECS)
+    for q, inst in zip(reqs, insts):
+        print(f"request {q.rid} mu={inst.mu} gate={inst.gate} m={inst.m}", flush=True)
+        got = [o.cpu().numpy() for o in q.outputs]
+        assert all(np.array_equal(a, b) for a, b in zip(got, _alone(inst)))
+        assert q.t_done >= q.t_admit >= q.arrival - 1e-3
+
+
+def test_tight_slots_and_memory_still_correct():
+    reqs, insts = _requests(SPECS[:6], seed=32)
+    # two slots and a budget below two footprints: requests wait for admission
+    budget = max(S.footprint(q) for q in reqs) + 1
+    stats = S.Server(slots=2, mem_budget=budget).run(reqs)
+    assert stats["errors"] == 0
+    for q, inst in zip(reqs, insts):
+        got = [o.cpu().numpy() for o in q.outputs]
+        assert all(np.array_equal(a, b) for a, b in zip(got, _alone(inst)))
+
+
+def test_host_tables_copied_at_admission():
+    reqs, insts = _requests(SPECS[:4], seed=33, host_tables=True)
+    stats = S.Server(slots=4).run(reqs)
+    assert stats["errors"] == 0
+    for q, inst in zip(reqs, insts):
+        got = [o.cpu().numpy() for o in q.outputs]
+        assert all(np.array_equal(a, b) for a, b in zip(got, _alone(inst)))
