@@ -281,6 +281,95 @@ def run_batch(name, steps, warmup, tune=True):
     return res
 
 
+def run_serve(name, check=4):
+    """The served stream: Poisson arrivals at rho x the plain serial service
+    rate, plus one saturated run (every request waiting at t = 0), against
+    proving the same requests one after another with zc_prove."""
+    import numpy as np
+    import torch
+
+    from paper_2606_16146_amd import inputs as I
+    from paper_2606_16146_amd import serve as S
+    from paper_2606_16146_amd import zc
+
+    cfg = I.SERVE_PRESETS[name]
+    specs = I.serve_specs(cfg["seed"], cfg["n"], cfg["mu_lo"], cfg["mu_hi"], cfg["p_d3"])
+    dev = torch.device("cuda:0")
+    # one full-size instance per gate; a request of size mu uses its first 2^mu
+    # rows (each row satisfies the gate on its own), its own r
+    t0 = time.time()
+    gates = sorted({(g, m) for _, g, m in specs})
+    base = {gm: I.make_instance(cfg["seed"], 100 + gi, cfg["mu_hi"], gm[0], gm[1], workers=min(16, os.cpu_count() or 1))
+            for gi, gm in enumerate(gates)}
+    log(f"[bench] {name}: generated {len(gates)} base instances (mu={cfg['mu_hi']}) in {time.time() - t0:.1f}s")
+    scratch = zc.new_workspace(zc.shape(4, 0), dev)
+    pools = {}
+    for mu, g, m in sorted(set(specs)):
+        canon = base[(g, m)].tables[:, :1 << mu]
+        pools[(mu, g, m)] = [zc.pack(torch.from_numpy(np.ascontiguousarray(c)).to(dev), scratch) for c in canon]
+    rs = [torch.from_numpy(I.draw_elements(cfg["seed"], 1000 + i, I.R_TABLE_ID, mu)).to(dev)
+          for i, (mu, _, _) in enumerate(specs)]
+    torch.cuda.synchronize()
+    del base
+
+    # plain serial: each shape's proof time (median of 3), summed over the requests
+    t_shape = {}
+    for key, tabs in pools.items():
+        s = zc.shape(*key)
+        ws = zc.new_workspace(s, dev)
+        outs = zc.new_outputs(s, dev)
+        r0 = torch.zeros((key[0], 8), dtype=torch.uint32, device=dev)  # any r: same work
+        zc.prove(s, tabs, r0, ws, outs)
+        ts = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            zc.prove(s, tabs, r0, ws, outs)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - a)
+        t_shape[key] = statistics.median(ts)
+        del ws
+    serial_s = sum(t_shape[sp] for sp in specs)
+    points = sum(1 << mu for mu, _, _ in specs)
+    mean_t = serial_s / len(specs)
+
+    def requests(arrivals):
+        return [S.Request(i, float(arrivals[i]), zc.shape(*sp), pools[sp], rs[i], tile=0)
+                for i, sp in enumerate(specs)]
+
+    out = {"metric": "hypercube points/s served; p50/p99 request latency", "requests": len(specs),
+           "points": points, "plain_serial_points_per_s": points / serial_s,
+           "plain_serial_mean_ms": mean_t * 1e3, "runs": []}
+    for run, rho in enumerate(cfg["rhos"]):
+        arr = I.serve_arrivals(cfg["seed"], len(specs), rho / mean_t, run)
+        st = S.Server(slots=256).run(requests(arr))
+        st.update({"rho": rho, "arrival_rate_per_s": rho / mean_t})
+        out["runs"].append(st)
+        log(f"[bench] {name}: rho {rho}: {st['points_per_s'] / 1e6:.1f} M points/s, "
+            f"p50 {st['p50_ms']:.2f} ms, p99 {st['p99_ms']:.2f} ms, errors {st['errors']}")
+    reqs = requests(np.zeros(len(specs)))
+    st = S.Server(slots=256).run(reqs)
+    st.update({"rho": "saturated"})
+    out["runs"].append(st)
+    out["value"] = st["points_per_s"]
+    out["speedup_vs_plain"] = st["points_per_s"] * serial_s / points
+    log(f"[bench] {name}: saturated {st['points_per_s'] / 1e6:.1f} M points/s vs plain serial "
+        f"{points / serial_s / 1e6:.1f} M points/s, p50 {st['p50_ms']:.2f} ms, p99 {st['p99_ms']:.2f} ms")
+    # the served bytes equal the same proofs made alone (a sample)
+    same = True
+    for q in reqs[:check]:
+        ws = zc.new_workspace(q.shape, dev)
+        alone = zc.prove(q.shape, q.tables, q.r, ws)
+        same &= all(torch.equal(a, b) for a, b in zip(alone, q.outputs))
+    out["parity_vs_alone"] = "bit-exact" if same and all(r["errors"] == 0 for r in out["runs"]) else "MISMATCH"
+    out["config"] = {"workload": name, "mu": [cfg["mu_lo"], cfg["mu_hi"]], "p_degree3": cfg["p_d3"],
+                     "seed": cfg["seed"], "field": "BN254 Fr", "slots": 256,
+                     "inputs": "one mu=24 instance per gate, first 2^mu rows per request, own r"}
+    if out["parity_vs_alone"] != "bit-exact":
+        raise RuntimeError("served proofs differ from the same proofs alone")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -290,6 +379,7 @@ def main():
     ap.add_argument("--secondary", default="plain20_d9", help="second workload ('' to skip)")
     ap.add_argument("--batch", default="batch256", help="batched workload ('' to skip)")
     ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--serve", default="serve", help="served stream ('' to skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB three times (the known-size "
@@ -348,6 +438,8 @@ def main():
         out["secondary"] = {k: v for k, v in sec.items()}
     if args.batch:
         out["batched"] = run_batch(args.batch, args.batch_steps, min(args.warmup, 2))
+    if args.serve:
+        out["served"] = run_serve(args.serve)
     print(json.dumps(out), flush=True)
 
 

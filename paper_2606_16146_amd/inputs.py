@@ -137,9 +137,29 @@ class Instance:
         return limbs_to_ints(self.r)
 
 
+def _satisfying_column(gate: int, cols_limbs: np.ndarray) -> np.ndarray:
+    """The last column that makes the gate vanish on every row (Python ints)."""
+    cols = [limbs_to_ints(c) for c in cols_limbs]
+    if gate == GATE_VANILLA:
+        last = [(-(qm * a % P * b + ql * a + qr * b + qo * c)) % P
+                for a, b, c, qm, ql, qr, qo in zip(*cols)]
+    else:
+        last = cols[0]
+        for w in cols[1:]:
+            last = [x * y % P for x, y in zip(last, w)]
+    return ints_to_limbs(last)
+
+
+def _satisfying_chunk(args):
+    gate, cols = args
+    return _satisfying_column(gate, cols)
+
+
 def make_instance(seed: int, inst: int, mu: int, gate: int, m: int = 0,
-                  satisfying: bool = True) -> Instance:
-    """Draw one instance.  ``satisfying=False`` leaves the last column random."""
+                  satisfying: bool = True, workers: int = 1) -> Instance:
+    """Draw one instance.  ``satisfying=False`` leaves the last column random.
+    ``workers`` > 1 computes the satisfying column in row chunks in parallel
+    processes (same values)."""
     if mu < 1:
         raise ValueError("mu must be >= 1")
     k = gate_tables(gate, m)
@@ -148,15 +168,15 @@ def make_instance(seed: int, inst: int, mu: int, gate: int, m: int = 0,
     for t in range(k - 1):
         tabs[t] = draw_elements(seed, inst, t, n)
     if satisfying:
-        cols = [limbs_to_ints(tabs[t]) for t in range(k - 1)]
-        if gate == GATE_VANILLA:
-            last = [(-(qm * a % P * b + ql * a + qr * b + qo * c)) % P
-                    for a, b, c, qm, ql, qr, qo in zip(*cols)]
+        chunk = 1 << 16
+        if workers > 1 and n > chunk:
+            from concurrent.futures import ProcessPoolExecutor
+            jobs = [(gate, tabs[:k - 1, i:i + chunk]) for i in range(0, n, chunk)]
+            with ProcessPoolExecutor(max_workers=workers) as ex:
+                for i, part in zip(range(0, n, chunk), ex.map(_satisfying_chunk, jobs)):
+                    tabs[k - 1, i:i + chunk] = part
         else:
-            last = cols[0]
-            for w in cols[1:]:
-                last = [x * y % P for x, y in zip(last, w)]
-        tabs[k - 1] = ints_to_limbs(last)
+            tabs[k - 1] = _satisfying_column(gate, tabs[:k - 1])
     else:
         tabs[k - 1] = draw_elements(seed, inst, k - 1, n)
     r = draw_elements(seed, inst, R_TABLE_ID, mu)
@@ -210,3 +230,25 @@ def make_batch(seed: int, specs, workers: int = 1) -> list[Instance]:
     from concurrent.futures import ProcessPoolExecutor
     with ProcessPoolExecutor(max_workers=workers) as ex:
         return list(ex.map(_make_batch_item, jobs, chunksize=4))
+
+
+# Served stream: Poisson arrivals of single proofs, mu uniform in 14..24,
+# degree 3 with probability 0.7, else 9.
+SERVE_PRESETS = {
+    "serve": dict(seed=5, n=500, mu_lo=14, mu_hi=24, p_d3=0.7, rhos=(0.5, 0.8, 0.95)),
+}
+SERVE_TABLE_ID = 0xFFFD  # stream of the requests' shape and arrival draws
+
+
+def serve_specs(seed: int, n: int, mu_lo: int, mu_hi: int, p_d3: float) -> list[tuple[int, int, int]]:
+    """(mu, gate, m) of each request of a served stream."""
+    rng = _stream(seed, 0, SERVE_TABLE_ID)
+    mus = rng.integers(mu_lo, mu_hi + 1, size=n)
+    d3 = rng.random(size=n) < p_d3
+    return [(int(mu), *DEGREE_GATES[3 if a else 9]) for mu, a in zip(mus, d3)]
+
+
+def serve_arrivals(seed: int, n: int, rate: float, run: int = 0) -> np.ndarray:
+    """Poisson arrival times (seconds) of n requests at `rate` per second."""
+    rng = _stream(seed, 1 + run, SERVE_TABLE_ID)
+    return np.cumsum(rng.exponential(1.0 / rate, size=n)) - 0.0
