@@ -58,7 +58,11 @@ typedef enum {
      tables [a, b, c, qM, qL, qR, qO, qC] (HyperPlonk-style vanilla gate) */
   ZC_GATE_VANILLA = 0,
   /* f = s*w1*...*wm - o, degree m+1, tables [s, w1, .., wm, o], 1 <= m <= 8 */
-  ZC_GATE_PROD = 1
+  ZC_GATE_PROD = 1,
+  /* the polynomials of Table 1: f = g1*...*gP + gP+1 + ... + gP+A, degree P,
+     tables [g1, .., gP+A], m = P + 16*A with (P, A) one of (2,0) (2,1)
+     (2,2) (2,3) (3,0) (4,0) */
+  ZC_GATE_SUMPROD = 2
 } zc_gate;
 
 /* Instance shape: 1 <= mu <= 30, gate in zc_gate, m used by ZC_GATE_PROD. */

@@ -129,16 +129,25 @@ static fe from_mont(fe a) { fe one = {{1, 0, 0, 0}}; return fmul(a, one); }
 static fe small(uint64_t k) { fe a = {{k, 0, 0, 0}}; return to_mont(a); }
 
 /* ------------------------------------------------------------------ gate */
-enum { GATE_VANILLA = 0, GATE_PROD = 1 };
+enum { GATE_VANILLA = 0, GATE_PROD = 1, GATE_SUMPROD = 2 };
+
+/* Table 1 shapes g1..gP + gP+1..gP+A, m = P + 16 A. */
+static int sumprod_ok(uint32_t m) {
+    uint32_t pp = m & 15, aa = m >> 4;
+    return (pp == 2 && aa <= 3) || ((pp == 3 || pp == 4) && aa == 0);
+}
 
 static int gate_ntables(uint32_t gate, uint32_t m) {
     if (gate == GATE_VANILLA) return 8;
     if (gate == GATE_PROD && m >= 1 && m <= 8) return (int)m + 2;
+    if (gate == GATE_SUMPROD && sumprod_ok(m)) return (int)((m & 15) + (m >> 4));
     return -1;
 }
 
 static int gate_degree(uint32_t gate, uint32_t m) {
-    return gate == GATE_VANILLA ? 3 : (int)m + 1;
+    if (gate == GATE_VANILLA) return 3;
+    if (gate == GATE_SUMPROD) return (int)(m & 15);
+    return (int)m + 1;
 }
 
 /* f_M on one value per witness table, Montgomery form in and out. */
@@ -151,9 +160,22 @@ static fe gate_value(uint32_t gate, uint32_t m, const fe *v) {
         t = fadd(t, fmul(v[6], v[2]));
         return fadd(t, v[7]);
     }
+    if (gate == GATE_SUMPROD) {
+        /* g1*...*gP + gP+1 + ... + gP+A */
+        uint32_t pp = m & 15, aa = m >> 4;
+        fe t = v[0];
+        for (uint32_t k = 1; k < pp; ++k) t = fmul(t, v[k]);
+        for (uint32_t k = 0; k < aa; ++k) t = fadd(t, v[pp + k]);
+        return t;
+    }
     fe prod = v[0];
     for (uint32_t k = 1; k <= m; ++k) prod = fmul(prod, v[k]);
     return fsub(prod, v[m + 1]);
+}
+
+/* Gate degree d, or -1 for an unknown gate (exported for the wrapper). */
+int zco_degree(uint32_t gate, uint32_t m) {
+    return gate_ntables(gate, m) < 0 ? -1 : gate_degree(gate, m);
 }
 
 /* ------------------------------------------------------------ transcript */

@@ -19,6 +19,8 @@ def load():
         if not os.path.exists(_build.LIB):
             _build.build()
         lib = ctypes.CDLL(_build.LIB)
+        lib.zco_degree.restype = ctypes.c_int
+        lib.zco_degree.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
         lib.zco_prove.restype = ctypes.c_int
         lib.zco_prove.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -33,7 +35,10 @@ def max_threads() -> int:
 
 
 def degree(gate, m):
-    return 3 if gate == 0 else m + 1
+    d = load().zco_degree(gate, m)
+    if d < 0:
+        raise ValueError(f"unknown gate {gate}, m={m}")
+    return d
 
 
 def prove(mu, gate, m, tables: np.ndarray, r: np.ndarray, nthreads: int = 0):

@@ -43,6 +43,18 @@ P = 2188824287183927522224640574525727508854836440041603434369820418657580849561
 
 GATE_VANILLA = 0
 GATE_PROD = 1
+GATE_SUMPROD = 2
+
+# The polynomials of Table 1: g_1...g_P + g_{P+1} + ... + g_{P+A}, as (P, A);
+# the gate parameter is m = P + 16 A.
+TABLE1_SHAPES = ((2, 0), (2, 1), (2, 2), (2, 3), (3, 0), (4, 0))
+
+
+def sumprod_pa(m: int) -> tuple[int, int]:
+    pa = (m & 15, m >> 4)
+    if pa not in TABLE1_SHAPES:
+        raise ValueError(f"not a Table 1 shape: m={m}")
+    return pa
 
 
 # ----------------------------------------------------------------- field ---
@@ -66,6 +78,8 @@ def gate_degree(gate: int, m: int) -> int:
         return 3
     if gate == GATE_PROD:
         return m + 1
+    if gate == GATE_SUMPROD:
+        return sumprod_pa(m)[0]
     raise ValueError(f"unknown gate {gate}")
 
 
@@ -74,6 +88,9 @@ def gate_ntables(gate: int, m: int) -> int:
         return 8
     if gate == GATE_PROD:
         return m + 2
+    if gate == GATE_SUMPROD:
+        pp, aa = sumprod_pa(m)
+        return pp + aa
     raise ValueError(f"unknown gate {gate}")
 
 
@@ -84,6 +101,8 @@ def gate_value(gate: int, m: int, v) -> int:
         f = qM*a*b + qL*a + qR*b + qO*c + qC                      (degree 3)
     Product gate [s, w1, .., wm, o]:
         f = s*w1*...*wm - o                                        (degree m+1)
+    Table 1 shapes [g1 .. gP, gP+1 .. gP+A] (m = P + 16 A):
+        f = g1*...*gP + gP+1 + ... + gP+A                          (degree P)
     """
     if gate == GATE_VANILLA:
         a, b, c, qm, ql, qr, qo, qc = v
@@ -93,6 +112,12 @@ def gate_value(gate: int, m: int, v) -> int:
         for w in v[1:1 + m]:
             prod = prod * w % P
         return (prod - v[1 + m]) % P
+    if gate == GATE_SUMPROD:
+        pp, aa = sumprod_pa(m)
+        prod = 1
+        for g in v[:pp]:
+            prod = prod * g % P
+        return (prod + sum(v[pp:pp + aa])) % P
     raise ValueError(f"unknown gate {gate}")
 
 

@@ -21,6 +21,8 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
 UNITS = [("zc_api.hip", [], "zc_api.o"), ("zc_testing.hip", [], "zc_testing.o"),
          ("zc_inst.hip", ["-DZC_INST_VANILLA"], "zc_inst_vanilla.o")]
 UNITS += [("zc_inst.hip", [f"-DZC_INST_PROD={m}"], f"zc_inst_prod{m}.o") for m in range(1, 9)]
+# the polynomials of Table 1, m = P + 16 A
+UNITS += [("zc_inst.hip", [f"-DZC_INST_SUM={c}"], f"zc_inst_sum{c}.o") for c in (2, 18, 34, 50, 3, 4)]
 
 
 def _compile(unit, verbose):

@@ -26,17 +26,29 @@ struct Layout {
 
 constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Table 1 shapes g1..gP + gP+1..gP+A, m = P + 16 A; index in the gate keys.
+constexpr uint32_t kSumCodes[6] = {2, 18, 34, 50, 3, 4};
+
+int sum_index(uint32_t m) {
+  for (int i = 0; i < 6; ++i)
+    if (kSumCodes[i] == m) return i;
+  return -1;
+}
+
 int shape_k(const zc_shape* s) {
   if (!s) return ZC_EINVAL;
   if (s->gate == ZC_GATE_VANILLA) return 8;
   if (s->gate == ZC_GATE_PROD) return (s->m >= 1 && s->m <= 8) ? (int)s->m + 2 : ZC_EUNSUPPORTED;
+  if (s->gate == ZC_GATE_SUMPROD) return sum_index(s->m) >= 0 ? (int)((s->m & 15) + (s->m >> 4)) : ZC_EUNSUPPORTED;
   return ZC_EUNSUPPORTED;
 }
 
 int shape_d(const zc_shape* s) {
   const int k = shape_k(s);
   if (k < 0) return k;
-  return s->gate == ZC_GATE_VANILLA ? 3 : (int)s->m + 1;
+  if (s->gate == ZC_GATE_VANILLA) return 3;
+  if (s->gate == ZC_GATE_SUMPROD) return (int)(s->m & 15);
+  return (int)s->m + 1;
 }
 
 int make_layout(const zc_shape* s, Layout* L) {
@@ -73,6 +85,17 @@ inline uint8_t* bytes(void* ws) { return reinterpret_cast<uint8_t*>(ws); }
 int dispatch_round(const zc_shape* s, bool fold, RoundKind kind, const RoundArgs& a, const TabPtrs& src,
                    const TabPtrs& dst, hipStream_t st, hipEvent_t after = nullptr) {
   if (s->gate == ZC_GATE_VANILLA) return launch_round_vanilla(fold, kind, a, src, dst, st, after);
+  if (s->gate == ZC_GATE_SUMPROD) {
+    switch (s->m) {
+      case 2: return launch_round_sum2(fold, kind, a, src, dst, st, after);
+      case 18: return launch_round_sum18(fold, kind, a, src, dst, st, after);
+      case 34: return launch_round_sum34(fold, kind, a, src, dst, st, after);
+      case 50: return launch_round_sum50(fold, kind, a, src, dst, st, after);
+      case 3: return launch_round_sum3(fold, kind, a, src, dst, st, after);
+      case 4: return launch_round_sum4(fold, kind, a, src, dst, st, after);
+      default: return ZC_EUNSUPPORTED;
+    }
+  }
   switch (s->m) {
     case 1: return launch_round_prod1(fold, kind, a, src, dst, st, after);
     case 2: return launch_round_prod2(fold, kind, a, src, dst, st, after);
@@ -183,7 +206,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_eq(const InstDesc* __restrict_
 }
 
 constexpr uint32_t kBatchMax = 65536;
-constexpr uint32_t kGateKeys = 9;  // 0 vanilla, m = 1..8 product gate
+constexpr uint32_t kGateKeys = 15;  // 0 vanilla, 1..8 product gate m, 9..14 the Table 1 shapes
 
 // Host-side schedule of a batch, recomputed identically by upload and launch.
 struct BatchSeg {
@@ -204,7 +227,11 @@ size_t desc_bytes(uint32_t n) { return align256((size_t)n * sizeof(InstDesc)); }
 
 size_t sched_words_max(uint32_t n) { return (size_t)kMuMax * (2 * (size_t)n + kGateKeys); }
 
-uint32_t gate_key(const zc_shape& s) { return s.gate == ZC_GATE_VANILLA ? 0u : s.m; }
+uint32_t gate_key(const zc_shape& s) {
+  if (s.gate == ZC_GATE_VANILLA) return 0u;
+  if (s.gate == ZC_GATE_SUMPROD) return 9u + (uint32_t)sum_index(s.m);
+  return s.m;
+}
 
 int check_instance(const zc_instance& in, Layout* L) {
   int rc = make_layout(&in.shape, L);
@@ -298,6 +325,12 @@ int launch_batch_key(uint32_t key, const BatchStep& bs, uint32_t blocks, bool fo
     case 6: return launch_batch_prod6(bs, blocks, fold, tail, st);
     case 7: return launch_batch_prod7(bs, blocks, fold, tail, st);
     case 8: return launch_batch_prod8(bs, blocks, fold, tail, st);
+    case 9: return launch_batch_sum2(bs, blocks, fold, tail, st);
+    case 10: return launch_batch_sum18(bs, blocks, fold, tail, st);
+    case 11: return launch_batch_sum34(bs, blocks, fold, tail, st);
+    case 12: return launch_batch_sum50(bs, blocks, fold, tail, st);
+    case 13: return launch_batch_sum3(bs, blocks, fold, tail, st);
+    case 14: return launch_batch_sum4(bs, blocks, fold, tail, st);
     default: return ZC_EUNSUPPORTED;
   }
 }
@@ -335,6 +368,12 @@ int launch_serve_key(uint32_t key, const ServeStep& ss, uint32_t blocks, bool fo
     case 6: return launch_serve_prod6(ss, blocks, fold, tail, st);
     case 7: return launch_serve_prod7(ss, blocks, fold, tail, st);
     case 8: return launch_serve_prod8(ss, blocks, fold, tail, st);
+    case 9: return launch_serve_sum2(ss, blocks, fold, tail, st);
+    case 10: return launch_serve_sum18(ss, blocks, fold, tail, st);
+    case 11: return launch_serve_sum34(ss, blocks, fold, tail, st);
+    case 12: return launch_serve_sum50(ss, blocks, fold, tail, st);
+    case 13: return launch_serve_sum3(ss, blocks, fold, tail, st);
+    case 14: return launch_serve_sum4(ss, blocks, fold, tail, st);
     default: return ZC_EUNSUPPORTED;
   }
 }

@@ -1,6 +1,6 @@
 // Round-kernel instantiations for one gate.  Built once per gate with
-// -DZC_INST_VANILLA or -DZC_INST_PROD=<m>, so the unrolled kernels compile in
-// parallel.
+// -DZC_INST_VANILLA, -DZC_INST_PROD=<m> or -DZC_INST_SUM=<P + 16 A>, so the
+// unrolled kernels compile in parallel.
 #include <hip/hip_runtime.h>
 
 #include "zc_kernels.h"
@@ -140,8 +140,25 @@ int ZC_CAT(launch_serve_prod, ZC_INST_PROD)(const ServeStep& ss, uint32_t blocks
                                             hipStream_t st) {
   return launch_serve<GateProd<ZC_INST_PROD>>(ss, blocks, fold, tail, st);
 }
+#elif defined(ZC_INST_SUM)
+// m = P + 16 A of a Table 1 shape
+using GateT1 = GateSum<(ZC_INST_SUM & 15), (ZC_INST_SUM >> 4)>;
+#define ZC_CAT2(a, b) a##b
+#define ZC_CAT(a, b) ZC_CAT2(a, b)
+int ZC_CAT(launch_round_sum, ZC_INST_SUM)(bool fold, RoundKind kind, const RoundArgs& a, const TabPtrs& src,
+                                          const TabPtrs& dst, hipStream_t st, hipEvent_t after) {
+  return launch_round<GateT1>(fold, kind, a, src, dst, st, after);
+}
+int ZC_CAT(launch_batch_sum, ZC_INST_SUM)(const BatchStep& bs, uint32_t blocks, bool fold, bool tail,
+                                          hipStream_t st) {
+  return launch_batch<GateT1>(bs, blocks, fold, tail, st);
+}
+int ZC_CAT(launch_serve_sum, ZC_INST_SUM)(const ServeStep& ss, uint32_t blocks, bool fold, bool tail,
+                                          hipStream_t st) {
+  return launch_serve<GateT1>(ss, blocks, fold, tail, st);
+}
 #else
-#error "build zc_inst.hip with -DZC_INST_VANILLA or -DZC_INST_PROD=<m>"
+#error "build zc_inst.hip with -DZC_INST_VANILLA, -DZC_INST_PROD=<m> or -DZC_INST_SUM=<P + 16 A>"
 #endif
 
 }  // namespace zc

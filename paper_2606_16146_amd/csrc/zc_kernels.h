@@ -309,6 +309,58 @@ struct GateProd {
   }
 };
 
+// f = g1*...*gP + gP+1 + ... + gP+A, the polynomials of Table 1 (degree P,
+// P + A unique polynomials, A + 1 additive terms), columns [g1 .. gP+A].
+template <int P, int A>
+struct GateSum {
+  static_assert(P >= 2 && P <= 4 && A >= 0 && A <= 3, "Table 1 shapes");
+  static constexpr int K = P + A;
+  static constexpr int D = P;
+  static constexpr int NH = D + 1;
+  static constexpr int NE = D + 2;
+  // f_M at one point from the extensions e[0..K-1] (< 5p); result < 17p.
+  __device__ static __forceinline__ Fe point(const Fe* e) {
+    Fe f = fe_mul(e[0], e[1]);  // < 2p (5*5)
+    auto pm = [&](auto k) __attribute__((always_inline)) { f = fe_mul(f, e[k]); };  // < 2p (2*5)
+    Unroll<2, P>::run(pm);
+    auto ad = [&](auto k) __attribute__((always_inline)) { f = fe_add(f, e[k]); };  // < 2p + 15p
+    Unroll<P, K>::run(ad);
+    return f;
+  }
+  template <class Src>
+  __device__ static __forceinline__ void eval(const Src& src, const EqRows& er, Fe (&acc)[NH]) {
+    // extensions at X <= P are < (P+1) p <= 5p
+    Fe f[NH], lo, dl;
+    typename Src::Raw cur = src.issue(0);
+    typename Src::Raw nxt = src.issue(1);
+    src.get(cur, 0, lo, dl);
+    auto f0 = [&](auto x) __attribute__((always_inline)) {
+      f[x] = (x == 0) ? lo : fe_add(f[x > 0 ? x - 1 : 0], dl);
+    };
+    Unroll<0, NH>::run(f0);
+    auto step = [&](auto k) __attribute__((always_inline)) {
+      cur = nxt;
+      if (k + 1 < K) nxt = src.issue(k + 1 < K ? k + 1 : 0);
+      src.get(cur, k, lo, dl);
+      Fe e = lo;
+      auto px = [&](auto x) __attribute__((always_inline)) {
+        if (k < P)
+          f[x] = fe_mul(f[x], e);  // < 2p
+        else
+          f[x] = fe_add(f[x], e);  // < 17p after A additions
+        e = fe_add(e, dl);
+      };
+      Unroll<0, NH>::run(px);
+    };
+    Unroll<1, K>::run(step);
+    const Fe E = resolve_eq(er);
+    auto fo = [&](auto x) __attribute__((always_inline)) {
+      acc[x] = fe_csub(fe_add(acc[x], fe_mul(f[x], E)), kP2);  // product < 2p (17*1); acc < 2p
+    };
+    Unroll<0, NH>::run(fo);
+  }
+};
+
 // ---- reductions ---------------------------------------------------------------
 
 __device__ __forceinline__ Fe shfl_xor_fe(const Fe& a, int mask) {

@@ -81,4 +81,18 @@ ZC_DECL_SPROD(7)
 ZC_DECL_SPROD(8)
 #undef ZC_DECL_SPROD
 
+// Table 1 shapes, one set per m = P + 16 A.
+#define ZC_DECL_SUM(C)                                                                                            \
+  int launch_round_sum##C(bool fold, RoundKind kind, const RoundArgs& a, const TabPtrs& src, const TabPtrs& dst, \
+                          hipStream_t st, hipEvent_t after);                                                     \
+  int launch_batch_sum##C(const BatchStep& bs, uint32_t blocks, bool fold, bool tail, hipStream_t st);          \
+  int launch_serve_sum##C(const ServeStep& ss, uint32_t blocks, bool fold, bool tail, hipStream_t st);
+ZC_DECL_SUM(2)
+ZC_DECL_SUM(18)
+ZC_DECL_SUM(34)
+ZC_DECL_SUM(50)
+ZC_DECL_SUM(3)
+ZC_DECL_SUM(4)
+#undef ZC_DECL_SUM
+
 }  // namespace zc

@@ -14,8 +14,11 @@ Recipe (one independent stream per (seed, instance, table)):
 * The eq point ``r`` uses ``table_id = 0xFFFF`` and the same recipe.
 * The witness is made to satisfy the gate on every hypercube point by
   setting its last column: ``qC = -(qM*a*b + qL*a + qR*b + qO*c)`` for the
-  vanilla gate, ``o = s*w1*...*wm`` for the product gate.  That single
-  column is computed here with Python integers modulo p; a wrong column
+  vanilla gate, ``o = s*w1*...*wm`` for the product gate, and for the
+  Table 1 shapes ``g1*...*gP + gP+1 + ... + gP+A`` the last additive term
+  (minus the rest); a pure product (A = 0) is made to vanish by zeroing, on
+  every row, one factor picked by a stream of its own (``table_id =
+  0xFFFC``).  That column is computed here with Python integers modulo p; a wrong column
   would only make the witness non-satisfying, which the protocol-level
   tests (first claim equal to 0) detect independently of either prover.
 
@@ -35,8 +38,24 @@ P = 2188824287183927522224640574525727508854836440041603434369820418657580849561
 
 GATE_VANILLA = 0
 GATE_PROD = 1
+GATE_SUMPROD = 2  # Table 1 shapes g1*...*gP + gP+1 + ... + gP+A, m = P + 16 A
+
+# (P, A) of the six polynomials of Table 1
+TABLE1_SHAPES = ((2, 0), (2, 1), (2, 2), (2, 3), (3, 0), (4, 0))
 
 R_TABLE_ID = 0xFFFF
+ZERO_TABLE_ID = 0xFFFC  # which factor of a pure product is zeroed, per row
+
+
+def sumprod_m(pp: int, aa: int) -> int:
+    return pp + 16 * aa
+
+
+def sumprod_pa(m: int) -> tuple[int, int]:
+    pa = (m & 15, m >> 4)
+    if pa not in TABLE1_SHAPES:
+        raise ValueError(f"not a Table 1 shape: m={m}")
+    return pa
 
 
 def gate_tables(gate: int, m: int) -> int:
@@ -47,6 +66,9 @@ def gate_tables(gate: int, m: int) -> int:
         if not 1 <= m <= 8:
             raise ValueError("product gate needs 1 <= m <= 8")
         return m + 2
+    if gate == GATE_SUMPROD:
+        pp, aa = sumprod_pa(m)
+        return pp + aa
     raise ValueError(f"unknown gate {gate}")
 
 
@@ -56,6 +78,8 @@ def gate_degree(gate: int, m: int) -> int:
         return 3
     if gate == GATE_PROD:
         return m + 1
+    if gate == GATE_SUMPROD:
+        return sumprod_pa(m)[0]
     raise ValueError(f"unknown gate {gate}")
 
 
@@ -137,12 +161,20 @@ class Instance:
         return limbs_to_ints(self.r)
 
 
-def _satisfying_column(gate: int, cols_limbs: np.ndarray) -> np.ndarray:
+def _satisfying_column(gate: int, cols_limbs: np.ndarray, m: int = 0) -> np.ndarray:
     """The last column that makes the gate vanish on every row (Python ints)."""
     cols = [limbs_to_ints(c) for c in cols_limbs]
     if gate == GATE_VANILLA:
         last = [(-(qm * a % P * b + ql * a + qr * b + qo * c)) % P
                 for a, b, c, qm, ql, qr, qo in zip(*cols)]
+    elif gate == GATE_SUMPROD:
+        pp, _ = sumprod_pa(m)
+        last = []
+        for row in zip(*cols):
+            prod = 1
+            for g in row[:pp]:
+                prod = prod * g % P
+            last.append((-(prod + sum(row[pp:]))) % P)
     else:
         last = cols[0]
         for w in cols[1:]:
@@ -151,8 +183,8 @@ def _satisfying_column(gate: int, cols_limbs: np.ndarray) -> np.ndarray:
 
 
 def _satisfying_chunk(args):
-    gate, cols = args
-    return _satisfying_column(gate, cols)
+    gate, cols, m = args
+    return _satisfying_column(gate, cols, m)
 
 
 def make_instance(seed: int, inst: int, mu: int, gate: int, m: int = 0,
@@ -167,16 +199,22 @@ def make_instance(seed: int, inst: int, mu: int, gate: int, m: int = 0,
     tabs = np.empty((k, n, 8), dtype=np.uint32)
     for t in range(k - 1):
         tabs[t] = draw_elements(seed, inst, t, n)
-    if satisfying:
+    if satisfying and gate == GATE_SUMPROD and sumprod_pa(m)[1] == 0:
+        # a pure product vanishes where one of its factors does
+        tabs[k - 1] = draw_elements(seed, inst, k - 1, n)
+        zero = _stream(seed, inst, ZERO_TABLE_ID).integers(0, k, size=n)
+        for t in range(k):
+            tabs[t][zero == t] = 0
+    elif satisfying:
         chunk = 1 << 16
         if workers > 1 and n > chunk:
             from concurrent.futures import ProcessPoolExecutor
-            jobs = [(gate, tabs[:k - 1, i:i + chunk]) for i in range(0, n, chunk)]
+            jobs = [(gate, tabs[:k - 1, i:i + chunk], m) for i in range(0, n, chunk)]
             with ProcessPoolExecutor(max_workers=workers) as ex:
                 for i, part in zip(range(0, n, chunk), ex.map(_satisfying_chunk, jobs)):
                     tabs[k - 1, i:i + chunk] = part
         else:
-            tabs[k - 1] = _satisfying_column(gate, tabs[:k - 1])
+            tabs[k - 1] = _satisfying_column(gate, tabs[:k - 1], m)
     else:
         tabs[k - 1] = draw_elements(seed, inst, k - 1, n)
     r = draw_elements(seed, inst, R_TABLE_ID, mu)

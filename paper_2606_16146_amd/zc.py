@@ -19,7 +19,7 @@ LIB_PATH = os.environ.get("ZC_LIB") or os.path.join(HERE, "libzc.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
 ZC_OK, ZC_EINVAL, ZC_EUNSUPPORTED, ZC_EHIP, ZC_ERANGE, ZC_ESTATE = 0, -1, -2, -3, -4, -5
-GATE_VANILLA, GATE_PROD = 0, 1
+GATE_VANILLA, GATE_PROD, GATE_SUMPROD = 0, 1, 2
 
 
 class Shape(ctypes.Structure):

@@ -17,7 +17,9 @@ def test_library_exports_every_declared_symbol():
 
 
 @pytest.mark.parametrize("mu,gate,m,k,d", [(20, 0, 0, 8, 3), (20, 1, 8, 10, 9), (12, 1, 4, 6, 5),
-                                           (1, 1, 1, 3, 2)])
+                                           (1, 1, 1, 3, 2), (10, 2, 2, 2, 2), (10, 2, 18, 3, 2),
+                                           (10, 2, 34, 4, 2), (10, 2, 50, 5, 2), (10, 2, 3, 3, 3),
+                                           (10, 2, 4, 4, 4)])
 def test_shape_queries(mu, gate, m, k, d):
     s = zc.shape(mu, gate, m)
     assert zc.table_count(s) == k
@@ -30,7 +32,8 @@ def test_shape_queries(mu, gate, m, k, d):
     assert ws % 256 == 0
 
 
-@pytest.mark.parametrize("mu,gate,m", [(0, 0, 0), (31, 0, 0), (10, 2, 0), (10, 1, 0), (10, 1, 9)])
+@pytest.mark.parametrize("mu,gate,m", [(0, 0, 0), (31, 0, 0), (10, 3, 0), (10, 1, 0), (10, 1, 9),
+                                       (10, 2, 0), (10, 2, 19), (10, 2, 5)])
 def test_invalid_shapes(mu, gate, m):
     s = zc.shape(mu, gate, m)
     assert zc.workspace_bytes(s) == 0

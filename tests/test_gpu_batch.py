@@ -19,6 +19,7 @@ pytestmark = pytest.mark.gpu
 MIX = [
     (1, 0, 0, 0), (3, 1, 2, 1), (5, 0, 0, 2), (6, 1, 8, 0), (7, 0, 0, 1), (7, 1, 4, 4),
     (8, 1, 1, 8), (9, 0, 0, 0), (10, 1, 8, 2), (11, 1, 5, 0), (12, 0, 0, 16), (13, 1, 4, 1),
+    (9, 2, 2, 0), (6, 2, 50, 2), (11, 2, 4, 1), (8, 2, 18, 4),  # Table 1 shapes
 ]
 
 

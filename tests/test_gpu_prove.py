@@ -26,7 +26,9 @@ def zc():
 
 SMALL = [(1, 0, 0), (2, 0, 0), (3, 0, 0), (5, 0, 0), (9, 0, 0), (10, 0, 0),
          (1, 1, 1), (4, 1, 1), (6, 1, 2), (7, 1, 3), (8, 1, 4), (5, 1, 5), (6, 1, 6), (4, 1, 7),
-         (7, 1, 8), (2, 1, 8)]
+         (7, 1, 8), (2, 1, 8),
+         # the polynomials of Table 1
+         (1, 2, 2), (7, 2, 2), (8, 2, 18), (6, 2, 34), (9, 2, 50), (5, 2, 3), (10, 2, 4)]
 
 
 @pytest.mark.parametrize("mu,gate,m", SMALL)
@@ -143,6 +145,16 @@ def test_repeat_runs_are_identical_and_tables_untouched(zc):
         assert torch.equal(a, b)
     assert (again[0].cpu().numpy() == res["evals"]).all()
     assert (again[2].cpu().numpy() == res["openings"]).all()
+
+
+@pytest.mark.parametrize("m", [2, 18, 34, 50, 3, 4])
+def test_table1_shapes_mu16_match_c_oracle(zc, m):
+    inst = I.make_instance(41, m, 16, 2, m)
+    res = gpu_prove(inst)
+    assert res["err"] == 0
+    ora = C.prove(16, 2, m, inst.tables, inst.r)
+    assert np.array_equal(res["evals"], ora["evals"]) and np.array_equal(res["alphas"], ora["alphas"])
+    assert np.array_equal(res["openings"], ora["openings"])
 
 
 @pytest.mark.parametrize("name", ["plain20_d3", "plain20_d9"])

@@ -42,6 +42,7 @@ def _alone(inst):
 SPECS = [  # (mu, gate, m, arrival seconds): staggered, overlapping, several gates and tails
     (9, 0, 0, 0.0), (12, 1, 8, 0.0), (5, 1, 4, 0.0005), (14, 0, 0, 0.001), (7, 1, 2, 0.001),
     (11, 0, 0, 0.002), (3, 1, 8, 0.002), (13, 1, 4, 0.003), (8, 0, 0, 0.004), (1, 1, 1, 0.004),
+    (10, 2, 3, 0.001), (7, 2, 34, 0.003),  # Table 1 shapes
 ]
 
 

@@ -31,7 +31,9 @@ def test_python_oracle_matches_frozen_golden(path):
 
 @pytest.mark.parametrize("mu,gate,m,sat", [(1, 0, 0, True), (4, 0, 0, True), (9, 0, 0, True),
                                            (7, 0, 0, False), (5, 1, 1, True), (6, 1, 2, True),
-                                           (6, 1, 4, False), (5, 1, 8, True)])
+                                           (6, 1, 4, False), (5, 1, 8, True),
+                                           (6, 2, 2, True), (5, 2, 18, True), (7, 2, 34, False),
+                                           (4, 2, 50, True), (6, 2, 3, True), (5, 2, 4, True)])
 def test_c_oracle_equals_python_oracle(mu, gate, m, sat):
     x = I.make_instance(40 + mu, 0, mu, gate, m, satisfying=sat)
     a = C.prove(mu, gate, m, x.tables, x.r)

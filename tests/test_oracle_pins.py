@@ -138,8 +138,10 @@ def test_folding_all_variables_equals_mle_at_point():
 
 # ------------------------------------------------------- prover vs MLE ---
 
+T1 = [I.sumprod_m(pp, aa) for pp, aa in I.TABLE1_SHAPES]  # the polynomials of Table 1
 CASES = [(3, O.GATE_VANILLA, 0), (4, O.GATE_VANILLA, 0), (3, O.GATE_PROD, 2),
-         (4, O.GATE_PROD, 4), (2, O.GATE_PROD, 8), (3, O.GATE_PROD, 1)]
+         (4, O.GATE_PROD, 4), (2, O.GATE_PROD, 8), (3, O.GATE_PROD, 1)] + \
+        [(3 + (i % 2), O.GATE_SUMPROD, m) for i, m in enumerate(T1)]
 
 
 @pytest.mark.parametrize("mu,gate,m", CASES)
@@ -158,7 +160,7 @@ def test_round_polys_equal_bruteforce_interpolation_form(mu, gate, m):
 
 
 @pytest.mark.parametrize("mu,gate,m", [(6, O.GATE_VANILLA, 0), (5, O.GATE_PROD, 4),
-                                       (4, O.GATE_PROD, 8)])
+                                       (4, O.GATE_PROD, 8)] + [(5, O.GATE_SUMPROD, m) for m in T1])
 def test_claim_chain_first_claim_zero_and_verifier(mu, gate, m):
     inst = I.make_instance(7, 1, mu, gate, m)
     tabs, r = inst.tables_int(), inst.r_int()
@@ -170,7 +172,8 @@ def test_claim_chain_first_claim_zero_and_verifier(mu, gate, m):
     assert O.verify(mu, gate, m, r, ev, al, res["openings"])
 
 
-@pytest.mark.parametrize("gate,m", [(O.GATE_VANILLA, 0), (O.GATE_PROD, 2), (O.GATE_PROD, 8)])
+@pytest.mark.parametrize("gate,m", [(O.GATE_VANILLA, 0), (O.GATE_PROD, 2), (O.GATE_PROD, 8),
+                                    (O.GATE_SUMPROD, 2), (O.GATE_SUMPROD, 50), (O.GATE_SUMPROD, 4)])
 def test_round_poly_degree_extra_point_on_interpolant(gate, m):
     """G_i has degree d+1: its value at X=d+2 lies on the interpolant of 0..d+1."""
     mu = 4
@@ -266,7 +269,8 @@ def test_tampered_messages_are_rejected():
 
 # --------------------------------------------------------------- generator ---
 
-@pytest.mark.parametrize("gate,m", [(O.GATE_VANILLA, 0), (O.GATE_PROD, 4), (O.GATE_PROD, 8)])
+@pytest.mark.parametrize("gate,m", [(O.GATE_VANILLA, 0), (O.GATE_PROD, 4), (O.GATE_PROD, 8)] +
+                         [(O.GATE_SUMPROD, m) for m in T1])
 def test_generator_witness_satisfies_gate(gate, m):
     inst = I.make_instance(5, 3, 6, gate, m)
     tabs = inst.tables_int()
@@ -282,3 +286,23 @@ def test_generator_is_deterministic_and_streams_differ():
     assert (a.tables == b.tables).all() and (a.r == b.r).all()
     assert not (a.tables == c.tables).all()
     assert len({bytes(t) for t in a.tables}) == a.k
+
+
+def test_table1_gate_values_by_hand():
+    """The Table 1 polynomials on small integers, written out by hand."""
+    v = [2, 3, 5, 7, 11]
+    assert O.gate_value(O.GATE_SUMPROD, I.sumprod_m(2, 0), v[:2]) == 6            # g1 g2
+    assert O.gate_value(O.GATE_SUMPROD, I.sumprod_m(2, 1), v[:3]) == 6 + 5        # g1 g2 + g3
+    assert O.gate_value(O.GATE_SUMPROD, I.sumprod_m(2, 2), v[:4]) == 6 + 5 + 7
+    assert O.gate_value(O.GATE_SUMPROD, I.sumprod_m(2, 3), v[:5]) == 6 + 5 + 7 + 11
+    assert O.gate_value(O.GATE_SUMPROD, I.sumprod_m(3, 0), v[:3]) == 30           # g1 g2 g3
+    assert O.gate_value(O.GATE_SUMPROD, I.sumprod_m(4, 0), v[:4]) == 210          # g1 g2 g3 g4
+    # degree, unique polynomials and additive terms as Table 1 lists them
+    for (pp, aa), (d, uniq, terms) in zip(I.TABLE1_SHAPES, [(2, 2, 1), (2, 3, 2), (2, 4, 3), (2, 5, 4),
+                                                             (3, 3, 1), (4, 4, 1)]):
+        m = I.sumprod_m(pp, aa)
+        assert O.gate_degree(O.GATE_SUMPROD, m) == d
+        assert O.gate_ntables(O.GATE_SUMPROD, m) == uniq
+        assert aa + 1 == terms
+    with pytest.raises(ValueError):
+        O.gate_degree(O.GATE_SUMPROD, I.sumprod_m(3, 1))  # not in Table 1
