@@ -237,6 +237,32 @@ __device__ __forceinline__ void sha256_schedule_block(const uint32_t* msg, uint3
   }
 }
 
+// The same for a message of len bytes known at run time (any length, at most
+// kwords/64 blocks): lane b < nblocks expands block b.  Returns the number of
+// blocks.
+__device__ __forceinline__ uint32_t sha256_schedule_var(const uint32_t* msg, uint32_t len, uint32_t* kw) {
+  const uint32_t nb = (len + 9u + 63u) / 64u;
+  const uint32_t tw = nb * 16u;
+  if (threadIdx.x < nb) {
+    const uint32_t b = threadIdx.x;
+    uint32_t W[16];
+#pragma unroll
+    for (uint32_t t = 0; t < 16; ++t) {
+      W[t] = sha_padded_word(msg, len, tw, b * 16u + t);
+      kw[b * 64u + t] = W[t] + kSha256K[t];
+    }
+#pragma unroll
+    for (int t = 16; t < 64; ++t) {
+      const uint32_t w15 = W[(t - 15) & 15], w2 = W[(t - 2) & 15];
+      const uint32_t s0 = sha_xor3(sha_rotr(w15, 7), sha_rotr(w15, 18), w15 >> 3);
+      const uint32_t s1 = sha_xor3(sha_rotr(w2, 17), sha_rotr(w2, 19), w2 >> 10);
+      W[t & 15] = W[t & 15] + s0 + W[(t - 7) & 15] + s1;
+      kw[b * 64u + t] = W[t & 15] + kSha256K[t];
+    }
+  }
+  return nb;
+}
+
 // The compression of nb blocks whose schedules sha256_schedule_block left
 // in kw; one lane.  The digest is in the byte order of sha256().
 __device__ __forceinline__ void sha256_compress_blocks(const uint32_t* kw, uint32_t nb, uint32_t out[8]) {

@@ -132,12 +132,12 @@ RoundArgs round_args(const zc_shape* s, const Layout& L, void* ws, uint32_t i,
 // r -> canonical and Montgomery copies, C_1 and coef_1, the factored eq tables.
 int launch_setup(const zc_shape* s, const Layout& L, const uint32_t* r, void* ws, hipStream_t st) {
   Ctrl* ctrl = ctrl_of(ws);
-  hipLaunchKernelGGL(k_setup, dim3(1), dim3(64), 0, st, r, s->mu, s->gate, s->m, L.d + 2, ctrl);
+  hipLaunchKernelGGL(k_setup, dim3(1), dim3(64), 0, st, r, s->mu, L.d + 2, ctrl);
   if (launch_ok() != ZC_OK) return ZC_EHIP;
   const uint32_t nrows = (1u << L.ml) + (1u << L.mh) + (2u << L.ml);
   uint32_t* rows = reinterpret_cast<uint32_t*>(bytes(ws) + L.eqrows);
-  hipLaunchKernelGGL(k_eq_tables, dim3((nrows + kBlock - 1) / kBlock), dim3(kBlock), 0, st, ctrl, s->mu, L.ml,
-                     rows);
+  hipLaunchKernelGGL(k_eq_tables, dim3((nrows + kBlock - 1) / kBlock + 1), dim3(kBlock), 0, st, ctrl, r, s->mu,
+                     s->gate, s->m, L.ml, rows);
   return launch_ok();
 }
 
@@ -197,11 +197,16 @@ int prove_impl(const zc_shape* shape, const uint32_t* const* tables, const uint3
 
 __global__ __launch_bounds__(64) void k_batch_setup(const InstDesc* __restrict__ descs) {
   const InstDesc& d = descs[blockIdx.x];
-  setup_body(d.r, d.mu, d.gate, d.m, d.ne, d.ctrl);
+  setup_body(d.r, d.mu, d.ne, d.ctrl);
 }
 
+// eq rows of instance blockIdx.y; its T_0 in the last x block
 __global__ __launch_bounds__(kBlock) void k_batch_eq(const InstDesc* __restrict__ descs) {
   const InstDesc& d = descs[blockIdx.y];
+  if (blockIdx.x == gridDim.x - 1) {
+    t0_body(d.r, d.mu, d.gate, d.m, d.ctrl);
+    return;
+  }
   eq_row_body(d.ctrl, d.mu, d.eq.ml, const_cast<uint32_t*>(d.eq.lo), blockIdx.x * blockDim.x + threadIdx.x);
 }
 
@@ -341,10 +346,14 @@ constexpr uint32_t kServeSlots = 65535;  // slot ids travel as u16
 
 __global__ __launch_bounds__(64) void k_serve_setup(InstDesc* __restrict__ pool, uint32_t slot, InstDesc d) {
   if (threadIdx.x == 0) pool[slot] = d;
-  setup_body(d.r, d.mu, d.gate, d.m, d.ne, d.ctrl);
+  setup_body(d.r, d.mu, d.ne, d.ctrl);
 }
 
 __global__ __launch_bounds__(kBlock) void k_serve_eq(InstDesc d) {
+  if (blockIdx.x == gridDim.x - 1) {
+    t0_body(d.r, d.mu, d.gate, d.m, d.ctrl);
+    return;
+  }
   eq_row_body(d.ctrl, d.mu, d.eq.ml, const_cast<uint32_t*>(d.eq.lo), blockIdx.x * blockDim.x + threadIdx.x);
 }
 
@@ -487,7 +496,7 @@ int zc_batch_launch(uint32_t n, const zc_instance* inst, void* batch_ws, hipStre
   const uint32_t* words = reinterpret_cast<const uint32_t*>(bytes(batch_ws) + desc_bytes(n));
   hipLaunchKernelGGL(k_batch_setup, dim3(n), dim3(64), 0, stream, descs);
   if ((rc = launch_ok()) != ZC_OK) return rc;
-  hipLaunchKernelGGL(k_batch_eq, dim3((P.max_eq_rows + kBlock - 1) / kBlock, n), dim3(kBlock), 0, stream, descs);
+  hipLaunchKernelGGL(k_batch_eq, dim3((P.max_eq_rows + kBlock - 1) / kBlock + 1, n), dim3(kBlock), 0, stream, descs);
   if ((rc = launch_ok()) != ZC_OK) return rc;
   for (const BatchSeg& g : P.segs) {
     BatchStep bs{descs, words + g.inst_off, words + g.prefix_off, g.count, g.step};
@@ -521,7 +530,7 @@ int zc_serve_admit(void* pool, uint32_t slots, uint32_t slot, const zc_instance*
   hipLaunchKernelGGL(k_serve_setup, dim3(1), dim3(64), 0, stream, reinterpret_cast<InstDesc*>(pool), slot, d);
   if ((rc = launch_ok()) != ZC_OK) return rc;
   const uint32_t nrows = (1u << L.ml) + (1u << L.mh) + (2u << L.ml);
-  hipLaunchKernelGGL(k_serve_eq, dim3((nrows + kBlock - 1) / kBlock), dim3(kBlock), 0, stream, d);
+  hipLaunchKernelGGL(k_serve_eq, dim3((nrows + kBlock - 1) / kBlock + 1), dim3(kBlock), 0, stream, d);
   return launch_ok();
 }
 

@@ -786,15 +786,15 @@ __device__ __forceinline__ void run_tail(const RoundArgs& a, const TabPtrs& dst,
     const uint32_t q = L / 2;
     Fe c = fe_zero();
     if (x < (uint32_t)NH) {
-      for (uint32_t e = pp; e < q; e += PP) {
-        // keeps the compiler from moving LDS reads across iterations, which
-        // made one pass several times slower
-        asm volatile("" ::: "memory");
-        auto get = [&](int t, Fe& u0, Fe& u1) __attribute__((always_inline)) {
-          u0 = lds_fe(T(t, e));
-          u1 = lds_fe(T(t, e + q));
-        };
-        c = fe_addmod(c, mont(point_f<Gate>(get, x), lds_fe(eqrow + (q + e) * NL)));
+      for (uint32_t e0 = 0; e0 < q; e0 += PP) {  // uniform trip count, lanes past q idle
+        const uint32_t e = e0 + pp;
+        if (e < q) {
+          auto get = [&](int t, Fe& u0, Fe& u1) __attribute__((always_inline)) {
+            u0 = lds_fe(T(t, e));
+            u1 = lds_fe(T(t, e + q));
+          };
+          c = fe_addmod(c, mont(point_f<Gate>(get, x), lds_fe(eqrow + (q + e) * NL)));
+        }
       }
     }
 #pragma unroll

@@ -25,22 +25,14 @@ __device__ __forceinline__ Fe lam_mont(uint32_t d, uint32_t k) {
 
 // One block: resets the control block, checks r, keeps it in canonical and
 // Montgomery form, sets C_1 = 1, coef_1[x] = eq1(x, r_1) for x < ne and
-// coefl_1, and starts the transcript:
-// T_0 = SHA-256("ZCv1" || u32 mu || u32 gate || u32 m || enc(r_1) .. enc(r_mu)).
-__device__ __forceinline__ void setup_body(const uint32_t* __restrict__ r, uint32_t mu, uint32_t gate, uint32_t m,
-                                           uint32_t ne, Ctrl* ctrl) {
-  __shared__ uint32_t m0[4 + kMuMax * 8];
+// coefl_1.  (T_0 is hashed by t0_body, in the launch that follows.)
+__device__ __forceinline__ void setup_body(const uint32_t* __restrict__ r, uint32_t mu, uint32_t ne, Ctrl* ctrl) {
   if (threadIdx.x == 0) {
     ctrl->err = 0;
     ctrl->round_done = 0;
     ctrl->fold_done = 0;
     store_words_fe(ctrl->c_m, fe_const(kOne));
-    m0[0] = 0x3176435au;  // bytes 'Z' 'C' 'v' '1'
-    m0[1] = mu;
-    m0[2] = gate;
-    m0[3] = m;
   }
-  for (uint32_t i = threadIdx.x; i < mu * 8; i += blockDim.x) m0[4 + i] = r[i];
   __syncthreads();  // the reset above must precede any error flagged below
   for (uint32_t i = threadIdx.x; i < mu; i += blockDim.x) {
     uint32_t w[8];
@@ -72,18 +64,34 @@ __device__ __forceinline__ void setup_body(const uint32_t* __restrict__ r, uint3
       store_words_fe(ctrl->coefl[k], fe_reduce2(fe_mul(e, lam_mont(d, k))));
     }
   }
+}
+
+__global__ __launch_bounds__(64) void k_setup(const uint32_t* __restrict__ r, uint32_t mu, uint32_t ne, Ctrl* ctrl) {
+  setup_body(r, mu, ne, ctrl);
+}
+
+// T_0 = SHA-256("ZCv1" || u32 mu || u32 gate || u32 m || enc(r_1) .. enc(r_mu)),
+// one block: lane b expands message block b, lane 0 compresses.
+__device__ __forceinline__ void t0_body(const uint32_t* __restrict__ r, uint32_t mu, uint32_t gate, uint32_t m,
+                                        Ctrl* ctrl) {
+  __shared__ uint32_t m0[4 + kMuMax * 8];
+  __shared__ uint32_t kw[((16u + 32u * kMuMax + 9u + 63u) / 64u) * 64u];
+  if (threadIdx.x == 0) {
+    m0[0] = 0x3176435au;  // bytes 'Z' 'C' 'v' '1'
+    m0[1] = mu;
+    m0[2] = gate;
+    m0[3] = m;
+  }
+  for (uint32_t i = threadIdx.x; i < mu * 8; i += blockDim.x) m0[4 + i] = r[i];
+  __syncthreads();
+  const uint32_t nb = sha256_schedule_var(m0, 16u + 32u * mu, kw);
   __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t dg[8];
-    sha256(m0, 16u + 32u * mu, dg);
+    sha256_compress_blocks(kw, nb, dg);
 #pragma unroll
     for (int k = 0; k < 8; ++k) ctrl->ts[k] = dg[k];
   }
-}
-
-__global__ __launch_bounds__(64) void k_setup(const uint32_t* __restrict__ r, uint32_t mu, uint32_t gate,
-                                              uint32_t m, uint32_t ne, Ctrl* ctrl) {
-  setup_body(r, mu, gate, m, ne, ctrl);
 }
 
 // Rows of the factored eq tables (see EqTabs): LO (2^ml rows), the HI heap
@@ -125,8 +133,14 @@ __device__ __forceinline__ void eq_row_body(const Ctrl* __restrict__ ctrl, uint3
   store_words_fe(rows + (uint64_t)e * 8, acc);
 }
 
-__global__ __launch_bounds__(kBlock) void k_eq_tables(const Ctrl* __restrict__ ctrl, uint32_t mu, uint32_t ml,
+// The eq rows, and T_0 in the last block (it needs r only, so it overlaps).
+__global__ __launch_bounds__(kBlock) void k_eq_tables(Ctrl* __restrict__ ctrl, const uint32_t* __restrict__ r,
+                                                      uint32_t mu, uint32_t gate, uint32_t m, uint32_t ml,
                                                       uint32_t* __restrict__ rows) {
+  if (blockIdx.x == gridDim.x - 1) {
+    t0_body(r, mu, gate, m, ctrl);
+    return;
+  }
   eq_row_body(ctrl, mu, ml, rows, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
