@@ -181,6 +181,9 @@ struct FoldSrc {
 // evaluated as a*(qM*b + qL) + qR*b + qO*c + qC (four products per point).
 struct GateVanilla {
   static constexpr int K = 8;
+  // fold in a loop of its own: inlining the 16 fold products into the
+  // unrolled gate makes the round-2 kernel slower (measured)
+  static constexpr bool kFoldInGate = false;
   static constexpr int D = 3;
   static constexpr int NH = D + 1;
   static constexpr int NE = D + 2;
@@ -264,6 +267,7 @@ struct GateVanilla {
 template <int M>
 struct GateProd {
   static constexpr int K = M + 2;
+  static constexpr bool kFoldInGate = true;  // the gate's table loop is rolled
   static constexpr int D = M + 1;
   static constexpr int NH = D + 1;
   static constexpr int NE = D + 2;
@@ -315,6 +319,7 @@ template <int P, int A>
 struct GateSum {
   static_assert(P >= 2 && P <= 4 && A >= 0 && A <= 3, "Table 1 shapes");
   static constexpr int K = P + A;
+  static constexpr bool kFoldInGate = true;
   static constexpr int D = P;
   static constexpr int NH = D + 1;
   static constexpr int NE = D + 2;
@@ -676,10 +681,29 @@ __device__ __forceinline__ void round_body(const RoundArgs& a, const TabPtrs& sr
     const uint32_t stride = nblk * blockDim.x;
     for (uint32_t j = blk * blockDim.x + threadIdx.x; j < q; j += stride) {
       const EqRows er = issue_eq(a.eq, a.round, j);
-      if (FOLD)
+      if (FOLD && Gate::kFoldInGate) {
         Gate::eval(FoldSrc{src, dst, a.src_pitch, a.dst_pitch, j, q, alpha}, er, acc);
-      else
+      } else if (FOLD) {
+        // fold every table first (a rolled loop: one copy of the code), then
+        // evaluate on the folded pairs, which the L2 still holds
+        const uint64_t sp = a.src_pitch, dp = a.dst_pitch;
+        RawPair n01 = issue_pair(src.p[0], sp, j, q), n23 = issue_pair(src.p[0], sp, j + 2 * q, q);
+#pragma unroll 1
+        for (int t = 0; t < Gate::K; ++t) {
+          const RawPair c01 = n01, c23 = n23;
+          if (t + 1 < Gate::K) {
+            n01 = issue_pair(src.p[t + 1], sp, j, q);
+            n23 = issue_pair(src.p[t + 1], sp, j + 2 * q, q);
+          }
+          const Fe a0 = fe_from_words(c01.w0), a1 = fe_from_words(c01.w1);
+          const Fe a2 = fe_from_words(c23.w0), a3 = fe_from_words(c23.w1);
+          store_el(dst.p[t], dp, j, fe_addmod(a0, fe_reduce2(fe_mul(alpha, fe_submod(a2, a0)))));
+          store_el(dst.p[t], dp, j + q, fe_addmod(a1, fe_reduce2(fe_mul(alpha, fe_submod(a3, a1)))));
+        }
+        Gate::eval(PairSrc{dst, dp, j, q}, er, acc);
+      } else {
         Gate::eval(PairSrc{src, a.src_pitch, j, q}, er, acc);
+      }
     }
   }
   auto red = [&](auto x) __attribute__((always_inline)) { acc[x] = fe_reduce2(acc[x]); };
