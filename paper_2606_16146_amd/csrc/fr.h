@@ -277,6 +277,48 @@ __device__ __forceinline__ Fe fe_mul(const Fe& a, const Fe& b) {
   return r;
 }
 
+// Sum of N Montgomery products with one reduction: (sum_n a_n b_n) R^-1 mod p
+// up to a multiple of p.  The products share the column accumulators and the
+// m_i p_j half is done once, so N products cost 81 (N + 1) v_mad_u64_u32
+// instead of 162 N.  For a_n < A_n p, b_n < B_n p with sum_n A_n B_n <= 128 the
+// result is < 2p (as in fe_mul, since p / R < 2^-7).  A column holds at most
+// 9 (N + 1) terms below 2^58 plus a carry below 2^35, so N <= 6 keeps it below
+// 2^64.
+template <int N>
+__device__ __forceinline__ Fe fe_sop(const Fe (&a)[N], const Fe (&b)[N]) {
+  static_assert(N >= 1 && N <= 6, "column sums below 2^64");
+  uint32_t m[NL];
+  Fe r;
+  uint64_t acc = 0;
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+#pragma unroll
+    for (int i = 0; i < k; ++i) {
+#pragma unroll
+      for (int n = 0; n < N; ++n) acc = (uint64_t)a[n].l[i] * b[n].l[k - i] + acc;
+      acc = (uint64_t)m[i] * ZC_CL(kP, k - i) + acc;
+    }
+#pragma unroll
+    for (int n = 0; n < N; ++n) acc = (uint64_t)a[n].l[k] * b[n].l[0] + acc;
+    m[k] = ((uint32_t)acc * kNInv) & LM;
+    acc = (uint64_t)m[k] * ZC_CL(kP, 0) + acc;  // low 29 bits become 0
+    acc >>= 29;
+  }
+#pragma unroll
+  for (int k = NL; k < 2 * NL - 1; ++k) {
+#pragma unroll
+    for (int i = k - NL + 1; i < NL; ++i) {
+#pragma unroll
+      for (int n = 0; n < N; ++n) acc = (uint64_t)a[n].l[i] * b[n].l[k - i] + acc;
+      acc = (uint64_t)m[i] * ZC_CL(kP, k - i) + acc;
+    }
+    r.l[k - NL] = (uint32_t)acc & LM;
+    acc >>= 29;
+  }
+  r.l[NL - 1] = (uint32_t)acc;
+  return r;
+}
+
 // k * a for a small integer k <= 15 and a normalized a < p; result < k p,
 // normalized (each limb product is one v_mad_u64_u32 with the running carry).
 __device__ __forceinline__ Fe fe_mul_small(const Fe& a, uint32_t k) {
@@ -299,6 +341,18 @@ __device__ __forceinline__ Fe fe_from_mont(const Fe& a) {
   Fe one = fe_zero();
   one.l[0] = 1;
   return fe_reduce2(fe_mul(a, one));
+}
+
+// a + alpha (b - a) mod p, < p, for a, b < p and alpha < p in Montgomery form
+// (the fold of a table pair with a challenge).  b - a is taken as b + p - a
+// (< 2p, no reduction); alpha times it is < 2p (1 * 2 <= 128), plus a < 3p.
+__device__ __forceinline__ Fe fe_lerp(const Fe& a, const Fe& b, const Fe& alpha) {
+  return fe_csub(fe_csub(fe_add(a, fe_mul(alpha, fe_sub_plus(b, a, kP))), kP2), kP);
+}
+
+// Reduce a value < 128p below 2p.
+__device__ __forceinline__ Fe fe_reduce128_to2(const Fe& a) {
+  return fe_csub(fe_csub(fe_csub(fe_csub(fe_csub(fe_csub(a, kP64), kP32), kP16), kP8), kP4), kP2);
 }
 
 __device__ __forceinline__ bool fe_is_zero(const Fe& a) {

@@ -60,7 +60,16 @@ __device__ __forceinline__ void cvt_pair(const RawPair& r, Fe& lo, Fe& dl) {
   dl = fe_submod(fe_from_words(r.w1), lo);
 }
 
+// The same with a lazy difference dl = t[j+q] + p - t[j] < 2p (not reduced).
+// An extension lo + X dl = (1 - X) t[j] + X t[j+q] + X p is then < p at X = 0
+// and < 2X p for X >= 1.
+__device__ __forceinline__ void cvt_pair_lazy(const RawPair& r, Fe& lo, Fe& dl) {
+  lo = fe_from_words(r.w0);
+  dl = fe_sub_plus(fe_from_words(r.w1), lo, kP);
+}
+
 constexpr L9 kP11 = detail::mul_small(kP, 11);
+constexpr L9 kP18 = detail::mul_small(kP, 18);
 
 // ---- the factored eq table --------------------------------------------------------
 //
@@ -129,7 +138,8 @@ __device__ __forceinline__ Fe eq_factor(const EqTabs& E, uint32_t round, uint32_
 //
 // A gate asks for the pair (t[j], t[j+q]) of table t in two steps: issue(t)
 // starts the loads, get() turns them into (lo, dl) = (t[j], t[j+q] - t[j]),
-// so that the loads of the next table are in flight meanwhile.
+// so that the loads of the next table are in flight meanwhile.  getl() gives
+// the lazy difference of cvt_pair_lazy (dl < 2p) instead.
 
 // Tables already holding the round's 2q live entries.
 struct PairSrc {
@@ -139,6 +149,7 @@ struct PairSrc {
   using Raw = RawPair;
   __device__ __forceinline__ Raw issue(int t) const { return issue_pair(tp.p[t], pitch, j, q); }
   __device__ __forceinline__ void get(const Raw& r, int, Fe& lo, Fe& dl) const { cvt_pair(r, lo, dl); }
+  __device__ __forceinline__ void getl(const Raw& r, int, Fe& lo, Fe& dl) const { cvt_pair_lazy(r, lo, dl); }
 };
 
 // Tables holding 4q entries, folded on the way with alpha_{i-1}:
@@ -156,29 +167,38 @@ struct FoldSrc {
   __device__ __forceinline__ Raw issue(int t) const {
     return Raw{issue_pair(src.p[t], sp, j, q), issue_pair(src.p[t], sp, j + 2 * q, q)};
   }
-  __device__ __forceinline__ void get(const Raw& r, int t, Fe& lo, Fe& dl) const {
-    const Fe a0 = fe_from_words(r.lo2.w0), a1 = fe_from_words(r.lo2.w1);
-    const Fe a2 = fe_from_words(r.hi2.w0), a3 = fe_from_words(r.hi2.w1);
-    const Fe u0 = fe_addmod(a0, fe_reduce2(fe_mul(alpha, fe_submod(a2, a0))));
-    const Fe u1 = fe_addmod(a1, fe_reduce2(fe_mul(alpha, fe_submod(a3, a1))));
+  __device__ __forceinline__ void fold(const Raw& r, int t, Fe& u0, Fe& u1) const {
+    u0 = fe_lerp(fe_from_words(r.lo2.w0), fe_from_words(r.hi2.w0), alpha);
+    u1 = fe_lerp(fe_from_words(r.lo2.w1), fe_from_words(r.hi2.w1), alpha);
     store_el(dst.p[t], dp, j, u0);
     store_el(dst.p[t], dp, j + q, u1);
-    lo = u0;
-    dl = fe_submod(u1, u0);
+  }
+  __device__ __forceinline__ void get(const Raw& r, int t, Fe& lo, Fe& dl) const {
+    Fe u1;
+    fold(r, t, lo, u1);
+    dl = fe_submod(u1, lo);
+  }
+  __device__ __forceinline__ void getl(const Raw& r, int t, Fe& lo, Fe& dl) const {
+    Fe u1;
+    fold(r, t, lo, u1);
+    dl = fe_sub_plus(u1, lo, kP);
   }
 };
 
 // ---- gates ---------------------------------------------------------------------
 //
 // eval() adds E * f_M(ext(X)) for X = 0..NH-1 (NH = d+1) of one pair to
-// acc[X] (kept < 2p).  The extension of a table at X is e(X) = lo + X*dl,
-// built by plain additions, so e(X) < (X+1) p.  The NH products of one step
+// acc[X]; the addend is < 2p and acc is not reduced (round_body reduces it
+// every kLazyPairs pairs).  The extension of a table at X is e(X) = lo + X*dl,
+// built by plain additions: e(X) < (X+1) p with strict differences (get),
+// e(X) < 2X p (X >= 1) with lazy ones (getl).  The NH products of one step
 // are independent of each other, which keeps the multiply pipeline busy, and
 // the loads of the next table are issued before the current step's products
 // so that their latency is hidden.
 
 // f = qM*a*b + qL*a + qR*b + qO*c + qC, columns [a b c qM qL qR qO qC], degree 3,
-// evaluated as a*(qM*b + qL) + qR*b + qO*c + qC (four products per point).
+// evaluated as a*(qM*b + qL) + qR*b + qO*c + qC: per point one product and one
+// sum of three products (fe_sop), then the product with E.
 struct GateVanilla {
   static constexpr int K = 8;
   // fold in a loop of its own: inlining the 16 fold products into the
@@ -197,66 +217,56 @@ struct GateVanilla {
   }
   template <class Src>
   __device__ static __forceinline__ void eval(const Src& src, const EqRows& er, Fe (&acc)[NH]) {
-    // extensions at X <= 3 are < 4p
-    Fe bx[NH], t[NH], lo, dl, e;
-    typename Src::Raw ra = src.issue(1);  // b
-    typename Src::Raw rb = src.issue(3);  // qM
-    src.get(ra, 1, lo, dl);
-    ra = src.issue(4);  // qL
+    // lazy differences: every extension at X <= 3 is < 6p
+    Fe bx[NH], s[NH], lo, dl, e;
+    typename Src::Raw rb = src.issue(1);   // b
+    typename Src::Raw rm = src.issue(3);   // qM
+    typename Src::Raw rl = src.issue(4);   // qL
+    src.getl(rb, 1, lo, dl);
+    typename Src::Raw ra = src.issue(0);   // a
+    typename Src::Raw rr = src.issue(5);   // qR
     auto fb = [&](auto x) __attribute__((always_inline)) {
       bx[x] = (x == 0) ? lo : fe_add(bx[x > 0 ? x - 1 : 0], dl);
     };
     Unroll<0, NH>::run(fb);
-    src.get(rb, 3, lo, dl);  // qM
-    rb = src.issue(0);  // a
+    src.getl(rm, 3, lo, dl);  // qM
+    typename Src::Raw ro = src.issue(6);   // qO
+    typename Src::Raw rc = src.issue(2);   // c
     e = lo;
     auto f1 = [&](auto x) __attribute__((always_inline)) {
-      t[x] = fe_mul(e, bx[x]);  // < 2p
+      s[x] = fe_mul(e, bx[x]);  // < 2p (6*6)
       e = fe_add(e, dl);
     };
     Unroll<0, NH>::run(f1);
-    src.get(ra, 4, lo, dl);  // qL
-    ra = src.issue(5);  // qR
+    src.getl(rl, 4, lo, dl);  // qL
+    typename Src::Raw rq = src.issue(7);   // qC
     e = lo;
     auto f2 = [&](auto x) __attribute__((always_inline)) {
-      t[x] = fe_add(t[x], e);  // < 6p
+      s[x] = fe_add(s[x], e);  // < 8p
       e = fe_add(e, dl);
     };
     Unroll<0, NH>::run(f2);
-    src.get(rb, 0, lo, dl);  // a
-    rb = src.issue(6);  // qO
-    e = lo;
+    Fe ea, da, er5, dr5, eo, dlo, ec, dc;
+    src.getl(ra, 0, ea, da);    // a
+    src.getl(rr, 5, er5, dr5);  // qR
+    src.getl(ro, 6, eo, dlo);   // qO
+    src.getl(rc, 2, ec, dc);    // c
     auto f3 = [&](auto x) __attribute__((always_inline)) {
-      t[x] = fe_mul(e, t[x]);  // < 2p (4*6)
-      e = fe_add(e, dl);
+      const Fe fa[3] = {ea, er5, eo};
+      const Fe fb2[3] = {s[x], bx[x], ec};
+      s[x] = fe_sop<3>(fa, fb2);  // a s + qR b + qO c < 2p (6*8 + 6*6 + 6*6 = 120)
+      ea = fe_add(ea, da);
+      er5 = fe_add(er5, dr5);
+      eo = fe_add(eo, dlo);
+      ec = fe_add(ec, dc);
     };
     Unroll<0, NH>::run(f3);
-    src.get(ra, 5, lo, dl);  // qR
-    ra = src.issue(2);  // c
-    e = lo;
-    auto f4 = [&](auto x) __attribute__((always_inline)) {
-      t[x] = fe_add(t[x], fe_mul(e, bx[x]));  // < 4p
-      e = fe_add(e, dl);
-    };
-    Unroll<0, NH>::run(f4);
-    Fe lo2, dl2, e2;
-    src.get(rb, 6, lo, dl);    // qO
-    src.get(ra, 2, lo2, dl2);  // c
-    rb = src.issue(7);  // qC
-    e = lo;
-    e2 = lo2;
-    auto f5 = [&](auto x) __attribute__((always_inline)) {
-      t[x] = fe_add(t[x], fe_mul(e, e2));  // < 6p
-      e = fe_add(e, dl);
-      e2 = fe_add(e2, dl2);
-    };
-    Unroll<0, NH>::run(f5);
-    src.get(rb, 7, lo, dl);  // qC
+    src.getl(rq, 7, lo, dl);  // qC
     const Fe E = resolve_eq(er);
     e = lo;
     auto f6 = [&](auto x) __attribute__((always_inline)) {
-      const Fe f = fe_add(t[x], e);                         // f < 10p
-      acc[x] = fe_csub(fe_add(acc[x], fe_mul(f, E)), kP2);  // product < 2p; acc < 2p
+      const Fe f = fe_add(s[x], e);           // < 8p
+      acc[x] = fe_add(acc[x], fe_mul(f, E));  // product < 2p (8*1)
       e = fe_add(e, dl);
     };
     Unroll<0, NH>::run(f6);
@@ -280,7 +290,8 @@ struct GateProd {
   }
   template <class Src>
   __device__ static __forceinline__ void eval(const Src& src, const EqRows& er, Fe (&acc)[NH]) {
-    // extensions at X <= m+1 are < (m+2) p <= 10 p
+    // s and w1 with strict differences (extensions at X <= m+1 < (m+2) p <= 10p,
+    // so their product fits: 10*10), the other tables lazy (< 2(m+1) p <= 18p)
     Fe pr[NH], lo, dl, e;
     typename Src::Raw cur = src.issue(0);  // s
     typename Src::Raw nxt = src.issue(1);  // w1
@@ -290,10 +301,13 @@ struct GateProd {
     };
     Unroll<0, NH>::run(f0);
 #pragma unroll 1
-    for (int k = 1; k <= M; ++k) {  // pr *= w_k  (< 2p after each product: 10*10, then 2*10)
+    for (int k = 1; k <= M; ++k) {  // pr *= w_k  (< 2p after each product: 10*10, then 2*18)
       cur = nxt;
       nxt = src.issue(k + 1);  // w_{k+1}, or o after the last w
-      src.get(cur, k, lo, dl);
+      if (k == 1)
+        src.get(cur, k, lo, dl);
+      else
+        src.getl(cur, k, lo, dl);
       e = lo;
       auto fk = [&](auto x) __attribute__((always_inline)) {
         pr[x] = fe_mul(pr[x], e);
@@ -301,12 +315,12 @@ struct GateProd {
       };
       Unroll<0, NH>::run(fk);
     }
-    src.get(nxt, M + 1, lo, dl);  // o: pr + 11p - o in (0, 13p) -> < 8p
+    src.getl(nxt, M + 1, lo, dl);  // o (< 18p): pr + 18p - o < 20p
     const Fe E = resolve_eq(er);
     e = lo;
     auto fo = [&](auto x) __attribute__((always_inline)) {
-      const Fe f = fe_csub(fe_sub_plus(pr[x], e, kP11), kP8);
-      acc[x] = fe_csub(fe_add(acc[x], fe_mul(f, E)), kP2);  // product < 2p (8*1); acc < 2p
+      const Fe f = fe_sub_plus(pr[x], e, kP18);
+      acc[x] = fe_add(acc[x], fe_mul(f, E));  // product < 2p (20*1)
       e = fe_add(e, dl);
     };
     Unroll<0, NH>::run(fo);
@@ -334,11 +348,11 @@ struct GateSum {
   }
   template <class Src>
   __device__ static __forceinline__ void eval(const Src& src, const EqRows& er, Fe (&acc)[NH]) {
-    // extensions at X <= P are < (P+1) p <= 5p
+    // lazy differences: extensions at X <= P are < 2P p <= 8p
     Fe f[NH], lo, dl;
     typename Src::Raw cur = src.issue(0);
     typename Src::Raw nxt = src.issue(1);
-    src.get(cur, 0, lo, dl);
+    src.getl(cur, 0, lo, dl);
     auto f0 = [&](auto x) __attribute__((always_inline)) {
       f[x] = (x == 0) ? lo : fe_add(f[x > 0 ? x - 1 : 0], dl);
     };
@@ -346,13 +360,13 @@ struct GateSum {
     auto step = [&](auto k) __attribute__((always_inline)) {
       cur = nxt;
       if (k + 1 < K) nxt = src.issue(k + 1 < K ? k + 1 : 0);
-      src.get(cur, k, lo, dl);
+      src.getl(cur, k, lo, dl);
       Fe e = lo;
       auto px = [&](auto x) __attribute__((always_inline)) {
         if (k < P)
-          f[x] = fe_mul(f[x], e);  // < 2p
+          f[x] = fe_mul(f[x], e);  // < 2p (8*8, then 2*8)
         else
-          f[x] = fe_add(f[x], e);  // < 17p after A additions
+          f[x] = fe_add(f[x], e);  // < 26p after A <= 3 additions
         e = fe_add(e, dl);
       };
       Unroll<0, NH>::run(px);
@@ -360,7 +374,7 @@ struct GateSum {
     Unroll<1, K>::run(step);
     const Fe E = resolve_eq(er);
     auto fo = [&](auto x) __attribute__((always_inline)) {
-      acc[x] = fe_csub(fe_add(acc[x], fe_mul(f[x], E)), kP2);  // product < 2p (17*1); acc < 2p
+      acc[x] = fe_add(acc[x], fe_mul(f[x], E));  // product < 2p (26*1)
     };
     Unroll<0, NH>::run(fo);
   }
@@ -666,6 +680,10 @@ __device__ __forceinline__ void emit_round(Ctrl* ctrl, uint32_t round, uint32_t 
 //
 // The body is shared with the batched kernel: block `blk` of the `nblk`
 // blocks working on this round.
+// Pairs a thread adds to its sums before bringing them back below 2p: each
+// pair adds < 2p, so they stay < 2p + 32 * 2p < 128p.
+constexpr uint32_t kLazyPairs = 32;
+
 template <class Gate, bool FOLD>
 __device__ __forceinline__ void round_body(const RoundArgs& a, const TabPtrs& src, const TabPtrs& dst, uint32_t blk,
                                            uint32_t nblk) {
@@ -673,40 +691,44 @@ __device__ __forceinline__ void round_body(const RoundArgs& a, const TabPtrs& sr
   Fe acc[NH];
   auto z = [&](auto x) __attribute__((always_inline)) { acc[x] = fe_zero(); };
   Unroll<0, NH>::run(z);
+  auto lower = [&](auto x) __attribute__((always_inline)) { acc[x] = fe_reduce128_to2(acc[x]); };
 
   {
     Fe alpha;
     if (FOLD) alpha = load_words_fe(a.ctrl->alpha_m[a.round - 2]);
     const uint32_t q = (uint32_t)a.q;
     const uint32_t stride = nblk * blockDim.x;
-    for (uint32_t j = blk * blockDim.x + threadIdx.x; j < q; j += stride) {
-      const EqRows er = issue_eq(a.eq, a.round, j);
-      if (FOLD && Gate::kFoldInGate) {
-        Gate::eval(FoldSrc{src, dst, a.src_pitch, a.dst_pitch, j, q, alpha}, er, acc);
-      } else if (FOLD) {
-        // fold every table first (a rolled loop: one copy of the code), then
-        // evaluate on the folded pairs, which the L2 still holds
-        const uint64_t sp = a.src_pitch, dp = a.dst_pitch;
-        RawPair n01 = issue_pair(src.p[0], sp, j, q), n23 = issue_pair(src.p[0], sp, j + 2 * q, q);
+    // chunks of kLazyPairs pairs per thread, the sums lowered after each
+    for (uint32_t j0 = blk * blockDim.x + threadIdx.x; j0 < q; j0 += kLazyPairs * stride) {
+      const uint32_t jend = (uint32_t)min((uint64_t)q, (uint64_t)j0 + (uint64_t)kLazyPairs * stride);
+      for (uint32_t j = j0; j < jend; j += stride) {
+        const EqRows er = issue_eq(a.eq, a.round, j);
+        if (FOLD && Gate::kFoldInGate) {
+          Gate::eval(FoldSrc{src, dst, a.src_pitch, a.dst_pitch, j, q, alpha}, er, acc);
+        } else if (FOLD) {
+          // fold every table first (a rolled loop: one copy of the code), then
+          // evaluate on the folded pairs, which the L2 still holds
+          const uint64_t sp = a.src_pitch, dp = a.dst_pitch;
+          RawPair n01 = issue_pair(src.p[0], sp, j, q), n23 = issue_pair(src.p[0], sp, j + 2 * q, q);
 #pragma unroll 1
-        for (int t = 0; t < Gate::K; ++t) {
-          const RawPair c01 = n01, c23 = n23;
-          if (t + 1 < Gate::K) {
-            n01 = issue_pair(src.p[t + 1], sp, j, q);
-            n23 = issue_pair(src.p[t + 1], sp, j + 2 * q, q);
+          for (int t = 0; t < Gate::K; ++t) {
+            const RawPair c01 = n01, c23 = n23;
+            if (t + 1 < Gate::K) {
+              n01 = issue_pair(src.p[t + 1], sp, j, q);
+              n23 = issue_pair(src.p[t + 1], sp, j + 2 * q, q);
+            }
+            store_el(dst.p[t], dp, j, fe_lerp(fe_from_words(c01.w0), fe_from_words(c23.w0), alpha));
+            store_el(dst.p[t], dp, j + q, fe_lerp(fe_from_words(c01.w1), fe_from_words(c23.w1), alpha));
           }
-          const Fe a0 = fe_from_words(c01.w0), a1 = fe_from_words(c01.w1);
-          const Fe a2 = fe_from_words(c23.w0), a3 = fe_from_words(c23.w1);
-          store_el(dst.p[t], dp, j, fe_addmod(a0, fe_reduce2(fe_mul(alpha, fe_submod(a2, a0)))));
-          store_el(dst.p[t], dp, j + q, fe_addmod(a1, fe_reduce2(fe_mul(alpha, fe_submod(a3, a1)))));
+          Gate::eval(PairSrc{dst, dp, j, q}, er, acc);
+        } else {
+          Gate::eval(PairSrc{src, a.src_pitch, j, q}, er, acc);
         }
-        Gate::eval(PairSrc{dst, dp, j, q}, er, acc);
-      } else {
-        Gate::eval(PairSrc{src, a.src_pitch, j, q}, er, acc);
       }
+      Unroll<0, NH>::run(lower);
     }
   }
-  auto red = [&](auto x) __attribute__((always_inline)) { acc[x] = fe_reduce2(acc[x]); };
+  auto red = [&](auto x) __attribute__((always_inline)) { acc[x] = fe_reduce2(acc[x]); };  // < 2p after lower
   Unroll<0, NH>::run(red);
   const Fe tot = block_reduce<NH>(acc);
   if (threadIdx.x < NH) store_words_fe(a.partials + ((uint64_t)blk * NH + threadIdx.x) * 8, tot);
@@ -802,7 +824,7 @@ __device__ __forceinline__ void run_tail(const RoundArgs& a, const TabPtrs& dst,
     for (uint32_t idx = threadIdx.x; idx < K * h; idx += blockDim.x) {
       const uint32_t t = idx / h, e = idx % h;
       const Fe u0 = lds_fe(T(t, e)), u1 = lds_fe(T(t, e + h));
-      lds_put(T(t, e), fe_addmod(u0, mont(alpha, fe_submod(u1, u0))));
+      lds_put(T(t, e), fe_lerp(u0, u1, alpha));
     }
     __syncthreads();
     L = h;
@@ -863,8 +885,8 @@ __global__ __launch_bounds__(kBlock) void k_round_split(RoundArgs a, TabPtrs src
           const uint64_t sp = a.src_pitch;
           const Fe a0 = load_el(src, sp, j), a2 = load_el(src, sp, j + 2 * q);
           const Fe a1 = load_el(src, sp, j + q), a3 = load_el(src, sp, j + 3 * q);
-          u0 = fe_addmod(a0, fe_reduce2(fe_mul(alpha, fe_submod(a2, a0))));
-          u1 = fe_addmod(a1, fe_reduce2(fe_mul(alpha, fe_submod(a3, a1))));
+          u0 = fe_lerp(a0, a2, alpha);
+          u1 = fe_lerp(a1, a3, alpha);
           store_el(dst, a.dst_pitch, j, u0);
           store_el(dst, a.dst_pitch, j + q, u1);
         } else {
