@@ -832,15 +832,19 @@ __device__ __forceinline__ void run_tail(const RoundArgs& a, const TabPtrs& dst,
     const uint32_t q = L / 2;
     Fe c = fe_zero();
     if (x < (uint32_t)NH) {
-      for (uint32_t e0 = 0; e0 < q; e0 += PP) {  // uniform trip count, lanes past q idle
-        const uint32_t e = e0 + pp;
-        if (e < q) {
-          auto get = [&](int t, Fe& u0, Fe& u1) __attribute__((always_inline)) {
-            u0 = lds_fe(T(t, e));
-            u1 = lds_fe(T(t, e + q));
-          };
-          c = fe_addmod(c, mont(point_f<Gate>(get, x), lds_fe(eqrow + (q + e) * NL)));
-        }
+      // uniform trip count; lanes past q evaluate pair e mod q (q is a power
+      // of two) and drop it, so the whole wave stays active (a wave with only
+      // a few active lanes ran this loop several times slower, measured)
+      for (uint32_t e0 = 0; e0 < q; e0 += PP) {
+        const uint32_t e = (e0 + pp) & (q - 1);
+        auto get = [&](int t, Fe& u0, Fe& u1) __attribute__((always_inline)) {
+          u0 = lds_fe(T(t, e));
+          u1 = lds_fe(T(t, e + q));
+        };
+        Fe v = fe_addmod(c, mont(point_f<Gate>(get, x), lds_fe(eqrow + (q + e) * NL)));
+#pragma unroll
+        for (int i = 0; i < NL; ++i) asm volatile("" : "+v"(v.l[i]));  // computed on every lane
+        if (e0 + pp < q) c = v;
       }
     }
 #pragma unroll
