@@ -61,12 +61,22 @@ __device__ __forceinline__ const uint32_t* plane_ptr(const uint32_t* base, uint6
   return base + (uint64_t)l * pitch;
 }
 
+// NT: non-temporal access (the line is kept in the caches with low
+// priority).  Table data read or written once per round goes this way, so
+// that a round's streams do not push out what the next launches use again:
+// the finisher's code and control block, the eq tables (measured faster).
+template <bool NT = false>
 __device__ __forceinline__ void load_words(const uint32_t* __restrict__ base, uint64_t pitch, uint32_t j,
                                            uint32_t w[8]) {
   const uint32_t off = j << 2;
 #pragma unroll
-  for (int l = 0; l < 8; ++l)
-    w[l] = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(plane_ptr(base, pitch, l)) + off);
+  for (int l = 0; l < 8; ++l) {
+    const uint32_t* p = reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(plane_ptr(base, pitch, l)) + off);
+    if constexpr (NT)
+      w[l] = __builtin_nontemporal_load(p);
+    else
+      w[l] = *p;
+  }
 }
 
 __device__ __forceinline__ Fe load_el(const uint32_t* __restrict__ base, uint64_t pitch, uint32_t j) {
@@ -75,13 +85,19 @@ __device__ __forceinline__ Fe load_el(const uint32_t* __restrict__ base, uint64_
   return fe_from_words(w);
 }
 
+template <bool NT = false>
 __device__ __forceinline__ void store_el(uint32_t* __restrict__ base, uint64_t pitch, uint32_t j, const Fe& a) {
   uint32_t w[8];
   fe_to_words(a, w);
   const uint32_t off = j << 2;
 #pragma unroll
-  for (int l = 0; l < 8; ++l)
-    *reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(base + (uint64_t)l * pitch) + off) = w[l];
+  for (int l = 0; l < 8; ++l) {
+    uint32_t* p = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(base + (uint64_t)l * pitch) + off);
+    if constexpr (NT)
+      __builtin_nontemporal_store(w[l], p);
+    else
+      *p = w[l];
+  }
 }
 
 // The two entries (j, j + q) of a table, loaded but not yet converted, so that
@@ -90,11 +106,12 @@ struct RawPair {
   uint32_t w0[8], w1[8];
 };
 
+template <bool NT = false>
 __device__ __forceinline__ RawPair issue_pair(const uint32_t* __restrict__ base, uint64_t pitch, uint32_t j,
                                               uint32_t q) {
   RawPair r;
-  load_words(base, pitch, j, r.w0);
-  load_words(base, pitch, j + q, r.w1);
+  load_words<NT>(base, pitch, j, r.w0);
+  load_words<NT>(base, pitch, j + q, r.w1);
   return r;
 }
 

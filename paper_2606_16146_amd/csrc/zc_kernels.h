@@ -141,20 +141,24 @@ __device__ __forceinline__ Fe eq_factor(const EqTabs& E, uint32_t round, uint32_
 // so that the loads of the next table are in flight meanwhile.  getl() gives
 // the lazy difference of cvt_pair_lazy (dl < 2p) instead.
 
-// Tables already holding the round's 2q live entries.
-struct PairSrc {
+// Tables already holding the round's 2q live entries (NT: read them
+// non-temporally, for tables read once in the round).
+template <bool NT>
+struct PairSrcT {
   const TabPtrs& tp;
   uint64_t pitch;
   uint32_t j, q;
   using Raw = RawPair;
-  __device__ __forceinline__ Raw issue(int t) const { return issue_pair(tp.p[t], pitch, j, q); }
+  __device__ __forceinline__ Raw issue(int t) const { return issue_pair<NT>(tp.p[t], pitch, j, q); }
   __device__ __forceinline__ void get(const Raw& r, int, Fe& lo, Fe& dl) const { cvt_pair(r, lo, dl); }
   __device__ __forceinline__ void getl(const Raw& r, int, Fe& lo, Fe& dl) const { cvt_pair_lazy(r, lo, dl); }
 };
+using PairSrc = PairSrcT<false>;
 
 // Tables holding 4q entries, folded on the way with alpha_{i-1}:
 // u[j] = t[j] + alpha (t[j+2q] - t[j]), u[j+q] likewise; u is written to the
 // destination tables (the next round reads it) and used from registers.
+// Loads and stores are non-temporal.
 struct FoldSrc {
   const TabPtrs& src;
   const TabPtrs& dst;
@@ -165,13 +169,13 @@ struct FoldSrc {
     RawPair lo2, hi2;  // (t[j], t[j+q]), (t[j+2q], t[j+3q])
   };
   __device__ __forceinline__ Raw issue(int t) const {
-    return Raw{issue_pair(src.p[t], sp, j, q), issue_pair(src.p[t], sp, j + 2 * q, q)};
+    return Raw{issue_pair<true>(src.p[t], sp, j, q), issue_pair<true>(src.p[t], sp, j + 2 * q, q)};
   }
   __device__ __forceinline__ void fold(const Raw& r, int t, Fe& u0, Fe& u1) const {
     u0 = fe_lerp(fe_from_words(r.lo2.w0), fe_from_words(r.hi2.w0), alpha);
     u1 = fe_lerp(fe_from_words(r.lo2.w1), fe_from_words(r.hi2.w1), alpha);
-    store_el(dst.p[t], dp, j, u0);
-    store_el(dst.p[t], dp, j + q, u1);
+    store_el<true>(dst.p[t], dp, j, u0);
+    store_el<true>(dst.p[t], dp, j + q, u1);
   }
   __device__ __forceinline__ void get(const Raw& r, int t, Fe& lo, Fe& dl) const {
     Fe u1;
@@ -707,22 +711,23 @@ __device__ __forceinline__ void round_body(const RoundArgs& a, const TabPtrs& sr
           Gate::eval(FoldSrc{src, dst, a.src_pitch, a.dst_pitch, j, q, alpha}, er, acc);
         } else if (FOLD) {
           // fold every table first (a rolled loop: one copy of the code), then
-          // evaluate on the folded pairs, which the L2 still holds
+          // evaluate on the folded pairs, which the L2 still holds (so the
+          // sources are read non-temporally, the folded values stored normally)
           const uint64_t sp = a.src_pitch, dp = a.dst_pitch;
-          RawPair n01 = issue_pair(src.p[0], sp, j, q), n23 = issue_pair(src.p[0], sp, j + 2 * q, q);
+          RawPair n01 = issue_pair<true>(src.p[0], sp, j, q), n23 = issue_pair<true>(src.p[0], sp, j + 2 * q, q);
 #pragma unroll 1
           for (int t = 0; t < Gate::K; ++t) {
             const RawPair c01 = n01, c23 = n23;
             if (t + 1 < Gate::K) {
-              n01 = issue_pair(src.p[t + 1], sp, j, q);
-              n23 = issue_pair(src.p[t + 1], sp, j + 2 * q, q);
+              n01 = issue_pair<true>(src.p[t + 1], sp, j, q);
+              n23 = issue_pair<true>(src.p[t + 1], sp, j + 2 * q, q);
             }
             store_el(dst.p[t], dp, j, fe_lerp(fe_from_words(c01.w0), fe_from_words(c23.w0), alpha));
             store_el(dst.p[t], dp, j + q, fe_lerp(fe_from_words(c01.w1), fe_from_words(c23.w1), alpha));
           }
           Gate::eval(PairSrc{dst, dp, j, q}, er, acc);
         } else {
-          Gate::eval(PairSrc{src, a.src_pitch, j, q}, er, acc);
+          Gate::eval(PairSrcT<true>{src, a.src_pitch, j, q}, er, acc);
         }
       }
       Unroll<0, NH>::run(lower);
