@@ -60,7 +60,7 @@ int make_layout(const zc_shape* s, Layout* L) {
   L->ml = s->mu / 2;
   L->mh = s->mu - L->ml;
   const size_t n = (size_t)1 << s->mu;
-  size_t off = kCtrlBytes;
+  size_t off = align256(kCtrlBytes + kEq1Bytes);  // control block, then the eq1 rows
   L->eqrows = off;  // LO (2^ml rows) + HI heap (2^mh) + SUF heap (2^(ml+1)), 32 bytes each
   off = align256(off + (((size_t)1 << L->ml) + ((size_t)1 << L->mh) + ((size_t)2 << L->ml)) * 32);
   L->partials = off;
@@ -132,7 +132,7 @@ RoundArgs round_args(const zc_shape* s, const Layout& L, void* ws, uint32_t i,
 // r -> canonical and Montgomery copies, C_1 and coef_1, the factored eq tables.
 int launch_setup(const zc_shape* s, const Layout& L, const uint32_t* r, void* ws, hipStream_t st) {
   Ctrl* ctrl = ctrl_of(ws);
-  hipLaunchKernelGGL(k_setup, dim3(1), dim3(64), 0, st, r, s->mu, L.d + 2, ctrl);
+  hipLaunchKernelGGL(k_setup, dim3(1), dim3(kBlock), 0, st, r, s->mu, L.d + 2, ctrl);
   if (launch_ok() != ZC_OK) return ZC_EHIP;
   const uint32_t nrows = (1u << L.ml) + (1u << L.mh) + (2u << L.ml);
   uint32_t* rows = reinterpret_cast<uint32_t*>(bytes(ws) + L.eqrows);
@@ -195,7 +195,7 @@ int prove_impl(const zc_shape* shape, const uint32_t* const* tables, const uint3
 
 // ---- batches -----------------------------------------------------------------
 
-__global__ __launch_bounds__(64) void k_batch_setup(const InstDesc* __restrict__ descs) {
+__global__ __launch_bounds__(kBlock) void k_batch_setup(const InstDesc* __restrict__ descs) {
   const InstDesc& d = descs[blockIdx.x];
   setup_body(d.r, d.mu, d.ne, d.ctrl);
 }
@@ -344,7 +344,7 @@ int launch_batch_key(uint32_t key, const BatchStep& bs, uint32_t blocks, bool fo
 
 constexpr uint32_t kServeSlots = 65535;  // slot ids travel as u16
 
-__global__ __launch_bounds__(64) void k_serve_setup(InstDesc* __restrict__ pool, uint32_t slot, InstDesc d) {
+__global__ __launch_bounds__(kBlock) void k_serve_setup(InstDesc* __restrict__ pool, uint32_t slot, InstDesc d) {
   if (threadIdx.x == 0) pool[slot] = d;
   setup_body(d.r, d.mu, d.ne, d.ctrl);
 }
@@ -494,7 +494,7 @@ int zc_batch_launch(uint32_t n, const zc_instance* inst, void* batch_ws, hipStre
   if (rc != ZC_OK) return rc;
   const InstDesc* descs = reinterpret_cast<const InstDesc*>(batch_ws);
   const uint32_t* words = reinterpret_cast<const uint32_t*>(bytes(batch_ws) + desc_bytes(n));
-  hipLaunchKernelGGL(k_batch_setup, dim3(n), dim3(64), 0, stream, descs);
+  hipLaunchKernelGGL(k_batch_setup, dim3(n), dim3(kBlock), 0, stream, descs);
   if ((rc = launch_ok()) != ZC_OK) return rc;
   hipLaunchKernelGGL(k_batch_eq, dim3((P.max_eq_rows + kBlock - 1) / kBlock + 1, n), dim3(kBlock), 0, stream, descs);
   if ((rc = launch_ok()) != ZC_OK) return rc;
@@ -527,7 +527,7 @@ int zc_serve_admit(void* pool, uint32_t slots, uint32_t slot, const zc_instance*
   int rc = check_instance(*inst, &L);
   if (rc != ZC_OK) return rc;
   const InstDesc d = make_desc(*inst, L, last_round(inst->shape.mu));
-  hipLaunchKernelGGL(k_serve_setup, dim3(1), dim3(64), 0, stream, reinterpret_cast<InstDesc*>(pool), slot, d);
+  hipLaunchKernelGGL(k_serve_setup, dim3(1), dim3(kBlock), 0, stream, reinterpret_cast<InstDesc*>(pool), slot, d);
   if ((rc = launch_ok()) != ZC_OK) return rc;
   const uint32_t nrows = (1u << L.ml) + (1u << L.mh) + (2u << L.ml);
   hipLaunchKernelGGL(k_serve_eq, dim3((nrows + kBlock - 1) / kBlock + 1), dim3(kBlock), 0, stream, d);

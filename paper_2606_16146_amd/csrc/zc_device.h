@@ -41,6 +41,25 @@ struct Ctrl {
 constexpr uint32_t kCtrlBytes = 4096;
 static_assert(sizeof(Ctrl) <= kCtrlBytes, "control block size");
 
+// The eq1 factors of every round, computed once from r at setup; the
+// workspace holds kMuMax of these rows right after the control block.  Row i
+// belongs to r_{i+1}.  With NE = d + 2 and NC = 2d + 3 slots:
+constexpr int kEq1Slots = 2 * kMaxEvals - 1;
+struct Eq1Row {
+  uint32_t c[kEq1Slots][8];  // eq1(x, r) for x < NE, then eq1(d+1, r) lam_k (k <= d): canonical, < p
+  uint32_t m[kEq1Slots][8];  // the same values in Montgomery form
+  uint32_t omr[8];           // 1 - r, Montgomery form
+  uint32_t tr[8];            // 2 r - 1, Montgomery form
+};
+constexpr size_t kEq1Bytes = sizeof(Eq1Row) * kMuMax;
+
+__device__ __forceinline__ Eq1Row* eq1_rows(Ctrl* c) {
+  return reinterpret_cast<Eq1Row*>(reinterpret_cast<char*>(c) + kCtrlBytes);
+}
+__device__ __forceinline__ const Eq1Row* eq1_rows(const Ctrl* c) {
+  return reinterpret_cast<const Eq1Row*>(reinterpret_cast<const char*>(c) + kCtrlBytes);
+}
+
 struct TabPtrs {
   uint32_t* p[kMaxTables];
 };

@@ -446,41 +446,6 @@ struct RoundArgs {
   EqTabs eq;
 };
 
-// (-1)^(d-k) C(d+1, k) in Montgomery form: H(d+1) = sum_k lam_k H(k) for any
-// polynomial H of degree <= d (its (d+1)-th finite difference vanishes).
-template <int D>
-struct Extrap {
-  L9 lam[D + 1];
-  constexpr Extrap() : lam{} {
-    for (int k = 0; k <= D; ++k) {
-      uint64_t c = 1;  // C(D+1, k)
-      for (int t = 0; t < k; ++t) c = c * (uint64_t)(D + 1 - t) / (uint64_t)(t + 1);
-      L9 v{};
-      for (uint64_t t = 0; t < c; ++t) {  // c * R mod p by repeated modular addition
-        v = detail::add(v, kOne);
-        if (detail::geq(v, kP)) v = detail::sub(v, kP);
-      }
-      if ((D - k) % 2 == 1) v = detail::sub(kP, v);  // c > 0 and c R mod p != 0, so p - v < p
-      lam[k] = v;
-    }
-  }
-};
-
-// eq1(x, r) = (1 - r) + x (2r - 1) for a small integer x (<= 15).  With
-// one = 1 (r canonical) the result is canonical; with one = R (r in
-// Montgomery form) it is in Montgomery form.
-__device__ __forceinline__ Fe eq1_small(const Fe& r, uint32_t x, const Fe& one) {
-  const Fe omr = fe_submod(one, r);
-  const Fe step = fe_submod(fe_addmod(r, r), one);
-  return fe_addmod(omr, fe_reduce32(fe_mul_small(step, x)));
-}
-
-__device__ __forceinline__ Fe fe_one_plain() {
-  Fe one = fe_zero();
-  one.l[0] = 1;
-  return one;
-}
-
 // Montgomery product reduced below p.
 __device__ __forceinline__ Fe mont(const Fe& a, const Fe& b) { return fe_reduce2(fe_mul(a, b)); }
 
@@ -510,7 +475,9 @@ __device__ __forceinline__ Fe fe_vgpr(Fe a) {
 //   coef_{i+1}[x]  = U_x + mont(alpha_i, V_x),  U_x = P e_x,  V_x = (Q e_x) R,
 //   coefl_{i+1}[k] = Ul_k + mont(alpha_i, Vl_k),
 //   C_{i+1} R      = P R + mont(alpha_i, Q R^2),
-// with e_x = eq1(x, r_{i+1}) and alpha_i canonical (mont(a, bR) = ab).
+// with e_x = eq1(x, r_{i+1}) and alpha_i canonical (mont(a, bR) = ab).  The
+// factors that depend on r only (e_x, e_{d+1} lam_k, 1 - r_i, 2 r_i - 1) come
+// from the eq1 rows filled at setup, so the idle wave does two products.
 
 template <int D>
 struct FinLds {
@@ -555,7 +522,6 @@ __device__ __forceinline__ void emit_round(Ctrl* ctrl, uint32_t round, uint32_t 
   constexpr int NH = D + 1, NE = D + 2, NC = FinLds<D>::NC;
   constexpr uint32_t LEN = FinLds<D>::LEN, NB = FinLds<D>::NB;
   static_assert(NH <= 16, "one 16-lane group");
-  constexpr Extrap<D> ex{};
   const uint32_t t = threadIdx.x;
   // lanes x <= d: G(x) = coef[x] H(x) and the term coefl[x] H(x) of G(d+1)
   // = sum_x coefl[x] H(x), summed over the 16-lane group by shuffles
@@ -602,33 +568,18 @@ __device__ __forceinline__ void emit_round(Ctrl* ctrl, uint32_t round, uint32_t 
       S.ac[k] = w[k];
     }
   } else if (t >= 192 && t < 192 + (uint32_t)NC + 1) {
-    // next round's precomputation, overlapping the compression
+    // next round's precomputation from the eq1 rows, overlapping the compression
     const uint32_t l = t - 192;
-    const Fe one_m = fe_const(kOne);
+    const Eq1Row* rows = eq1_rows(ctrl);
     const Fe cm = fe_vgpr(lds_fe(S.cm));
-    const Fe rm = load_words_fe(ctrl->r_m[round - 1]);
-    const Fe P = mont(cm, fe_submod(one_m, rm));
-    const Fe Q = mont(cm, fe_submod(fe_addmod(rm, rm), one_m));
+    const Fe P = mont(cm, load_words_fe(rows[round - 1].omr));
+    const Fe Q = mont(cm, load_words_fe(rows[round - 1].tr));
     if (l == (uint32_t)NC) {
       lds_put(S.pc, P);
       lds_put(S.q2, fe_to_mont(Q));
     } else if (round < mu) {
-      const Fe rn_c = load_words_fe(ctrl->r_c[round]);
-      const Fe rn_m = load_words_fe(ctrl->r_m[round]);
-      const uint32_t x = l < (uint32_t)NE ? l : (uint32_t)(D + 1);
-      Fe U = mont(P, eq1_small(rn_c, x, fe_one_plain()));
-      Fe V = mont(Q, eq1_small(rn_m, x, one_m));
-      if (l >= (uint32_t)NE) {
-        Fe lam = fe_zero();
-        auto pick = [&](auto k) __attribute__((always_inline)) {
-          if (l - NE == (uint32_t)k) lam = fe_const(ex.lam[k]);
-        };
-        Unroll<0, NH>::run(pick);
-        U = mont(U, lam);
-        V = mont(V, lam);
-      }
-      lds_put(S.u[l], U);
-      lds_put(S.v[l], V);
+      lds_put(S.u[l], mont(P, load_words_fe(rows[round].c[l])));
+      lds_put(S.v[l], mont(Q, load_words_fe(rows[round].m[l])));
     }
   }
   __syncthreads();
@@ -940,20 +891,23 @@ __device__ __forceinline__ void finish_body(const RoundArgs& a, const TabPtrs& d
     if (!ok) set_error(a.ctrl, -5);
   }
   fin_load<Gate::D>(a.ctrl, S);
-  // point x = t / 16: its 16 lanes stride over the partials (each < p),
-  // lazily summed (at most kMaxBlocks / 16 = 128 terms, < 128 p), reduced,
-  // then combined across the group by shuffles
-  static_assert(NH * 16 <= kBlock, "16 lanes per point");
-  const uint32_t x = t >> 4, g = t & 15;
+  // point x = t / LP: its LP lanes (the whole block shared by the points,
+  // rounded to powers of two) stride over the partials (each < p), lazily
+  // summed (at most kMaxBlocks / LP <= 128 terms, < 128 p), reduced, then
+  // combined across the group by shuffles
+  constexpr uint32_t NHP = NH <= 4 ? 4u : (NH <= 8 ? 8u : 16u);
+  constexpr uint32_t LP = kBlock / NHP;
+  static_assert(NH <= 16 && NHP * LP == kBlock && LP <= 64 && kMaxBlocks / LP <= 128, "lanes per point");
+  const uint32_t x = t / LP, g = t % LP;
   Fe v = fe_zero();
   if (x < (uint32_t)NH) {
 #pragma unroll 4
-    for (uint32_t b = g; b < a.nparts; b += 16) v = fe_add(v, load_words_fe(a.partials + ((uint64_t)b * NH + x) * 8));
+    for (uint32_t b = g; b < a.nparts; b += LP) v = fe_add(v, load_words_fe(a.partials + ((uint64_t)b * NH + x) * 8));
     v = fe_reduce128(v);
   }
 #pragma unroll
-  for (int msk = 8; msk >= 1; msk >>= 1) v = fe_add(v, shfl_xor_fe(v, msk));  // < 16 p
-  if (x < (uint32_t)NH && g == 0) lds_put(S.h[x], fe_reduce32(v));
+  for (uint32_t msk = LP / 2; msk >= 1; msk >>= 1) v = fe_add(v, shfl_xor_fe(v, (int)msk));  // < LP p <= 64 p
+  if (x < (uint32_t)NH && g == 0) lds_put(S.h[x], fe_reduce128(v));
   __syncthreads();
   if (S.skip) return;
   emit_round<Gate::D>(a.ctrl, a.round, a.mu, S, a.evals_out, a.alpha_out);

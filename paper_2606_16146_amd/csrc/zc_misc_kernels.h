@@ -24,8 +24,9 @@ __device__ __forceinline__ Fe lam_mont(uint32_t d, uint32_t k) {
 }
 
 // One block: resets the control block, checks r, keeps it in canonical and
-// Montgomery form, sets C_1 = 1, coef_1[x] = eq1(x, r_1) for x < ne and
-// coefl_1.  (T_0 is hashed by t0_body, in the launch that follows.)
+// Montgomery form, sets C_1 = 1, fills the eq1 rows of every round and
+// from row 1 coef_1[x] = eq1(x, r_1) for x < ne and coefl_1.  (T_0 is hashed
+// by t0_body, in the launch that follows.)
 __device__ __forceinline__ void setup_body(const uint32_t* __restrict__ r, uint32_t mu, uint32_t ne, Ctrl* ctrl) {
   if (threadIdx.x == 0) {
     ctrl->err = 0;
@@ -44,29 +45,36 @@ __device__ __forceinline__ void setup_body(const uint32_t* __restrict__ r, uint3
     if (!words_lt_p(w)) set_error(ctrl, -4);
     store_words_fe(ctrl->r_m[i], fe_to_mont(fe_from_words(w)));
   }
-  if (threadIdx.x < 2 * ne - 1) {
-    // coef_1[x] = C_1 eq1(x, r_1) = (1 - r_1) + x (2 r_1 - 1) (x < ne), and
-    // coefl_1[k] = coef_1[d+1] lam_k (k <= d), canonical
+  // eq1 rows: slot l < nc of round i is eq1(x, r_i) = (1 - r_i) + x (2 r_i - 1)
+  // (x = l < ne, else x = d+1 times lam_{l-ne}); slots nc, nc+1 are 1 - r_i and
+  // 2 r_i - 1.  Round 1's slots l < nc are also coef_1 and coefl_1 (C_1 = 1).
+  const uint32_t nc = 2 * ne - 1, d = ne - 2, ns = nc + 2;
+  Eq1Row* rows = eq1_rows(ctrl);
+  for (uint32_t idx = threadIdx.x; idx < mu * ns; idx += blockDim.x) {
+    const uint32_t i = idx / ns, l = idx % ns;
     uint32_t w[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) w[k] = r[k];
+    for (int k = 0; k < 8; ++k) w[k] = r[i * 8 + k];
     Fe rc = fe_from_words(w);
     if (!words_lt_p(w)) rc = fe_zero();  // flagged above; keep the arithmetic in range
     Fe one = fe_zero();
     one.l[0] = 1;
-    const uint32_t x = threadIdx.x < ne ? threadIdx.x : ne - 1;
+    const Fe omr = fe_submod(one, rc);
     const Fe step = fe_submod(fe_addmod(rc, rc), one);
-    Fe e = fe_addmod(fe_submod(one, rc), fe_reduce32(fe_mul_small(step, x)));
-    if (threadIdx.x < ne) {
-      store_words_fe(ctrl->coef[threadIdx.x], e);
+    if (l < nc) {
+      const uint32_t x = l < ne ? l : d + 1;
+      Fe e = fe_addmod(omr, fe_reduce32(fe_mul_small(step, x)));
+      if (l >= ne) e = fe_reduce2(fe_mul(e, lam_mont(d, l - ne)));
+      store_words_fe(rows[i].c[l], e);
+      store_words_fe(rows[i].m[l], fe_to_mont(e));
+      if (i == 0) store_words_fe(l < ne ? ctrl->coef[l] : ctrl->coefl[l - ne], e);
     } else {
-      const uint32_t d = ne - 2, k = threadIdx.x - ne;
-      store_words_fe(ctrl->coefl[k], fe_reduce2(fe_mul(e, lam_mont(d, k))));
+      store_words_fe(l == nc ? rows[i].omr : rows[i].tr, fe_to_mont(l == nc ? omr : step));
     }
   }
 }
 
-__global__ __launch_bounds__(64) void k_setup(const uint32_t* __restrict__ r, uint32_t mu, uint32_t ne, Ctrl* ctrl) {
+__global__ __launch_bounds__(kBlock) void k_setup(const uint32_t* __restrict__ r, uint32_t mu, uint32_t ne, Ctrl* ctrl) {
   setup_body(r, mu, ne, ctrl);
 }
 
