@@ -20,6 +20,7 @@ The JSON line also carries
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import os
 import statistics
@@ -127,7 +128,7 @@ def run_workload(name, steps, warmup, cpu_baseline):
     # are reported separately, and the rest of a proof (setup, the one-block
     # finishers with their SHA-256 and the tail) is what round_kernels_share
     # leaves.
-    kinds = [zc.lib().zc_prove_round_kernel(mu, i) for i in range(1, mu + 1)]
+    kinds = [zc.lib().zc_prove_round_kernel(ctypes.byref(s), i) for i in range(1, mu + 1)]
     fused_t, fused_b, fused_p, first_t, split_t = 0.0, 0, 0, 0.0, 0.0
     launches = 0
     for st in range(steps):

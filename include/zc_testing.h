@@ -44,11 +44,11 @@ int zc_prove_profiled(const zc_shape* shape, const uint32_t* const* tables, cons
                       uint32_t* round_evals, uint32_t* challenges, uint32_t* openings, void* events,
                       hipStream_t stream);
 
-/* Which kernel zc_prove uses for round i of a mu-variable proof:
+/* Which kernel zc_prove uses for round i (1..mu) of a proof of this shape:
    0 one thread per pair, 1 sixteen lanes per pair, 2 sixteen lanes per pair
    whose finisher then runs all later rounds and the openings in one block,
-   3 a round run inside such a tail.  Negative zc_status for bad arguments. */
-int zc_prove_round_kernel(uint32_t mu, uint32_t i);
+   3 a round run inside such a tail.  Negative zc_status for a bad shape or i. */
+int zc_prove_round_kernel(const zc_shape* shape, uint32_t i);
 
 /* SHA-256 of len bytes (msg: little-endian packed uint32 words); out: 32 bytes as uint32[8]. */
 int zc_test_sha256(const uint32_t* msg, uint32_t len, uint32_t* out, hipStream_t stream);

@@ -173,7 +173,7 @@ int prove_impl(const zc_shape* shape, const uint32_t* const* tables, const uint3
 
   if ((rc = launch_setup(shape, L, r, ws, stream)) != ZC_OK) return rc;
   for (uint32_t i = 1; i <= mu; ++i) {
-    const RoundKind kind = prove_round_kind(mu, i);
+    const RoundKind kind = prove_round_kind(mu, i, L.d);
     if (kind == kInTail) {  // evaluated inside the tail of an earlier launch
       if (ev && (hipEventRecord(ev[2 * (i - 1)], stream) != hipSuccess ||
                  hipEventRecord(ev[2 * (i - 1) + 1], stream) != hipSuccess))
@@ -447,7 +447,7 @@ int zc_round(const zc_shape* shape, const uint32_t* const* tables, const uint32_
   }
   RoundArgs a = round_args(shape, L, ws, i, round_evals, challenges);
   a.src_pitch = a.dst_pitch = n;
-  return dispatch_round(shape, false, a.q > kSplitQ ? kPerPair : kSplit, a, cur, cur, stream);
+  return dispatch_round(shape, false, a.q > split_q(L.d) ? kPerPair : kSplit, a, cur, cur, stream);
 }
 
 int zc_fold(const zc_shape* shape, uint32_t* const* tables, void* ws, uint32_t i, hipStream_t stream) {
@@ -585,9 +585,12 @@ int zc_read_error(void* ws, hipStream_t stream) {
   return (int)(int32_t)err;
 }
 
-int zc_prove_round_kernel(uint32_t mu, uint32_t i) {
-  if (mu < 1 || mu > (uint32_t)kMuMax || i < 1 || i > mu) return ZC_EINVAL;
-  return (int)prove_round_kind(mu, i);
+int zc_prove_round_kernel(const zc_shape* shape, uint32_t i) {
+  Layout L;
+  const int rc = make_layout(shape, &L);
+  if (rc != ZC_OK) return rc;
+  if (i < 1 || i > shape->mu) return ZC_EINVAL;
+  return (int)prove_round_kind(shape->mu, i, L.d);
 }
 
 const char* zc_strerror(int status) {

@@ -470,8 +470,8 @@ __device__ __forceinline__ Fe fe_vgpr(Fe a) {
 // The coefficients of round i+1 depend on alpha_i only through
 // C_{i+1} = C_i eq1(alpha_i, r_i) = P + alpha_i Q, P = C_i (1 - r_i),
 // Q = C_i (2 r_i - 1).  Everything except the final product with alpha_i is
-// computed by an otherwise idle wave while lane 0 runs the SHA-256
-// compression, so after the hash each coefficient costs one product:
+// computed by an otherwise idle wave before the SHA-256 compression, so after
+// the hash each coefficient costs one product:
 //   coef_{i+1}[x]  = U_x + mont(alpha_i, V_x),  U_x = P e_x,  V_x = (Q e_x) R,
 //   coefl_{i+1}[k] = Ul_k + mont(alpha_i, Vl_k),
 //   C_{i+1} R      = P R + mont(alpha_i, Q R^2),
@@ -550,6 +550,22 @@ __device__ __forceinline__ void emit_round(Ctrl* ctrl, uint32_t round, uint32_t 
         evals_out[NH * 8 + k] = w[k];
       }
     }
+  } else if (t >= 192 && t < 192 + (uint32_t)NC + 1) {
+    // next round's precomputation from the eq1 rows, by an otherwise idle wave
+    // while G is formed and the message expanded, so that the compression
+    // runs alone
+    const uint32_t l = t - 192;
+    const Eq1Row* rows = eq1_rows(ctrl);
+    const Fe cm = fe_vgpr(lds_fe(S.cm));
+    const Fe P = mont(cm, load_words_fe(rows[round - 1].omr));
+    const Fe Q = mont(cm, load_words_fe(rows[round - 1].tr));
+    if (l == (uint32_t)NC) {
+      lds_put(S.pc, P);
+      lds_put(S.q2, fe_to_mont(Q));
+    } else if (round < mu) {
+      lds_put(S.u[l], mont(P, load_words_fe(rows[round].c[l])));
+      lds_put(S.v[l], mont(Q, load_words_fe(rows[round].m[l])));
+    }
   }
   __syncthreads();
   sha256_schedule_block<LEN>(S.msg, S.kw);
@@ -566,20 +582,6 @@ __device__ __forceinline__ void emit_round(Ctrl* ctrl, uint32_t round, uint32_t 
     for (int k = 0; k < 8; ++k) {
       S.dg[k] = dg[k];
       S.ac[k] = w[k];
-    }
-  } else if (t >= 192 && t < 192 + (uint32_t)NC + 1) {
-    // next round's precomputation from the eq1 rows, overlapping the compression
-    const uint32_t l = t - 192;
-    const Eq1Row* rows = eq1_rows(ctrl);
-    const Fe cm = fe_vgpr(lds_fe(S.cm));
-    const Fe P = mont(cm, load_words_fe(rows[round - 1].omr));
-    const Fe Q = mont(cm, load_words_fe(rows[round - 1].tr));
-    if (l == (uint32_t)NC) {
-      lds_put(S.pc, P);
-      lds_put(S.q2, fe_to_mont(Q));
-    } else if (round < mu) {
-      lds_put(S.u[l], mont(P, load_words_fe(rows[round].c[l])));
-      lds_put(S.v[l], mont(Q, load_words_fe(rows[round].m[l])));
     }
   }
   __syncthreads();

@@ -18,16 +18,20 @@ struct ServeStep;
 
 // Rounds with more pairs than this run one thread per pair (k_round); the
 // others run 16 lanes per pair (k_round_split).
-constexpr uint64_t kSplitQ = 16384;
 constexpr int kTailQ = 32;  // the tail runs rounds with at most this many pairs
+
+// Rounds with at most this many pairs use sixteen lanes per pair.  One thread
+// per pair is the faster of the two down to 16384 pairs for the gates of
+// degree > 3 and down to 8192 for the lighter ones (measured at mu = 20).
+inline uint64_t split_q(uint32_t degree) { return degree <= 3 ? 8192u : 16384u; }
 
 enum RoundKind { kPerPair = 0, kSplit = 1, kSplitTail = 2, kInTail = 3 };
 
 // Which kernel evaluates round i of a whole proof (zc_prove).
-inline RoundKind prove_round_kind(uint32_t mu, uint32_t i) {
+inline RoundKind prove_round_kind(uint32_t mu, uint32_t i, uint32_t degree) {
   const uint64_t q = 1ull << (mu - i);
   const uint64_t first_tail_q = 2 * (uint64_t)kTailQ;
-  if (q > kSplitQ) return kPerPair;
+  if (q > split_q(degree)) return kPerPair;
   if (q > first_tail_q) return kSplit;
   // the first round with q <= 2 kTailQ launches the tail; later rounds run inside it
   const uint64_t prev_q = q * 2;

@@ -54,7 +54,7 @@ _SIGS = {
     "zc_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "zc_test_field": (ctypes.c_int, [ctypes.c_int, _VP, _VP, _VP, ctypes.c_uint64, _VP]),
     "zc_test_sha256": (ctypes.c_int, [_VP, ctypes.c_uint32, _VP, _VP]),
-    "zc_prove_round_kernel": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32]),
+    "zc_prove_round_kernel": (ctypes.c_int, [ctypes.POINTER(Shape), ctypes.c_uint32]),
     "zc_prove_profiled": (ctypes.c_int, [ctypes.POINTER(Shape), _VP, _VP, _VP, _VP, _VP, _VP, _VP,
                                          _VP]),
     "zc_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_uint32]),

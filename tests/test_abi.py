@@ -74,15 +74,20 @@ def test_strerror_covers_every_status():
 def test_round_kernel_schedule_is_consistent():
     """Every round of a proof is either launched or covered by exactly one tail."""
     h = zc.lib()
-    for mu in range(1, 31):
-        kinds = [h.zc_prove_round_kernel(mu, i) for i in range(1, mu + 1)]
-        assert kinds.count(2) == 1, (mu, kinds)
-        t = kinds.index(2)
-        assert all(k == 3 for k in kinds[t + 1:]), (mu, kinds)
-        assert all(k in (0, 1) for k in kinds[:t]), (mu, kinds)
-        # thread-per-pair rounds come first (largest q), then lane-split rounds
-        assert kinds[:t] == sorted(kinds[:t]), (mu, kinds)
-    assert h.zc_prove_round_kernel(0, 1) < 0 and h.zc_prove_round_kernel(5, 6) < 0
+    for gate, m in ((0, 0), (1, 8), (2, 2)):
+        for mu in range(1, 31):
+            s = zc.shape(mu, gate, m)
+            kinds = [h.zc_prove_round_kernel(ctypes.byref(s), i) for i in range(1, mu + 1)]
+            assert kinds.count(2) == 1, (mu, kinds)
+            t = kinds.index(2)
+            assert all(k == 3 for k in kinds[t + 1:]), (mu, kinds)
+            assert all(k in (0, 1) for k in kinds[:t]), (mu, kinds)
+            # thread-per-pair rounds come first (largest q), then lane-split rounds
+            assert kinds[:t] == sorted(kinds[:t]), (mu, kinds)
+    s = zc.shape(5, 0, 0)
+    assert h.zc_prove_round_kernel(ctypes.byref(s), 0) < 0 and h.zc_prove_round_kernel(ctypes.byref(s), 6) < 0
+    bad = zc.shape(5, 7, 0)
+    assert h.zc_prove_round_kernel(ctypes.byref(bad), 1) < 0
 
 
 def test_batch_host_validation_without_gpu():
