@@ -66,6 +66,12 @@ constexpr bool geq(const L9& a, const L9& b) {
   return true;
 }
 
+constexpr bool same(const L9& a, const L9& b) {
+  for (int i = 0; i < NL; ++i)
+    if (a.v[i] != b.v[i]) return false;
+  return true;
+}
+
 constexpr L9 add(const L9& a, const L9& b) {
   L9 r{};
   uint32_t c = 0;
@@ -110,6 +116,33 @@ constexpr uint32_t neg_inv29() {
   return (0u - x) & LM;
 }
 
+// a b R^-1 mod p for a, b < p (the device product's steps, then one
+// conditional subtraction), for constants.
+constexpr L9 mont_mul(const L9& a, const L9& b) {
+  const uint32_t ninv = neg_inv29();
+  uint32_t m[NL] = {};
+  L9 r{};
+  uint64_t acc = 0;
+  for (int k = 0; k < 2 * NL - 1; ++k) {
+    for (int i = 0; i < NL; ++i) {
+      const int j = k - i;
+      if (j < 0 || j >= NL) continue;
+      acc += (uint64_t)a.v[i] * b.v[j];
+      if (i < k && i < NL) acc += (uint64_t)m[i] * kP.v[j];
+    }
+    if (k < NL) {
+      m[k] = ((uint32_t)acc * ninv) & LM;
+      acc += (uint64_t)m[k] * kP.v[0];
+      acc >>= 29;
+    } else {
+      r.v[k - NL] = (uint32_t)acc & LM;
+      acc >>= 29;
+    }
+  }
+  r.v[NL - 1] = (uint32_t)acc;
+  return geq(r, kP) ? sub(r, kP) : r;
+}
+
 }  // namespace detail
 
 constexpr L9 kP = detail::kP;
@@ -124,6 +157,19 @@ constexpr L9 kP32 = detail::mul_small(kP, 32);
 constexpr L9 kP64 = detail::mul_small(kP, 64);
 
 static_assert(((kP.v[0] * kNInv) & LM) == LM, "-p^-1 mod 2^29");
+
+// R^(k+1) mod p, k = 0..15: the Montgomery form of R^k.
+struct RPowers {
+  L9 v[16];
+  constexpr RPowers() : v{} {
+    v[0] = kOne;
+    for (int k = 1; k < 16; ++k) v[k] = detail::mont_mul(v[k - 1], kR2);
+  }
+};
+constexpr RPowers kRPow{};
+static_assert(detail::same(detail::mont_mul(kR2, detail::pow2_mod(0)), kOne), "R^2 R^-1 = R");
+static_assert(detail::same(kRPow.v[1], kR2) && detail::same(kRPow.v[2], detail::pow2_mod(783)),
+              "powers of R from products equal those from doublings");
 static_assert(kP.v[8] < (1u << 22), "p < 2^254");
 
 // Constant limb i of a compile-time L9 (folded after unrolling).

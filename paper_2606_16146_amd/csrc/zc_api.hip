@@ -129,15 +129,14 @@ RoundArgs round_args(const zc_shape* s, const Layout& L, void* ws, uint32_t i,
   return a;
 }
 
-// r -> canonical and Montgomery copies, C_1 and coef_1, the factored eq tables.
+// One launch: r -> canonical and Montgomery copies, C_1, coef_1 and the eq1
+// rows, the factored eq tables, and T_0.
 int launch_setup(const zc_shape* s, const Layout& L, const uint32_t* r, void* ws, hipStream_t st) {
   Ctrl* ctrl = ctrl_of(ws);
-  hipLaunchKernelGGL(k_setup, dim3(1), dim3(kBlock), 0, st, r, s->mu, L.d + 2, ctrl);
-  if (launch_ok() != ZC_OK) return ZC_EHIP;
   const uint32_t nrows = (1u << L.ml) + (1u << L.mh) + (2u << L.ml);
   uint32_t* rows = reinterpret_cast<uint32_t*>(bytes(ws) + L.eqrows);
-  hipLaunchKernelGGL(k_eq_tables, dim3((nrows + kBlock - 1) / kBlock + 1), dim3(kBlock), 0, st, ctrl, r, s->mu,
-                     s->gate, s->m, L.ml, rows);
+  const uint32_t grid = 1 + (nrows + kBlock - 1) / kBlock + 1;
+  hipLaunchKernelGGL(k_setup_eq, dim3(grid), dim3(kBlock), 0, st, ctrl, r, s->mu, s->gate, s->m, L.ml, L.d + 2, rows);
   return launch_ok();
 }
 
@@ -195,19 +194,16 @@ int prove_impl(const zc_shape* shape, const uint32_t* const* tables, const uint3
 
 // ---- batches -----------------------------------------------------------------
 
-__global__ __launch_bounds__(kBlock) void k_batch_setup(const InstDesc* __restrict__ descs) {
-  const InstDesc& d = descs[blockIdx.x];
-  setup_body(d.r, d.mu, d.ne, d.ctrl);
-}
-
-// eq rows of instance blockIdx.y; its T_0 in the last x block
-__global__ __launch_bounds__(kBlock) void k_batch_eq(const InstDesc* __restrict__ descs) {
+// setup of instance blockIdx.y: setup_body in x block 0, T_0 in the last x
+// block, its eq rows in between
+__global__ __launch_bounds__(kBlock) void k_batch_setup_eq(const InstDesc* __restrict__ descs) {
   const InstDesc& d = descs[blockIdx.y];
-  if (blockIdx.x == gridDim.x - 1) {
+  if (blockIdx.x == 0)
+    setup_body(d.r, d.mu, d.ne, d.ctrl);
+  else if (blockIdx.x == gridDim.x - 1)
     t0_body(d.r, d.mu, d.gate, d.m, d.ctrl);
-    return;
-  }
-  eq_row_body(d.ctrl, d.mu, d.eq.ml, const_cast<uint32_t*>(d.eq.lo), blockIdx.x * blockDim.x + threadIdx.x);
+  else
+    eq_row_body(d.r, d.mu, d.eq.ml, const_cast<uint32_t*>(d.eq.lo), (blockIdx.x - 1) * blockDim.x + threadIdx.x);
 }
 
 constexpr uint32_t kBatchMax = 65536;
@@ -344,17 +340,17 @@ int launch_batch_key(uint32_t key, const BatchStep& bs, uint32_t blocks, bool fo
 
 constexpr uint32_t kServeSlots = 65535;  // slot ids travel as u16
 
-__global__ __launch_bounds__(kBlock) void k_serve_setup(InstDesc* __restrict__ pool, uint32_t slot, InstDesc d) {
-  if (threadIdx.x == 0) pool[slot] = d;
-  setup_body(d.r, d.mu, d.ne, d.ctrl);
-}
-
-__global__ __launch_bounds__(kBlock) void k_serve_eq(InstDesc d) {
-  if (blockIdx.x == gridDim.x - 1) {
+// admission of one instance: its descriptor into the pool and setup_body in
+// block 0, T_0 in the last block, the eq rows in between
+__global__ __launch_bounds__(kBlock) void k_serve_setup_eq(InstDesc* __restrict__ pool, uint32_t slot, InstDesc d) {
+  if (blockIdx.x == 0) {
+    if (threadIdx.x == 0) pool[slot] = d;
+    setup_body(d.r, d.mu, d.ne, d.ctrl);
+  } else if (blockIdx.x == gridDim.x - 1) {
     t0_body(d.r, d.mu, d.gate, d.m, d.ctrl);
-    return;
+  } else {
+    eq_row_body(d.r, d.mu, d.eq.ml, const_cast<uint32_t*>(d.eq.lo), (blockIdx.x - 1) * blockDim.x + threadIdx.x);
   }
-  eq_row_body(d.ctrl, d.mu, d.eq.ml, const_cast<uint32_t*>(d.eq.lo), blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 uint32_t last_round(uint32_t mu) { return mu <= 6 ? 1u : mu - 6; }
@@ -494,9 +490,8 @@ int zc_batch_launch(uint32_t n, const zc_instance* inst, void* batch_ws, hipStre
   if (rc != ZC_OK) return rc;
   const InstDesc* descs = reinterpret_cast<const InstDesc*>(batch_ws);
   const uint32_t* words = reinterpret_cast<const uint32_t*>(bytes(batch_ws) + desc_bytes(n));
-  hipLaunchKernelGGL(k_batch_setup, dim3(n), dim3(kBlock), 0, stream, descs);
-  if ((rc = launch_ok()) != ZC_OK) return rc;
-  hipLaunchKernelGGL(k_batch_eq, dim3((P.max_eq_rows + kBlock - 1) / kBlock + 1, n), dim3(kBlock), 0, stream, descs);
+  hipLaunchKernelGGL(k_batch_setup_eq, dim3((P.max_eq_rows + kBlock - 1) / kBlock + 2, n), dim3(kBlock), 0, stream,
+                     descs);
   if ((rc = launch_ok()) != ZC_OK) return rc;
   for (const BatchSeg& g : P.segs) {
     BatchStep bs{descs, words + g.inst_off, words + g.prefix_off, g.count, g.step};
@@ -527,10 +522,9 @@ int zc_serve_admit(void* pool, uint32_t slots, uint32_t slot, const zc_instance*
   int rc = check_instance(*inst, &L);
   if (rc != ZC_OK) return rc;
   const InstDesc d = make_desc(*inst, L, last_round(inst->shape.mu));
-  hipLaunchKernelGGL(k_serve_setup, dim3(1), dim3(kBlock), 0, stream, reinterpret_cast<InstDesc*>(pool), slot, d);
-  if ((rc = launch_ok()) != ZC_OK) return rc;
   const uint32_t nrows = (1u << L.ml) + (1u << L.mh) + (2u << L.ml);
-  hipLaunchKernelGGL(k_serve_eq, dim3((nrows + kBlock - 1) / kBlock + 1), dim3(kBlock), 0, stream, d);
+  hipLaunchKernelGGL(k_serve_setup_eq, dim3((nrows + kBlock - 1) / kBlock + 2), dim3(kBlock), 0, stream,
+                     reinterpret_cast<InstDesc*>(pool), slot, d);
   return launch_ok();
 }
 

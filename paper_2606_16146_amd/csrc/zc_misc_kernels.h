@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include "zc_device.h"
+#include "zc_t0.h"
 
 namespace zc {
 
@@ -26,7 +27,7 @@ __device__ __forceinline__ Fe lam_mont(uint32_t d, uint32_t k) {
 // One block: resets the control block, checks r, keeps it in canonical and
 // Montgomery form, sets C_1 = 1, fills the eq1 rows of every round and
 // from row 1 coef_1[x] = eq1(x, r_1) for x < ne and coefl_1.  (T_0 is hashed
-// by t0_body, in the launch that follows.)
+// by t0_body, in another block of the same launch.)
 __device__ __forceinline__ void setup_body(const uint32_t* __restrict__ r, uint32_t mu, uint32_t ne, Ctrl* ctrl) {
   if (threadIdx.x == 0) {
     ctrl->err = 0;
@@ -74,33 +75,6 @@ __device__ __forceinline__ void setup_body(const uint32_t* __restrict__ r, uint3
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_setup(const uint32_t* __restrict__ r, uint32_t mu, uint32_t ne, Ctrl* ctrl) {
-  setup_body(r, mu, ne, ctrl);
-}
-
-// T_0 = SHA-256("ZCv1" || u32 mu || u32 gate || u32 m || enc(r_1) .. enc(r_mu)),
-// one block: lane b expands message block b, lane 0 compresses.
-__device__ __forceinline__ void t0_body(const uint32_t* __restrict__ r, uint32_t mu, uint32_t gate, uint32_t m,
-                                        Ctrl* ctrl) {
-  __shared__ uint32_t m0[4 + kMuMax * 8];
-  __shared__ uint32_t kw[((16u + 32u * kMuMax + 9u + 63u) / 64u) * 64u];
-  if (threadIdx.x == 0) {
-    m0[0] = 0x3176435au;  // bytes 'Z' 'C' 'v' '1'
-    m0[1] = mu;
-    m0[2] = gate;
-    m0[3] = m;
-  }
-  for (uint32_t i = threadIdx.x; i < mu * 8; i += blockDim.x) m0[4 + i] = r[i];
-  __syncthreads();
-  const uint32_t nb = sha256_schedule_var(m0, 16u + 32u * mu, kw);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t dg[8];
-    sha256_compress_blocks(kw, nb, dg);
-#pragma unroll
-    for (int k = 0; k < 8; ++k) ctrl->ts[k] = dg[k];
-  }
-}
 
 // Rows of the factored eq tables (see EqTabs): LO (2^ml rows), the HI heap
 // (2^mh rows, row 0 unused) and the SUF heap (2^(ml+1) rows, row 0 unused),
@@ -108,7 +82,11 @@ __device__ __forceinline__ void t0_body(const uint32_t* __restrict__ r, uint32_t
 // last variable is v is prod_k (bit ? r : 1 - r) over variables v-nb+1..v,
 // the most significant bit of the row index within the table being the
 // first of them.
-__device__ __forceinline__ void eq_row_body(const Ctrl* __restrict__ ctrl, uint32_t mu, uint32_t ml,
+//
+// The factors are read from the caller's canonical r (a value >= p, flagged by
+// setup_body, is taken as 0); starting from R^(nb+1) each Montgomery product
+// with a canonical factor keeps the row in Montgomery form.
+__device__ __forceinline__ void eq_row_body(const uint32_t* __restrict__ r, uint32_t mu, uint32_t ml,
                                             uint32_t* __restrict__ rows, uint32_t e) {
   const uint32_t mh = mu - ml;
   const uint32_t nlo = 1u << ml, nhi = 1u << mh, nsuf = 2u << ml;
@@ -131,25 +109,37 @@ __device__ __forceinline__ void eq_row_body(const Ctrl* __restrict__ ctrl, uint3
     y = srow - (1u << nb);
     last = mu;
   }
-  const Fe one = fe_const(kOne);
-  Fe acc = one;
+  Fe acc = fe_zero();
+#pragma unroll
+  for (int k = 0; k < 16; ++k)
+    if ((uint32_t)k == nb) acc = fe_const(kRPow.v[k]);  // nb <= 15 (mu <= 30)
+  Fe one = fe_zero();
+  one.l[0] = 1;
   for (uint32_t k = 0; k < nb; ++k) {
-    const Fe ri = load_words_fe(ctrl->r_m[last - nb + k]);  // variable last-nb+1+k (1-based)
+    uint32_t w[8];
+    const uint32_t* rw = r + (uint64_t)(last - nb + k) * 8;  // variable last-nb+1+k (1-based)
+#pragma unroll
+    for (int t = 0; t < 8; ++t) w[t] = rw[t];
+    const Fe ri = words_lt_p(w) ? fe_from_words(w) : fe_zero();
     const uint32_t bit = (y >> (nb - 1 - k)) & 1u;
     acc = fe_reduce2(fe_mul(acc, bit ? ri : fe_submod(one, ri)));
   }
   store_words_fe(rows + (uint64_t)e * 8, acc);
 }
 
-// The eq rows, and T_0 in the last block (it needs r only, so it overlaps).
-__global__ __launch_bounds__(kBlock) void k_eq_tables(Ctrl* __restrict__ ctrl, const uint32_t* __restrict__ r,
-                                                      uint32_t mu, uint32_t gate, uint32_t m, uint32_t ml,
-                                                      uint32_t* __restrict__ rows) {
-  if (blockIdx.x == gridDim.x - 1) {
+// The setup of a proof in one launch: block 0 runs setup_body, the last
+// block hashes T_0 and the blocks between build the eq rows (each part needs
+// r only, so they overlap).
+__global__ __launch_bounds__(kBlock) void k_setup_eq(Ctrl* __restrict__ ctrl, const uint32_t* __restrict__ r,
+                                                     uint32_t mu, uint32_t gate, uint32_t m, uint32_t ml, uint32_t ne,
+                                                     uint32_t* __restrict__ rows) {
+  if (blockIdx.x == 0) {
+    setup_body(r, mu, ne, ctrl);
+  } else if (blockIdx.x == gridDim.x - 1) {
     t0_body(r, mu, gate, m, ctrl);
-    return;
+  } else {
+    eq_row_body(r, mu, ml, rows, (blockIdx.x - 1) * blockDim.x + threadIdx.x);
   }
-  eq_row_body(ctrl, mu, ml, rows, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // ---- folds -----------------------------------------------------------------------
