@@ -830,6 +830,9 @@ __global__ __launch_bounds__(kBlock) void k_round_split(RoundArgs a, TabPtrs src
     const uint64_t stride = (uint64_t)gridDim.x * kSplitPairs;
     for (uint64_t base = (uint64_t)blockIdx.x * kSplitPairs; base < q; base += stride) {
       const uint32_t j = (uint32_t)(base + pl);
+      // the eq rows of the pair are loaded now, used after the exchange
+      EqRows er{};
+      if (j < q && g < (uint32_t)NH) er = issue_eq(a.eq, a.round, j);
       if (j < q && g < (uint32_t)K) {
         // table g's pointers, selected without indexing the argument array per lane
         const uint32_t* src = srct.p[0];
@@ -864,7 +867,7 @@ __global__ __launch_bounds__(kBlock) void k_round_split(RoundArgs a, TabPtrs src
           u0 = lds_fe(sh[pl][t][0]);
           u1 = lds_fe(sh[pl][t][1]);
         };
-        const Fe E = eq_factor(a.eq, a.round, j);
+        const Fe E = resolve_eq(er);
         c = fe_addmod(c, fe_reduce2(fe_mul(point_f<Gate>(get, g), E)));
       }
       __syncthreads();
