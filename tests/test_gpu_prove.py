@@ -157,6 +157,27 @@ def test_table1_shapes_mu16_match_c_oracle(zc, m):
     assert np.array_equal(res["openings"], ora["openings"])
 
 
+@pytest.mark.parametrize("gate,m", [(0, 0), (1, 8), (1, 2), (2, 34), (2, 4)])
+def test_extreme_values_thread_per_pair_rounds(zc, gate, m):
+    """Internal values 0 and p-1 mixed at random (seeded) at mu = 16, where
+    round 1 and the next rounds run the thread-per-pair kernels and their
+    lazy bounds: every combination of extremes in a pair (t[j], t[j+q]),
+    among them the largest unreduced difference (0, p-1), reaches the round-1
+    extensions and products; r mixes p-1 and 1."""
+    mu, n = 16, 1 << 16
+    k = zc.table_count(zc.shape(mu, gate, m))
+    top = limbs_of([(P - 1) * pow(R_MONT, -1, P) % P])[0]  # packs to p-1
+    rng = np.random.default_rng(2024 + 16 * gate + m)
+    tables = np.stack([np.where(rng.integers(0, 2, (n, 1)) == 1, top, 0).astype(np.uint32) for _ in range(k)])
+    r = limbs_of([P - 1 if b else 1 for b in rng.integers(0, 2, mu)])
+    inst = I.Instance(0, 0, mu, gate, m, tables, r)
+    res = gpu_prove(inst)
+    assert res["err"] == 0
+    ora = C.prove(mu, gate, m, inst.tables, inst.r)
+    assert np.array_equal(res["evals"], ora["evals"]) and np.array_equal(res["alphas"], ora["alphas"])
+    assert np.array_equal(res["openings"], ora["openings"])
+
+
 @pytest.mark.parametrize("name", ["plain20_d3", "plain20_d9"])
 def test_full_size_matches_c_oracle(zc, name):
     inst = I.preset_instance(name)
