@@ -127,7 +127,9 @@ def run_workload(name, steps, warmup, cpu_baseline):
     # thread per pair (kind 0, rounds >= 2); round 1 and the lane-split rounds
     # are reported separately, and the rest of a proof (setup, the one-block
     # finishers with their SHA-256 and the tail) is what round_kernels_share
-    # leaves.
+    # leaves.  With speculation (gates of degree <= 3) a lane-split round's
+    # launch also finishes the previous round, so split_rounds_us includes
+    # those finishers.
     kinds = [zc.lib().zc_prove_round_kernel(ctypes.byref(s), i) for i in range(1, mu + 1)]
     fused_t, fused_b, fused_p, first_t, split_t = 0.0, 0, 0, 0.0, 0.0
     launches = 0

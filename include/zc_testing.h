@@ -47,7 +47,10 @@ int zc_prove_profiled(const zc_shape* shape, const uint32_t* const* tables, cons
 /* Which kernel zc_prove uses for round i (1..mu) of a proof of this shape:
    0 one thread per pair, 1 sixteen lanes per pair, 2 sixteen lanes per pair
    whose finisher then runs all later rounds and the openings in one block,
-   3 a round run inside such a tail.  Negative zc_status for a bad shape or i. */
+   3 a round run inside such a tail, 4 sixteen lanes per pair evaluated for
+   every candidate alpha_{i-1} in 0..d in the launch that finishes round i-1
+   (gates of degree <= 3), 5 the same whose finisher then runs the tail.
+   Negative zc_status for a bad shape or i. */
 int zc_prove_round_kernel(const zc_shape* shape, uint32_t i);
 
 /* SHA-256 of len bytes (msg: little-endian packed uint32 words); out: 32 bytes as uint32[8]. */

@@ -143,6 +143,25 @@ constexpr L9 mont_mul(const L9& a, const L9& b) {
   return geq(r, kP) ? sub(r, kP) : r;
 }
 
+// 1/n mod p for a small n >= 1: (k p + 1) / n for the k < n that makes the
+// division exact (long division by n over the 29-bit limbs).
+constexpr L9 inv_small(uint32_t n) {
+  for (uint32_t k = 0; k < n; ++k) {
+    L9 v{};
+    v.v[0] = 1;
+    v = add(v, mul_small(kP, k));
+    uint64_t rem = 0;
+    L9 q{};
+    for (int i = NL - 1; i >= 0; --i) {
+      const uint64_t cur = (rem << 29) | v.v[i];
+      q.v[i] = (uint32_t)(cur / n);
+      rem = cur % n;
+    }
+    if (rem == 0) return q;
+  }
+  return L9{};
+}
+
 }  // namespace detail
 
 constexpr L9 kP = detail::kP;
@@ -167,6 +186,33 @@ struct RPowers {
   }
 };
 constexpr RPowers kRPow{};
+
+// Lagrange weights of the nodes 0..D: w_c = 1 / prod_{k != c} (c - k), in
+// Montgomery form (D <= 6).  p(x) = sum_c w_c prod_{k != c} (x - k) p(c)
+// for any p of degree <= D.
+template <int D>
+struct LagrangeW {
+  L9 w[D + 1];
+  L9 node[D + 1];  // c R mod p: the nodes in Montgomery form
+  constexpr LagrangeW() : w{}, node{} {
+    for (int c = 0; c <= D; ++c) {
+      L9 v{};
+      for (int k = 0; k < c; ++k) {
+        v = detail::add(v, kOne);
+        if (detail::geq(v, kP)) v = detail::sub(v, kP);
+      }
+      node[c] = v;
+    }
+    for (int c = 0; c <= D; ++c) {
+      uint32_t den = 1;  // c! (D - c)!
+      for (int k = 1; k <= c; ++k) den *= (uint32_t)k;
+      for (int k = 1; k <= D - c; ++k) den *= (uint32_t)k;
+      L9 v = detail::mont_mul(detail::inv_small(den), kR2);
+      if ((D - c) % 2 == 1) v = detail::sub(kP, v);  // the sign of prod (c - k)
+      w[c] = v;
+    }
+  }
+};
 static_assert(detail::same(detail::mont_mul(kR2, detail::pow2_mod(0)), kOne), "R^2 R^-1 = R");
 static_assert(detail::same(kRPow.v[1], kR2) && detail::same(kRPow.v[2], detail::pow2_mod(783)),
               "powers of R from products equal those from doublings");

@@ -21,7 +21,7 @@ struct Layout {
   uint32_t k;       // witness tables
   uint32_t d;       // gate degree
   uint32_t ml, mh;  // split of the variables for the factored eq tables
-  size_t eqrows, partials, scratch, total;
+  size_t eqrows, partials, specparts, scratch, total;
 };
 
 constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -65,6 +65,8 @@ int make_layout(const zc_shape* s, Layout* L) {
   off = align256(off + (((size_t)1 << L->ml) + ((size_t)1 << L->mh) + ((size_t)2 << L->ml)) * 32);
   L->partials = off;
   off = align256(off + (size_t)kMaxBlocks * kMaxEvals * 32);
+  L->specparts = off;  // two buffers of speculative partial sums (kSpecBlocks x kGroup values)
+  off = align256(off + 2 * (size_t)kSpecBlocks * 16 * 32);
   L->scratch = off;  // folded copies of the k witness tables, 2^(mu-1) entries each
   off = align256(off + (size_t)k * (n / 2 > 0 ? n / 2 : 1) * 32);
   L->total = off;
@@ -105,6 +107,33 @@ int dispatch_round(const zc_shape* s, bool fold, RoundKind kind, const RoundArgs
     case 6: return launch_round_prod6(fold, kind, a, src, dst, st, after);
     case 7: return launch_round_prod7(fold, kind, a, src, dst, st, after);
     case 8: return launch_round_prod8(fold, kind, a, src, dst, st, after);
+    default: return ZC_EUNSUPPORTED;
+  }
+}
+
+int dispatch_spec(const zc_shape* s, SpecStep step, const RoundArgs& fa, const TabPtrs& fdst, const RoundArgs& sa,
+                  const TabPtrs& src, const TabPtrs& dst, hipStream_t st, uint32_t* blocks) {
+  if (s->gate == ZC_GATE_VANILLA) return launch_spec_vanilla(step, fa, fdst, sa, src, dst, st, blocks);
+  if (s->gate == ZC_GATE_SUMPROD) {
+    switch (s->m) {
+      case 2: return launch_spec_sum2(step, fa, fdst, sa, src, dst, st, blocks);
+      case 18: return launch_spec_sum18(step, fa, fdst, sa, src, dst, st, blocks);
+      case 34: return launch_spec_sum34(step, fa, fdst, sa, src, dst, st, blocks);
+      case 50: return launch_spec_sum50(step, fa, fdst, sa, src, dst, st, blocks);
+      case 3: return launch_spec_sum3(step, fa, fdst, sa, src, dst, st, blocks);
+      case 4: return launch_spec_sum4(step, fa, fdst, sa, src, dst, st, blocks);
+      default: return ZC_EUNSUPPORTED;
+    }
+  }
+  switch (s->m) {
+    case 1: return launch_spec_prod1(step, fa, fdst, sa, src, dst, st, blocks);
+    case 2: return launch_spec_prod2(step, fa, fdst, sa, src, dst, st, blocks);
+    case 3: return launch_spec_prod3(step, fa, fdst, sa, src, dst, st, blocks);
+    case 4: return launch_spec_prod4(step, fa, fdst, sa, src, dst, st, blocks);
+    case 5: return launch_spec_prod5(step, fa, fdst, sa, src, dst, st, blocks);
+    case 6: return launch_spec_prod6(step, fa, fdst, sa, src, dst, st, blocks);
+    case 7: return launch_spec_prod7(step, fa, fdst, sa, src, dst, st, blocks);
+    case 8: return launch_spec_prod8(step, fa, fdst, sa, src, dst, st, blocks);
     default: return ZC_EUNSUPPORTED;
   }
 }
@@ -171,8 +200,48 @@ int prove_impl(const zc_shape* shape, const uint32_t* const* tables, const uint3
   }
 
   if ((rc = launch_setup(shape, L, r, ws, stream)) != ZC_OK) return rc;
+  const SpecPlan sp = spec_plan(mu, L.d);
+  uint32_t* spec_buf[2] = {reinterpret_cast<uint32_t*>(bytes(ws) + L.specparts),
+                           reinterpret_cast<uint32_t*>(bytes(ws) + L.specparts) + (size_t)kSpecBlocks * 16 * 8};
+  uint32_t prev_blocks = 0;      // partial-sum blocks of the previous launch (speculative schedule)
+  uint32_t* prev_parts = nullptr;
   for (uint32_t i = 1; i <= mu; ++i) {
     const RoundKind kind = prove_round_kind(mu, i, L.d);
+    if (sp.on && (i + 1 == sp.s0 || kind == kSpec || kind == kSpecTail)) {
+      // round s0-1 without its finisher, then for i = s0..r the finisher of
+      // round i-1 beside the speculative round i, then round r's finisher
+      // with the tail (tables: the folded copies, T_{i-1} or T_{i-2})
+      RoundArgs sa = round_args(shape, L, ws, i, round_evals, challenges);
+      sa.src_pitch = i <= 2 ? n : half;
+      sa.dst_pitch = half;
+      if (ev && hipEventRecord(ev[2 * (i - 1)], stream) != hipSuccess) return ZC_EHIP;
+      uint32_t blocks = 0;
+      if (i + 1 == sp.s0) {
+        rc = dispatch_spec(shape, kSpecRoundOnly, sa, fold, sa, i <= 2 ? orig : fold, fold, stream, &blocks);
+        prev_parts = sa.partials;
+      } else {
+        RoundArgs fa = round_args(shape, L, ws, i - 1, round_evals, challenges);
+        fa.nparts = prev_blocks;
+        fa.partials = prev_parts;
+        sa.partials = spec_buf[i & 1];
+        sa.src_pitch = sa.dst_pitch = half;
+        rc = dispatch_spec(shape, i == sp.s0 ? kSpecFirst : kSpecNext, fa, fold, sa, fold, fold, stream, &blocks);
+        prev_parts = sa.partials;
+      }
+      if (rc != ZC_OK) return rc;
+      if (ev && hipEventRecord(ev[2 * (i - 1) + 1], stream) != hipSuccess) return ZC_EHIP;
+      prev_blocks = blocks;
+      if (kind == kSpecTail) {
+        RoundArgs fa = round_args(shape, L, ws, i, round_evals, challenges);
+        fa.nparts = prev_blocks;
+        fa.partials = prev_parts;
+        fa.tail = 1;
+        fa.openings = openings;
+        fa.src_pitch = fa.dst_pitch = half;
+        if ((rc = dispatch_spec(shape, kSpecFinishTail, fa, fold, fa, fold, fold, stream, &blocks)) != ZC_OK) return rc;
+      }
+      continue;
+    }
     if (kind == kInTail) {  // evaluated inside the tail of an earlier launch
       if (ev && (hipEventRecord(ev[2 * (i - 1)], stream) != hipSuccess ||
                  hipEventRecord(ev[2 * (i - 1) + 1], stream) != hipSuccess))

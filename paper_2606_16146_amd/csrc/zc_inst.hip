@@ -86,6 +86,44 @@ int launch_round(bool fold, RoundKind kind, RoundArgs a, const TabPtrs& src, con
   return launch_ok();
 }
 
+template <class Gate, bool FIRST>
+struct SpecTag {};
+
+template <class Gate>
+int launch_spec(ZC_SPEC_ARGS) {
+  if constexpr (!SpecShape<Gate>::kOk) {
+    return -1;
+  } else {
+    int rc = 0;
+    if (step == kSpecRoundOnly) {
+      const void* kern = reinterpret_cast<const void*>(&k_round<Gate, true>);
+      const int per_cu = resident_blocks<RoundTag<Gate, true, false>>(kern);
+      const uint32_t b = round_grid((sa.q + kBlock - 1) / kBlock, per_cu, &rc);
+      if (rc) return rc;
+      hipLaunchKernelGGL((k_round<Gate, true>), dim3(b), dim3(kBlock), 0, st, sa, src, dst);
+      *blocks = b;
+    } else if (step == kSpecFinishTail) {
+      hipLaunchKernelGGL((k_finish_spec<Gate>), dim3(1), dim3(kBlock), tail_lds_bytes<Gate>(), st, fa, fdst);
+    } else {
+      const bool first = step == kSpecFirst;
+      const void* kern = first ? reinterpret_cast<const void*>(&k_fin_spec<Gate, true>)
+                               : reinterpret_cast<const void*>(&k_fin_spec<Gate, false>);
+      const int per_cu = first ? resident_blocks<SpecTag<Gate, true>>(kern) : resident_blocks<SpecTag<Gate, false>>(kern);
+      // one resident generation including the finisher block
+      uint32_t b = round_grid((sa.q + kSplitPairs - 1) / kSplitPairs + 1, per_cu, &rc) - 1;
+      if (rc) return rc;
+      if (b < 1) b = 1;
+      if (b > kSpecBlocks) b = kSpecBlocks;
+      if (first)
+        hipLaunchKernelGGL((k_fin_spec<Gate, true>), dim3(b + 1), dim3(kBlock), 0, st, fa, fdst, sa, src, dst);
+      else
+        hipLaunchKernelGGL((k_fin_spec<Gate, false>), dim3(b + 1), dim3(kBlock), 0, st, fa, fdst, sa, src, dst);
+      *blocks = b;
+    }
+    return launch_ok();
+  }
+}
+
 template <class Gate>
 int launch_batch(const BatchStep& bs, uint32_t blocks, bool fold, bool tail, hipStream_t st) {
   if (bs.count == 0) return 0;
@@ -125,6 +163,7 @@ int launch_batch_vanilla(const BatchStep& bs, uint32_t blocks, bool fold, bool t
 int launch_serve_vanilla(const ServeStep& ss, uint32_t blocks, bool fold, bool tail, hipStream_t st) {
   return launch_serve<GateVanilla>(ss, blocks, fold, tail, st);
 }
+int launch_spec_vanilla(ZC_SPEC_ARGS) { return launch_spec<GateVanilla>(step, fa, fdst, sa, src, dst, st, blocks); }
 #elif defined(ZC_INST_PROD)
 #define ZC_CAT2(a, b) a##b
 #define ZC_CAT(a, b) ZC_CAT2(a, b)
@@ -139,6 +178,9 @@ int ZC_CAT(launch_batch_prod, ZC_INST_PROD)(const BatchStep& bs, uint32_t blocks
 int ZC_CAT(launch_serve_prod, ZC_INST_PROD)(const ServeStep& ss, uint32_t blocks, bool fold, bool tail,
                                             hipStream_t st) {
   return launch_serve<GateProd<ZC_INST_PROD>>(ss, blocks, fold, tail, st);
+}
+int ZC_CAT(launch_spec_prod, ZC_INST_PROD)(ZC_SPEC_ARGS) {
+  return launch_spec<GateProd<ZC_INST_PROD>>(step, fa, fdst, sa, src, dst, st, blocks);
 }
 #elif defined(ZC_INST_SUM)
 // m = P + 16 A of a Table 1 shape
@@ -156,6 +198,9 @@ int ZC_CAT(launch_batch_sum, ZC_INST_SUM)(const BatchStep& bs, uint32_t blocks, 
 int ZC_CAT(launch_serve_sum, ZC_INST_SUM)(const ServeStep& ss, uint32_t blocks, bool fold, bool tail,
                                           hipStream_t st) {
   return launch_serve<GateT1>(ss, blocks, fold, tail, st);
+}
+int ZC_CAT(launch_spec_sum, ZC_INST_SUM)(ZC_SPEC_ARGS) {
+  return launch_spec<GateT1>(step, fa, fdst, sa, src, dst, st, blocks);
 }
 #else
 #error "build zc_inst.hip with -DZC_INST_VANILLA, -DZC_INST_PROD=<m> or -DZC_INST_SUM=<P + 16 A>"

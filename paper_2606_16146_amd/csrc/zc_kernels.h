@@ -751,8 +751,11 @@ __device__ __forceinline__ Fe group_reduce(Fe c) {
 // Evaluation: point x of pair j is one thread's work (SL point slots, the
 // power of two >= d+1, times PP = kBlock / SL pairs per pass); the PP lanes
 // of a point are adjacent, so their sum is a shuffle reduction in one wave.
+//
+// With prefold the tables at dst hold T_{a.round - 1} (4q entries) instead:
+// they are folded with alpha_{a.round - 1} on the way into LDS.
 template <class Gate>
-__device__ __forceinline__ void run_tail(const RoundArgs& a, const TabPtrs& dst, FinLds<Gate::D>& S) {
+__device__ __forceinline__ void run_tail(const RoundArgs& a, const TabPtrs& dst, FinLds<Gate::D>& S, bool prefold) {
   constexpr int K = Gate::K;
   constexpr int NH = Gate::NH;
   constexpr uint32_t SL = NH <= 4 ? 4u : (NH <= 8 ? 8u : 16u);
@@ -763,9 +766,12 @@ __device__ __forceinline__ void run_tail(const RoundArgs& a, const TabPtrs& dst,
   auto T = [&](int t, uint32_t e) -> uint32_t* { return tail_lds + ((uint32_t)t * CAP + e) * NL; };
   uint32_t* eqrow = tail_lds + (uint32_t)K * CAP * NL;
   uint32_t L = 2 * (uint32_t)a.q;
+  const Fe pa = prefold ? fe_vgpr(load_words_fe(a.ctrl->alpha_m[a.round - 2])) : fe_zero();
   for (uint32_t idx = threadIdx.x; idx < K * L; idx += blockDim.x) {
     const uint32_t t = idx / L, e = idx % L;
-    lds_put(T(t, e), load_el(dst.p[t], a.dst_pitch, e));
+    Fe v = load_el(dst.p[t], a.dst_pitch, e);
+    if (prefold) v = fe_lerp(v, load_el(dst.p[t], a.dst_pitch, e + L), pa);
+    lds_put(T(t, e), v);
   }
   // E_r[j] of every tail round r, heap-style: row 2^(mu-r) + j, rows [1, q)
   for (uint32_t hrow = threadIdx.x; hrow < (uint32_t)a.q; hrow += blockDim.x) {
@@ -877,6 +883,88 @@ __global__ __launch_bounds__(kBlock) void k_round_split(RoundArgs a, TabPtrs src
   if (threadIdx.x < NH) store_words_fe(a.partials + ((uint64_t)blockIdx.x * NH + threadIdx.x) * 8, tot);
 }
 
+// ---- speculative rounds (gates of degree <= 3) -----------------------------------------
+//
+// Round r needs alpha_{r-1}, which the finisher of round r-1 is still
+// deriving.  The fold is linear in alpha, so H_r(X) is a polynomial of degree
+// <= d in alpha_{r-1}: spec_body evaluates round r for alpha_{r-1} = c,
+// c = 0..d, beside that finisher (blocks 1.. of k_fin_spec), and the next
+// finisher interpolates the sums at the true alpha_{r-1} (exact in F_p, so
+// the round message is the same field element).  The (d+1)^2 pairs (c, X)
+// fill the 16 lanes of a pair.
+//
+// FIRST: the tables hold T_{r-1} (4q live entries, q the pairs of round r).
+// Otherwise they hold T_{r-2} (8q entries); alpha_{r-2} is known, so the
+// kernel folds T_{r-1} = T_{r-2} + alpha_{r-2} (T_{r-2}[+4q] - T_{r-2}) for the
+// entries j, j+q, j+2q, j+3q of each pair j and writes it to dst (in place:
+// each thread writes only entries it read).  Lane (c, X) folds T_{r-1} with c
+// (a small integer) on the fly and evaluates point X.  Block partials hold
+// the (d+1)^2 sums, slot c (d+1) + X.
+template <class Gate>
+struct SpecShape {
+  static constexpr int NS = Gate::NH * Gate::NH;
+  static constexpr bool kOk = NS <= kGroup;
+};
+
+template <class Gate, bool FIRST>
+__device__ __forceinline__ void spec_body(const RoundArgs& a, const TabPtrs& srct, const TabPtrs& dstt, uint32_t blk,
+                                          uint32_t nblk) {
+  constexpr int K = Gate::K;
+  constexpr int NH = Gate::NH;
+  constexpr int NS = SpecShape<Gate>::NS;
+  static_assert(SpecShape<Gate>::kOk, "(d+1)^2 lanes per pair");
+  __shared__ uint32_t sh[kSplitPairs][K][4][NL];
+  const uint32_t g = threadIdx.x % kGroup, pl = threadIdx.x / kGroup;
+  const uint32_t cc = g / NH, X = g % NH;  // candidate alpha_{r-1} = cc and point X of lane g < NS
+  Fe acc = fe_zero();
+  const uint32_t q = (uint32_t)a.q;
+  const uint64_t stride = (uint64_t)nblk * kSplitPairs;
+  for (uint64_t base = (uint64_t)blk * kSplitPairs; base < q; base += stride) {
+    const uint32_t j = (uint32_t)(base + pl);
+    EqRows er{};
+    if (j < q && g < (uint32_t)NS) er = issue_eq(a.eq, a.round, j);
+    if (j < q && g < (uint32_t)K) {
+      const uint32_t* src = srct.p[0];
+      uint32_t* dst = dstt.p[0];
+      auto sel = [&](auto t) __attribute__((always_inline)) {
+        if (g == (uint32_t)t) {
+          src = srct.p[t];
+          dst = dstt.p[t];
+        }
+      };
+      Unroll<1, K>::run(sel);
+      const uint64_t sp = a.src_pitch;
+      if (FIRST) {
+#pragma unroll
+        for (uint32_t k = 0; k < 4; ++k) lds_put(sh[pl][g][k], load_el(src, sp, j + k * q));
+      } else {
+        const Fe alpha = load_words_fe(a.ctrl->alpha_m[a.round - 3]);  // alpha_{r-2}
+#pragma unroll
+        for (uint32_t k = 0; k < 4; ++k) {
+          const Fe v = fe_lerp(load_el(src, sp, j + k * q), load_el(src, sp, j + k * q + 4 * q), alpha);
+          store_el(dst, a.dst_pitch, j + k * q, v);
+          lds_put(sh[pl][g][k], v);
+        }
+      }
+    }
+    __syncthreads();
+    if (j < q && g < (uint32_t)NS) {
+      // T_r for alpha_{r-1} = cc: u0 = A0 + cc (A2 - A0), u1 = A1 + cc (A3 - A1), < p
+      auto get = [&](int t, Fe& u0, Fe& u1) __attribute__((always_inline)) {
+        const Fe a0 = lds_fe(sh[pl][t][0]), a1 = lds_fe(sh[pl][t][1]);
+        const Fe a2 = lds_fe(sh[pl][t][2]), a3 = lds_fe(sh[pl][t][3]);
+        u0 = fe_csub(fe_csub(fe_add(a0, fe_mul_small(fe_submod(a2, a0), cc)), kP2), kP);  // < 4p before
+        u1 = fe_csub(fe_csub(fe_add(a1, fe_mul_small(fe_submod(a3, a1), cc)), kP2), kP);
+      };
+      const Fe E = resolve_eq(er);
+      acc = fe_addmod(acc, fe_reduce2(fe_mul(point_f<Gate>(get, X), E)));
+    }
+    __syncthreads();
+  }
+  const Fe tot = group_reduce<NS>(acc);
+  if (threadIdx.x < (uint32_t)NS) store_words_fe(a.partials + ((uint64_t)blk * NS + threadIdx.x) * 8, tot);
+}
+
 // ---- end of a round: one block -------------------------------------------------------
 //
 // Adds up the round kernel's a.nparts partial sums, emits G_i, derives
@@ -885,10 +973,18 @@ __global__ __launch_bounds__(kBlock) void k_round_split(RoundArgs a, TabPtrs src
 // emitted (ZC_ESTATE otherwise).
 // (Body shared with the batched finisher; `dst` holds the tables the tail
 // starts from.)
-template <class Gate>
+//
+// SPEC: the partials are spec_body's (d+1)^2 sums per block, H_i(X) for
+// alpha_{i-1} = c; the finisher interpolates them at alpha_{i-1}:
+// H_i(X) = sum_c L_c(alpha_{i-1}) H_i(X; c), L_c the Lagrange basis of the
+// nodes 0..d.  A tail then starts from T_{i-1} (prefold).
+template <class Gate, bool SPEC = false>
 __device__ __forceinline__ void finish_body(const RoundArgs& a, const TabPtrs& dst) {
   constexpr int NH = Gate::NH;
+  constexpr int NV = SPEC ? NH * NH : NH;  // partial sums per block
   __shared__ FinLds<Gate::D> S;
+  __shared__ uint32_t hs[SPEC ? NV : 1][NL];  // SPEC: H_i(X; c), slot c NH + X
+  __shared__ uint32_t lc[SPEC ? NH : 1][NL];  // SPEC: L_c(alpha_{i-1})
   const uint32_t t = threadIdx.x;
   if (t == 0) {
     const bool ok = a.ctrl->round_done + 1 == a.round;
@@ -900,28 +996,72 @@ __device__ __forceinline__ void finish_body(const RoundArgs& a, const TabPtrs& d
   // rounded to powers of two) stride over the partials (each < p), lazily
   // summed (at most kMaxBlocks / LP <= 128 terms, < 128 p), reduced, then
   // combined across the group by shuffles
-  constexpr uint32_t NHP = NH <= 4 ? 4u : (NH <= 8 ? 8u : 16u);
+  constexpr uint32_t NHP = NV <= 4 ? 4u : (NV <= 8 ? 8u : 16u);
   constexpr uint32_t LP = kBlock / NHP;
-  static_assert(NH <= 16 && NHP * LP == kBlock && LP <= 64 && kMaxBlocks / LP <= 128, "lanes per point");
+  static_assert(NV <= 16 && NHP * LP == kBlock && LP <= 64 && kMaxBlocks / LP <= 128, "lanes per point");
   const uint32_t x = t / LP, g = t % LP;
   Fe v = fe_zero();
-  if (x < (uint32_t)NH) {
+  if (x < (uint32_t)NV) {
 #pragma unroll 4
-    for (uint32_t b = g; b < a.nparts; b += LP) v = fe_add(v, load_words_fe(a.partials + ((uint64_t)b * NH + x) * 8));
+    for (uint32_t b = g; b < a.nparts; b += LP) v = fe_add(v, load_words_fe(a.partials + ((uint64_t)b * NV + x) * 8));
     v = fe_reduce128(v);
   }
 #pragma unroll
   for (uint32_t msk = LP / 2; msk >= 1; msk >>= 1) v = fe_add(v, shfl_xor_fe(v, (int)msk));  // < LP p <= 64 p
-  if (x < (uint32_t)NH && g == 0) lds_put(S.h[x], fe_reduce128(v));
+  if (x < (uint32_t)NV && g == 0) lds_put(SPEC ? hs[x] : S.h[x], fe_reduce128(v));
   __syncthreads();
   if (S.skip) return;
+  if constexpr (SPEC) {
+    constexpr LagrangeW<Gate::D> W{};
+    if (t < (uint32_t)NH) {  // lane c: L_c(alpha) = w_c prod_{k != c} (alpha - k)
+      const Fe al = fe_vgpr(load_words_fe(a.ctrl->alpha_m[a.round - 2]));
+      Fe l = fe_zero();
+      auto pick = [&](auto c) __attribute__((always_inline)) {
+        if (t == (uint32_t)c) l = fe_const(W.w[c]);
+      };
+      Unroll<0, NH>::run(pick);
+      auto term = [&](auto k) __attribute__((always_inline)) {
+        if (t != (uint32_t)k) l = mont(l, fe_submod(al, fe_const(W.node[k])));
+      };
+      Unroll<0, NH>::run(term);
+      lds_put(lc[t], l);
+    }
+    __syncthreads();
+    if (t < (uint32_t)NH) {  // lane X: H_i(X) = sum_c L_c H_i(X; c)
+      Fe h = fe_zero();
+      auto add = [&](auto c) __attribute__((always_inline)) {
+        h = fe_addmod(h, mont(fe_vgpr(lds_fe(lc[c])), lds_fe(hs[c * NH + t])));
+      };
+      Unroll<0, NH>::run(add);
+      lds_put(S.h[t], h);
+    }
+    __syncthreads();
+  }
   emit_round<Gate::D>(a.ctrl, a.round, a.mu, S, a.evals_out, a.alpha_out);
-  if (a.tail) run_tail<Gate>(a, dst, S);
+  if (a.tail) run_tail<Gate>(a, dst, S, SPEC);
 }
 
 template <class Gate>
 __global__ __launch_bounds__(kBlock) void k_finish(RoundArgs a, TabPtrs dst) {
   finish_body<Gate>(a, dst);
+}
+
+// The finisher of round r-1 (block 0) beside the speculative evaluation of
+// round r (the other blocks).  FIRST: round r-1 was evaluated normally, and
+// the tables hold T_{r-1}.
+template <class Gate, bool FIRST>
+__global__ __launch_bounds__(kBlock) void k_fin_spec(RoundArgs fa, TabPtrs fdst, RoundArgs sa, TabPtrs src,
+                                                     TabPtrs dst) {
+  if (blockIdx.x == 0)
+    finish_body<Gate, !FIRST>(fa, fdst);
+  else
+    spec_body<Gate, FIRST>(sa, src, dst, blockIdx.x - 1, gridDim.x - 1);
+}
+
+// The finisher of the last speculative round, which then runs the tail.
+template <class Gate>
+__global__ __launch_bounds__(kBlock) void k_finish_spec(RoundArgs a, TabPtrs dst) {
+  finish_body<Gate, true>(a, dst);
 }
 
 // ---- batches: many instances, round by round in lockstep ------------------------------

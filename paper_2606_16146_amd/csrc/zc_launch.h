@@ -25,18 +25,50 @@ constexpr int kTailQ = 32;  // the tail runs rounds with at most this many pairs
 // degree > 3 and down to 8192 for the lighter ones (measured at mu = 20).
 inline uint64_t split_q(uint32_t degree) { return degree <= 3 ? 8192u : 16384u; }
 
-enum RoundKind { kPerPair = 0, kSplit = 1, kSplitTail = 2, kInTail = 3 };
+enum RoundKind { kPerPair = 0, kSplit = 1, kSplitTail = 2, kInTail = 3, kSpec = 4, kSpecTail = 5 };
+
+// Speculative lane-split rounds (gates of degree <= 3, whose (d+1)^2
+// evaluations per pair fit the 16 lanes of a pair): round i is evaluated
+// for every candidate alpha_{i-1} in 0..d beside the finisher of round i-1,
+// and its own finisher interpolates.  s0 is the first lane-split round, r the
+// round whose finisher starts the tail; rounds s0..r-1 are kSpec, r is
+// kSpecTail.  Used when s0 >= 3 and r > s0.
+struct SpecPlan {
+  uint32_t s0, r;
+  bool on;
+};
+inline SpecPlan spec_plan(uint32_t mu, uint32_t degree) {
+  SpecPlan p{0, 0, false};
+  if (degree > 3) return p;
+  for (uint32_t i = 1; i <= mu; ++i) {
+    const uint64_t q = 1ull << (mu - i);
+    if (!p.s0 && q <= split_q(degree)) p.s0 = i;
+    if (!p.r && q <= 2 * (uint64_t)kTailQ) p.r = i;
+  }
+  p.on = p.s0 >= 3 && p.r > p.s0;
+  return p;
+}
 
 // Which kernel evaluates round i of a whole proof (zc_prove).
 inline RoundKind prove_round_kind(uint32_t mu, uint32_t i, uint32_t degree) {
   const uint64_t q = 1ull << (mu - i);
   const uint64_t first_tail_q = 2 * (uint64_t)kTailQ;
   if (q > split_q(degree)) return kPerPair;
+  const SpecPlan sp = spec_plan(mu, degree);
+  if (sp.on && i >= sp.s0 && i <= sp.r) return i < sp.r ? kSpec : kSpecTail;
   if (q > first_tail_q) return kSplit;
   // the first round with q <= 2 kTailQ launches the tail; later rounds run inside it
   const uint64_t prev_q = q * 2;
   return (i == 1 || prev_q > first_tail_q) ? kSplitTail : kInTail;
 }
+
+// The launches of a speculative schedule: the last thread-per-pair round
+// without its finisher; the finisher of round r-1 beside the speculative
+// round r (first or later); the finisher of the last speculative round,
+// which runs the tail.  *blocks receives the number of partial-sum blocks
+// written.  Negative for a gate without speculation.
+enum SpecStep { kSpecRoundOnly = 0, kSpecFirst = 1, kSpecNext = 2, kSpecFinishTail = 3 };
+constexpr uint32_t kSpecBlocks = 1024;  // partial-sum blocks of a speculative round, at most
 
 // One launcher per gate instantiation (defined in zc_inst.hip).  `after`, if
 // not null, is recorded on the stream between the round kernel and its
@@ -85,12 +117,26 @@ ZC_DECL_SPROD(7)
 ZC_DECL_SPROD(8)
 #undef ZC_DECL_SPROD
 
+#define ZC_SPEC_ARGS                                                                                  \
+  SpecStep step, const RoundArgs &fa, const TabPtrs &fdst, const RoundArgs &sa, const TabPtrs &src, \
+      const TabPtrs &dst, hipStream_t st, uint32_t *blocks
+int launch_spec_vanilla(ZC_SPEC_ARGS);
+int launch_spec_prod1(ZC_SPEC_ARGS);
+int launch_spec_prod2(ZC_SPEC_ARGS);
+int launch_spec_prod3(ZC_SPEC_ARGS);
+int launch_spec_prod4(ZC_SPEC_ARGS);
+int launch_spec_prod5(ZC_SPEC_ARGS);
+int launch_spec_prod6(ZC_SPEC_ARGS);
+int launch_spec_prod7(ZC_SPEC_ARGS);
+int launch_spec_prod8(ZC_SPEC_ARGS);
+
 // Table 1 shapes, one set per m = P + 16 A.
 #define ZC_DECL_SUM(C)                                                                                            \
   int launch_round_sum##C(bool fold, RoundKind kind, const RoundArgs& a, const TabPtrs& src, const TabPtrs& dst, \
                           hipStream_t st, hipEvent_t after);                                                     \
   int launch_batch_sum##C(const BatchStep& bs, uint32_t blocks, bool fold, bool tail, hipStream_t st);          \
-  int launch_serve_sum##C(const ServeStep& ss, uint32_t blocks, bool fold, bool tail, hipStream_t st);
+  int launch_serve_sum##C(const ServeStep& ss, uint32_t blocks, bool fold, bool tail, hipStream_t st);          \
+  int launch_spec_sum##C(ZC_SPEC_ARGS);
 ZC_DECL_SUM(2)
 ZC_DECL_SUM(18)
 ZC_DECL_SUM(34)

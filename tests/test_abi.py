@@ -74,16 +74,24 @@ def test_strerror_covers_every_status():
 def test_round_kernel_schedule_is_consistent():
     """Every round of a proof is either launched or covered by exactly one tail."""
     h = zc.lib()
-    for gate, m in ((0, 0), (1, 8), (2, 2)):
+    for gate, m in ((0, 0), (1, 8), (1, 2), (2, 2), (2, 4)):
+        d = zc.degree(zc.shape(1, gate, m))
         for mu in range(1, 31):
             s = zc.shape(mu, gate, m)
             kinds = [h.zc_prove_round_kernel(ctypes.byref(s), i) for i in range(1, mu + 1)]
-            assert kinds.count(2) == 1, (mu, kinds)
-            t = kinds.index(2)
+            tail = 5 if 5 in kinds else 2
+            assert kinds.count(tail) == 1 and kinds.count(7 - tail) == 0, (mu, kinds)
+            t = kinds.index(tail)
             assert all(k == 3 for k in kinds[t + 1:]), (mu, kinds)
-            assert all(k in (0, 1) for k in kinds[:t]), (mu, kinds)
+            split = 4 if tail == 5 else 1
+            assert all(k in (0, split) for k in kinds[:t]), (mu, kinds)
             # thread-per-pair rounds come first (largest q), then lane-split rounds
             assert kinds[:t] == sorted(kinds[:t]), (mu, kinds)
+            # speculation: gates of degree <= 3, after at least two thread-per-pair rounds
+            if tail == 5:
+                assert d <= 3 and kinds[:2] == [0, 0], (mu, kinds)
+            if d <= 3 and kinds.count(0) >= 2 and kinds[t - 1] != 0:
+                assert tail == 5, (mu, kinds)
     s = zc.shape(5, 0, 0)
     assert h.zc_prove_round_kernel(ctypes.byref(s), 0) < 0 and h.zc_prove_round_kernel(ctypes.byref(s), 6) < 0
     bad = zc.shape(5, 7, 0)
