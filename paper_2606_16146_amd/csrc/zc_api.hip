@@ -223,6 +223,7 @@ int prove_impl(const zc_shape* shape, const uint32_t* const* tables, const uint3
         RoundArgs fa = round_args(shape, L, ws, i - 1, round_evals, challenges);
         fa.nparts = prev_blocks;
         fa.partials = prev_parts;
+        fa.next_spec = 1;
         sa.partials = spec_buf[i & 1];
         sa.src_pitch = sa.dst_pitch = half;
         rc = dispatch_spec(shape, i == sp.s0 ? kSpecFirst : kSpecNext, fa, fold, sa, fold, fold, stream, &blocks);

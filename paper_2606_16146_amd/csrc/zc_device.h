@@ -36,6 +36,8 @@ struct Ctrl {
   uint32_t c_m[8];                  // C_{round_done+1}, Montgomery form
   uint32_t coef[kMaxEvals][8];      // C_i * eq1(x, r_i), canonical, i = round_done + 1
   uint32_t coefl[kMaxEvals][8];     // coef[d+1] * lam_k (k <= d), canonical: G(d+1) = sum_k coefl[k] H(k)
+  uint32_t lagr[4][8];              // L_c(alpha_{round_done}), c <= d <= 3, Montgomery: the Lagrange basis of
+                                    // the nodes 0..d, for a next round evaluated speculatively
 };
 
 constexpr uint32_t kCtrlBytes = 4096;

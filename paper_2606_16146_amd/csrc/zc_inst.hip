@@ -114,10 +114,12 @@ int launch_spec(ZC_SPEC_ARGS) {
       if (rc) return rc;
       if (b < 1) b = 1;
       if (b > kSpecBlocks) b = kSpecBlocks;
+      // the finisher has no tail here and the speculative round folds in place
+      if (fa.tail || src.p[0] != dst.p[0]) return -1;
       if (first)
-        hipLaunchKernelGGL((k_fin_spec<Gate, true>), dim3(b + 1), dim3(kBlock), 0, st, fa, fdst, sa, src, dst);
+        hipLaunchKernelGGL((k_fin_spec<Gate, true>), dim3(b + 1), dim3(kBlock), 0, st, fa, sa, src);
       else
-        hipLaunchKernelGGL((k_fin_spec<Gate, false>), dim3(b + 1), dim3(kBlock), 0, st, fa, fdst, sa, src, dst);
+        hipLaunchKernelGGL((k_fin_spec<Gate, false>), dim3(b + 1), dim3(kBlock), 0, st, fa, sa, src);
       *blocks = b;
     }
     return launch_ok();

@@ -444,6 +444,7 @@ struct RoundArgs {
   uint32_t tail;               // 1: the finisher also runs rounds round+1..mu and the openings
   uint32_t* openings;          // tail only: (k+1) x 8 canonical
   EqTabs eq;
+  uint32_t next_spec;          // 1: round+1 is evaluated speculatively (the finisher stores L_c(alpha))
 };
 
 // Montgomery product reduced below p.
@@ -518,7 +519,7 @@ __device__ __forceinline__ void fin_load(const Ctrl* ctrl, FinLds<D>& S) {
 // barrier, so no barrier waits for them.  All threads of the block call it.
 template <int D>
 __device__ __forceinline__ void emit_round(Ctrl* ctrl, uint32_t round, uint32_t mu, FinLds<D>& S,
-                                           uint32_t* evals_out, uint32_t* alpha_out) {
+                                           uint32_t* evals_out, uint32_t* alpha_out, bool lagr = false) {
   constexpr int NH = D + 1, NE = D + 2, NC = FinLds<D>::NC;
   constexpr uint32_t LEN = FinLds<D>::LEN, NB = FinLds<D>::NB;
   static_assert(NH <= 16, "one 16-lane group");
@@ -606,6 +607,28 @@ __device__ __forceinline__ void emit_round(Ctrl* ctrl, uint32_t round, uint32_t 
       lds_put(S.am, out);
     }
   }
+  if constexpr (D <= 3) {
+    // with lagr, lane 128 + c: L_c(alpha) = w_c prod_{k != c} (alpha - k) for
+    // the speculative next round's finisher
+    if (lagr && t >= 128 && t < 128 + (uint32_t)NH) {
+      constexpr LagrangeW<D> W{};
+      const uint32_t c = t - 128;
+      uint32_t w[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) w[k] = S.ac[k];
+      const Fe am = fe_to_mont(fe_vgpr(fe_from_words(w)));
+      Fe l = fe_zero();
+      auto pick = [&](auto k) __attribute__((always_inline)) {
+        if (c == (uint32_t)k) l = fe_const(W.w[k]);
+      };
+      Unroll<0, NH>::run(pick);
+      auto term = [&](auto k) __attribute__((always_inline)) {
+        if (c != (uint32_t)k) l = mont(l, fe_submod(am, fe_const(W.node[k])));
+      };
+      Unroll<0, NH>::run(term);
+      out = l;
+    }
+  }
   if (t >= 64 && t < 72) S.msg[t - 64] = S.dg[t - 64];
   __syncthreads();
   // control block and outputs
@@ -619,6 +642,8 @@ __device__ __forceinline__ void emit_round(Ctrl* ctrl, uint32_t round, uint32_t 
     ctrl->ts[t - 64] = S.dg[t - 64];
     alpha_out[t - 64] = S.ac[t - 64];
     if (t == 64) ctrl->round_done = round;
+  } else if (D <= 3 && lagr && t >= 128 && t < 128 + (uint32_t)NH) {
+    store_words_fe(ctrl->lagr[t - 128], out);
   }
 }
 
@@ -897,9 +922,10 @@ __global__ __launch_bounds__(kBlock) void k_round_split(RoundArgs a, TabPtrs src
 // Otherwise they hold T_{r-2} (8q entries); alpha_{r-2} is known, so the
 // kernel folds T_{r-1} = T_{r-2} + alpha_{r-2} (T_{r-2}[+4q] - T_{r-2}) for the
 // entries j, j+q, j+2q, j+3q of each pair j and writes it to dst (in place:
-// each thread writes only entries it read).  Lane (c, X) folds T_{r-1} with c
-// (a small integer) on the fly and evaluates point X.  Block partials hold
-// the (d+1)^2 sums, slot c (d+1) + X.
+// each thread writes only entries it read).  The lane of table t also folds
+// its pair with every candidate c (a small integer: additions only) into
+// LDS; lane (c, X) then evaluates point X.  Block partials hold the (d+1)^2
+// sums, slot c (d+1) + X.
 template <class Gate>
 struct SpecShape {
   static constexpr int NS = Gate::NH * Gate::NH;
@@ -913,7 +939,7 @@ __device__ __forceinline__ void spec_body(const RoundArgs& a, const TabPtrs& src
   constexpr int NH = Gate::NH;
   constexpr int NS = SpecShape<Gate>::NS;
   static_assert(SpecShape<Gate>::kOk, "(d+1)^2 lanes per pair");
-  __shared__ uint32_t sh[kSplitPairs][K][4][NL];
+  __shared__ uint32_t sh[kSplitPairs][K][NH][2][NL];  // T_r[j], T_r[j+q] for alpha_{r-1} = c
   const uint32_t g = threadIdx.x % kGroup, pl = threadIdx.x / kGroup;
   const uint32_t cc = g / NH, X = g % NH;  // candidate alpha_{r-1} = cc and point X of lane g < NS
   Fe acc = fe_zero();
@@ -934,27 +960,36 @@ __device__ __forceinline__ void spec_body(const RoundArgs& a, const TabPtrs& src
       };
       Unroll<1, K>::run(sel);
       const uint64_t sp = a.src_pitch;
+      Fe A[4];  // T_{r-1} at j, j+q, j+2q, j+3q
       if (FIRST) {
 #pragma unroll
-        for (uint32_t k = 0; k < 4; ++k) lds_put(sh[pl][g][k], load_el(src, sp, j + k * q));
+        for (uint32_t k = 0; k < 4; ++k) A[k] = load_el(src, sp, j + k * q);
       } else {
         const Fe alpha = load_words_fe(a.ctrl->alpha_m[a.round - 3]);  // alpha_{r-2}
 #pragma unroll
         for (uint32_t k = 0; k < 4; ++k) {
-          const Fe v = fe_lerp(load_el(src, sp, j + k * q), load_el(src, sp, j + k * q + 4 * q), alpha);
-          store_el(dst, a.dst_pitch, j + k * q, v);
-          lds_put(sh[pl][g][k], v);
+          A[k] = fe_lerp(load_el(src, sp, j + k * q), load_el(src, sp, j + k * q + 4 * q), alpha);
+          store_el(dst, a.dst_pitch, j + k * q, A[k]);
+        }
+      }
+      // T_r for alpha_{r-1} = c: A0 + c (A2 - A0), A1 + c (A3 - A1), c = 0..d
+      const Fe d0 = fe_submod(A[2], A[0]), d1 = fe_submod(A[3], A[1]);
+      Fe u0 = A[0], u1 = A[1];
+#pragma unroll
+      for (int c = 0; c < NH; ++c) {
+        lds_put(sh[pl][g][c][0], u0);
+        lds_put(sh[pl][g][c][1], u1);
+        if (c + 1 < NH) {
+          u0 = fe_addmod(u0, d0);
+          u1 = fe_addmod(u1, d1);
         }
       }
     }
     __syncthreads();
     if (j < q && g < (uint32_t)NS) {
-      // T_r for alpha_{r-1} = cc: u0 = A0 + cc (A2 - A0), u1 = A1 + cc (A3 - A1), < p
       auto get = [&](int t, Fe& u0, Fe& u1) __attribute__((always_inline)) {
-        const Fe a0 = lds_fe(sh[pl][t][0]), a1 = lds_fe(sh[pl][t][1]);
-        const Fe a2 = lds_fe(sh[pl][t][2]), a3 = lds_fe(sh[pl][t][3]);
-        u0 = fe_csub(fe_csub(fe_add(a0, fe_mul_small(fe_submod(a2, a0), cc)), kP2), kP);  // < 4p before
-        u1 = fe_csub(fe_csub(fe_add(a1, fe_mul_small(fe_submod(a3, a1), cc)), kP2), kP);
+        u0 = lds_fe(sh[pl][t][cc][0]);
+        u1 = lds_fe(sh[pl][t][cc][1]);
       };
       const Fe E = resolve_eq(er);
       acc = fe_addmod(acc, fe_reduce2(fe_mul(point_f<Gate>(get, X), E)));
@@ -992,6 +1027,10 @@ __device__ __forceinline__ void finish_body(const RoundArgs& a, const TabPtrs& d
     if (!ok) set_error(a.ctrl, -5);
   }
   fin_load<Gate::D>(a.ctrl, S);
+  // SPEC: L_c(alpha_{i-1}), stored by the finisher of round i-1
+  if constexpr (SPEC) {
+    if (t >= 192 && t < 192 + (uint32_t)NH) lds_put(lc[t - 192], load_words_fe(a.ctrl->lagr[t - 192]));
+  }
   // point x = t / LP: its LP lanes (the whole block shared by the points,
   // rounded to powers of two) stride over the partials (each < p), lazily
   // summed (at most kMaxBlocks / LP <= 128 terms, < 128 p), reduced, then
@@ -1002,7 +1041,7 @@ __device__ __forceinline__ void finish_body(const RoundArgs& a, const TabPtrs& d
   const uint32_t x = t / LP, g = t % LP;
   Fe v = fe_zero();
   if (x < (uint32_t)NV) {
-#pragma unroll 4
+#pragma unroll 8
     for (uint32_t b = g; b < a.nparts; b += LP) v = fe_add(v, load_words_fe(a.partials + ((uint64_t)b * NV + x) * 8));
     v = fe_reduce128(v);
   }
@@ -1012,21 +1051,6 @@ __device__ __forceinline__ void finish_body(const RoundArgs& a, const TabPtrs& d
   __syncthreads();
   if (S.skip) return;
   if constexpr (SPEC) {
-    constexpr LagrangeW<Gate::D> W{};
-    if (t < (uint32_t)NH) {  // lane c: L_c(alpha) = w_c prod_{k != c} (alpha - k)
-      const Fe al = fe_vgpr(load_words_fe(a.ctrl->alpha_m[a.round - 2]));
-      Fe l = fe_zero();
-      auto pick = [&](auto c) __attribute__((always_inline)) {
-        if (t == (uint32_t)c) l = fe_const(W.w[c]);
-      };
-      Unroll<0, NH>::run(pick);
-      auto term = [&](auto k) __attribute__((always_inline)) {
-        if (t != (uint32_t)k) l = mont(l, fe_submod(al, fe_const(W.node[k])));
-      };
-      Unroll<0, NH>::run(term);
-      lds_put(lc[t], l);
-    }
-    __syncthreads();
     if (t < (uint32_t)NH) {  // lane X: H_i(X) = sum_c L_c H_i(X; c)
       Fe h = fe_zero();
       auto add = [&](auto c) __attribute__((always_inline)) {
@@ -1037,7 +1061,7 @@ __device__ __forceinline__ void finish_body(const RoundArgs& a, const TabPtrs& d
     }
     __syncthreads();
   }
-  emit_round<Gate::D>(a.ctrl, a.round, a.mu, S, a.evals_out, a.alpha_out);
+  emit_round<Gate::D>(a.ctrl, a.round, a.mu, S, a.evals_out, a.alpha_out, a.next_spec != 0);
   if (a.tail) run_tail<Gate>(a, dst, S, SPEC);
 }
 
@@ -1046,16 +1070,15 @@ __global__ __launch_bounds__(kBlock) void k_finish(RoundArgs a, TabPtrs dst) {
   finish_body<Gate>(a, dst);
 }
 
-// The finisher of round r-1 (block 0) beside the speculative evaluation of
-// round r (the other blocks).  FIRST: round r-1 was evaluated normally, and
-// the tables hold T_{r-1}.
+// The finisher of round r-1 (block 0, no tail) beside the speculative
+// evaluation of round r (the other blocks), on the folded copies `tabs`.
+// FIRST: round r-1 was evaluated normally, and the tables hold T_{r-1}.
 template <class Gate, bool FIRST>
-__global__ __launch_bounds__(kBlock) void k_fin_spec(RoundArgs fa, TabPtrs fdst, RoundArgs sa, TabPtrs src,
-                                                     TabPtrs dst) {
+__global__ __launch_bounds__(kBlock) void k_fin_spec(RoundArgs fa, RoundArgs sa, TabPtrs tabs) {
   if (blockIdx.x == 0)
-    finish_body<Gate, !FIRST>(fa, fdst);
+    finish_body<Gate, !FIRST>(fa, tabs);
   else
-    spec_body<Gate, FIRST>(sa, src, dst, blockIdx.x - 1, gridDim.x - 1);
+    spec_body<Gate, FIRST>(sa, tabs, tabs, blockIdx.x - 1, gridDim.x - 1);
 }
 
 // The finisher of the last speculative round, which then runs the tail.
@@ -1136,6 +1159,7 @@ __device__ __forceinline__ RoundArgs batch_round_args(const InstDesc& d, uint32_
   a.tail = round == d.last ? 1u : 0u;
   a.openings = d.openings;
   a.eq = d.eq;
+  a.next_spec = 0;
   return a;
 }
 
