@@ -178,6 +178,40 @@ def test_extreme_values_thread_per_pair_rounds(zc, gate, m):
     assert np.array_equal(res["openings"], ora["openings"])
 
 
+@pytest.mark.parametrize("mu,gate,m", [(15, 0, 0), (16, 0, 0), (17, 0, 0), (17, 1, 2), (17, 1, 1), (17, 2, 3),
+                                       (17, 2, 50), (17, 2, 4), (17, 1, 3)])
+def test_speculative_schedule_boundaries_match_c_oracle(zc, mu, gate, m):
+    """Around the sizes where speculative rounds switch on (degree <= 3 and at
+    least two thread-per-pair rounds: on from mu = 16), for the gates that
+    use them and two that do not (degree 4), against the C oracle."""
+    import ctypes
+    s = zc.shape(mu, gate, m)
+    kinds = [zc.lib().zc_prove_round_kernel(ctypes.byref(s), i) for i in range(1, mu + 1)]
+    assert (5 in kinds) == (zc.degree(s) <= 3 and mu >= 16), kinds
+    inst = I.make_instance(60 + mu, m, mu, gate, m)
+    res = gpu_prove(inst)
+    assert res["err"] == 0
+    ora = C.prove(mu, gate, m, inst.tables, inst.r)
+    assert np.array_equal(res["evals"], ora["evals"]) and np.array_equal(res["alphas"], ora["alphas"])
+    assert np.array_equal(res["openings"], ora["openings"])
+
+
+def test_profiled_prove_equals_prove(zc):
+    """The event-bracketed proof (the bench's path) gives the same bytes as
+    zc_prove, on a speculative schedule."""
+    inst = I.make_instance(71, 0, 17, 0, 0)
+    s = zc.shape(17, 0, 0)
+    ref = gpu_prove(inst)
+    ws = zc.new_workspace(s)
+    tabs = [zc.pack(dev(t), ws) for t in inst.tables]
+    ev = zc.HipEvents(2 * 17)
+    out = zc.prove_profiled(s, tabs, dev(inst.r), ws, ev)
+    assert zc.read_error(ws) == 0
+    for a, b in zip(out, (ref["evals"], ref["alphas"], ref["openings"])):
+        assert np.array_equal(a.cpu().numpy(), b)
+    assert all(ev.elapsed_ms(2 * i, 2 * i + 1) >= 0 for i in range(17))
+
+
 @pytest.mark.parametrize("name", ["plain20_d3", "plain20_d9"])
 def test_full_size_matches_c_oracle(zc, name):
     inst = I.preset_instance(name)
