@@ -20,10 +20,11 @@ struct ServeStep;
 // others run 16 lanes per pair (k_round_split).
 constexpr int kTailQ = 32;  // the tail runs rounds with at most this many pairs
 
-// Rounds with at most this many pairs use sixteen lanes per pair.  One thread
-// per pair is the faster of the two down to 16384 pairs for the gates of
-// degree > 3 and down to 8192 for the lighter ones (measured at mu = 20).
-inline uint64_t split_q(uint32_t degree) { return degree <= 3 ? 8192u : 16384u; }
+// Rounds with at most this many pairs use sixteen lanes per pair: one thread
+// per pair is the faster of the two down to 16384 pairs (measured at mu = 20
+// for degree 9; for degree 3, whose lane-split rounds are speculative, 16384
+// and 8192 measured the same and 4096 slower).
+inline uint64_t split_q(uint32_t) { return 16384u; }
 
 enum RoundKind { kPerPair = 0, kSplit = 1, kSplitTail = 2, kInTail = 3, kSpec = 4, kSpecTail = 5 };
 

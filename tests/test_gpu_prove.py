@@ -178,16 +178,16 @@ def test_extreme_values_thread_per_pair_rounds(zc, gate, m):
     assert np.array_equal(res["openings"], ora["openings"])
 
 
-@pytest.mark.parametrize("mu,gate,m", [(15, 0, 0), (16, 0, 0), (17, 0, 0), (17, 1, 2), (17, 1, 1), (17, 2, 3),
-                                       (17, 2, 50), (17, 2, 4), (17, 1, 3)])
+@pytest.mark.parametrize("mu,gate,m", [(16, 0, 0), (17, 0, 0), (18, 0, 0), (17, 1, 2), (17, 1, 1), (17, 2, 3),
+                                       (17, 2, 50), (18, 2, 2), (17, 2, 4), (17, 1, 3)])
 def test_speculative_schedule_boundaries_match_c_oracle(zc, mu, gate, m):
     """Around the sizes where speculative rounds switch on (degree <= 3 and at
-    least two thread-per-pair rounds: on from mu = 16), for the gates that
+    least two thread-per-pair rounds: on from mu = 17), for the gates that
     use them and two that do not (degree 4), against the C oracle."""
     import ctypes
     s = zc.shape(mu, gate, m)
     kinds = [zc.lib().zc_prove_round_kernel(ctypes.byref(s), i) for i in range(1, mu + 1)]
-    assert (5 in kinds) == (zc.degree(s) <= 3 and mu >= 16), kinds
+    assert (5 in kinds) == (zc.degree(s) <= 3 and mu >= 17), kinds
     inst = I.make_instance(60 + mu, m, mu, gate, m)
     res = gpu_prove(inst)
     assert res["err"] == 0
