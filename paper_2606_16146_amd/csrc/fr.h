@@ -193,8 +193,9 @@ constexpr RPowers kRPow{};
 template <int D>
 struct LagrangeW {
   L9 w[D + 1];
-  L9 node[D + 1];  // c R mod p: the nodes in Montgomery form
-  constexpr LagrangeW() : w{}, node{} {
+  L9 node[D + 1];   // c R mod p: the nodes in Montgomery form
+  L9 wsh[D + 1];    // w_c R^(D+1): D Montgomery products with canonical factors leave w_c (...) R
+  constexpr LagrangeW() : w{}, node{}, wsh{} {
     for (int c = 0; c <= D; ++c) {
       L9 v{};
       for (int k = 0; k < c; ++k) {
@@ -210,6 +211,7 @@ struct LagrangeW {
       L9 v = detail::mont_mul(detail::inv_small(den), kR2);
       if ((D - c) % 2 == 1) v = detail::sub(kP, v);  // the sign of prod (c - k)
       w[c] = v;
+      wsh[c] = detail::mont_mul(v, RPowers{}.v[D]);  // w R * R^(D+1) / R
     }
   }
 };

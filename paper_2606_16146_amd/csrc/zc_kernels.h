@@ -450,6 +450,14 @@ struct RoundArgs {
 // Montgomery product reduced below p.
 __device__ __forceinline__ Fe mont(const Fe& a, const Fe& b) { return fe_reduce2(fe_mul(a, b)); }
 
+// c ? a : b, limb by limb.
+__device__ __forceinline__ Fe fe_sel(bool c, const Fe& a, const Fe& b) {
+  Fe r;
+#pragma unroll
+  for (int i = 0; i < NL; ++i) r.l[i] = c ? a.l[i] : b.l[i];
+  return r;
+}
+
 // The same value, held in vector registers.  A value the compiler can prove
 // uniform across the wave (e.g. read from one LDS or control-block address)
 // would otherwise be multiplied on the scalar unit, where a 32 x 32 -> 64-bit
@@ -608,25 +616,35 @@ __device__ __forceinline__ void emit_round(Ctrl* ctrl, uint32_t round, uint32_t 
     }
   }
   if constexpr (D <= 3) {
-    // with lagr, lane 128 + c: L_c(alpha) = w_c prod_{k != c} (alpha - k) for
-    // the speculative next round's finisher
+    // with lagr, lane 128 + c: L_c(alpha) R = w_c prod_{k != c} (alpha - k) R
+    // for the speculative next round's finisher: the d factors (alpha - k)
+    // canonical, multiplied pairwise onto w_c R^(d+1) (two product levels)
     if (lagr && t >= 128 && t < 128 + (uint32_t)NH) {
+      static_assert(D == 2 || D == 3, "two or three factors");
       constexpr LagrangeW<D> W{};
       const uint32_t c = t - 128;
       uint32_t w[8];
 #pragma unroll
       for (int k = 0; k < 8; ++k) w[k] = S.ac[k];
-      const Fe am = fe_to_mont(fe_vgpr(fe_from_words(w)));
-      Fe l = fe_zero();
-      auto pick = [&](auto k) __attribute__((always_inline)) {
-        if (c == (uint32_t)k) l = fe_const(W.w[k]);
+      const Fe ac = fe_vgpr(fe_from_words(w));
+      Fe tk[NH];  // alpha - k, canonical
+      Fe ws = fe_zero();
+      auto terms = [&](auto k) __attribute__((always_inline)) {
+        Fe kk = fe_zero();
+        kk.l[0] = (uint32_t)k;
+        tk[k] = fe_submod(ac, kk);
+        if (c == (uint32_t)k) ws = fe_const(W.wsh[k]);
       };
-      Unroll<0, NH>::run(pick);
-      auto term = [&](auto k) __attribute__((always_inline)) {
-        if (c != (uint32_t)k) l = mont(l, fe_submod(am, fe_const(W.node[k])));
-      };
-      Unroll<0, NH>::run(term);
-      out = l;
+      Unroll<0, NH>::run(terms);
+      // the factors k != c in order: x, y (, z)
+      const Fe x = fe_sel(c == 0, tk[1], tk[0]);
+      const Fe y = fe_sel(c <= 1, tk[2], tk[1]);
+      if constexpr (D == 3) {
+        const Fe z = fe_sel(c <= 2, tk[3], tk[2]);
+        out = mont(mont(ws, x), mont(y, z));
+      } else {
+        out = mont(mont(ws, x), y);
+      }
     }
   }
   if (t >= 64 && t < 72) S.msg[t - 64] = S.dg[t - 64];

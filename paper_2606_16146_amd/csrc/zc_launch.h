@@ -16,8 +16,6 @@ struct RoundArgs;
 struct BatchStep;
 struct ServeStep;
 
-// Rounds with more pairs than this run one thread per pair (k_round); the
-// others run 16 lanes per pair (k_round_split).
 constexpr int kTailQ = 32;  // the tail runs rounds with at most this many pairs
 
 // Rounds with at most this many pairs use sixteen lanes per pair: one thread
