@@ -486,7 +486,10 @@ __device__ __forceinline__ Fe fe_vgpr(Fe a) {
 //   C_{i+1} R      = P R + mont(alpha_i, Q R^2),
 // with e_x = eq1(x, r_{i+1}) and alpha_i canonical (mont(a, bR) = ab).  The
 // factors that depend on r only (e_x, e_{d+1} lam_k, 1 - r_i, 2 r_i - 1) come
-// from the eq1 rows filled at setup, so the idle wave does two products.
+// from the eq1 rows filled at setup, so two products per lane remain: P then
+// U on one wave, Q then V on another.  A field product is some 160 64-bit
+// multiply-adds, which one wave issues one after another, so each wave of the
+// block is given at most two products in a row.
 
 template <int D>
 struct FinLds {
@@ -502,6 +505,7 @@ struct FinLds {
   uint32_t cm[NL];          // C_i R; C_{i+1} R after emit_round
   uint32_t am[NL];          // alpha_i R after emit_round
   uint32_t ac[8];           // alpha_i canonical words
+  uint32_t lb[NH][NL];      // second factor of L_c(alpha_i) R
   uint32_t msg[LEN / 4];
   uint32_t dg[8];           // T_i
   uint32_t kw[NB * 64];
@@ -532,14 +536,10 @@ __device__ __forceinline__ void emit_round(Ctrl* ctrl, uint32_t round, uint32_t 
   constexpr uint32_t LEN = FinLds<D>::LEN, NB = FinLds<D>::NB;
   static_assert(NH <= 16, "one 16-lane group");
   const uint32_t t = threadIdx.x;
-  // lanes x <= d: G(x) = coef[x] H(x) and the term coefl[x] H(x) of G(d+1)
-  // = sum_x coefl[x] H(x), summed over the 16-lane group by shuffles
-  if (t < 16) {
-    Fe term = fe_zero();
+  if (t < 64) {
+    // wave 0, lanes x <= d: G(x) = coef[x] H(x)
     if (t < (uint32_t)NH) {
-      const Fe h = lds_fe(S.h[t]);
-      const Fe g = mont(lds_fe(S.cf[t]), h);
-      term = mont(lds_fe(S.cf[NE + t]), h);
+      const Fe g = mont(lds_fe(S.cf[t]), lds_fe(S.h[t]));
       uint32_t w[8];
       fe_to_words(g, w);
 #pragma unroll
@@ -548,9 +548,15 @@ __device__ __forceinline__ void emit_round(Ctrl* ctrl, uint32_t round, uint32_t 
         evals_out[t * 8 + k] = w[k];
       }
     }
+  } else if (t < 80) {
+    // wave 1, lanes 64 + x: the terms coefl[x] H(x) of G(d+1) = sum_x
+    // coefl[x] H(x), summed over the 16-lane group by shuffles
+    const uint32_t x = t - 64;
+    Fe term = fe_zero();
+    if (x < (uint32_t)NH) term = mont(lds_fe(S.cf[NE + x]), lds_fe(S.h[x]));
 #pragma unroll
     for (int msk = 8; msk >= 1; msk >>= 1) term = fe_add(term, shfl_xor_fe(term, msk));  // < 16p
-    if (t == 0) {
+    if (x == 0) {
       uint32_t w[8];
       fe_to_words(fe_reduce32(term), w);
 #pragma unroll
@@ -559,22 +565,26 @@ __device__ __forceinline__ void emit_round(Ctrl* ctrl, uint32_t round, uint32_t 
         evals_out[NH * 8 + k] = w[k];
       }
     }
+  } else if (t >= 128 && t < 128 + (uint32_t)NC + 1) {
+    // wave 2: P = C_i (1 - r_i), then U_x = P e_x (the next round's
+    // precomputation, while G is formed and the message expanded, so that
+    // the compression runs alone)
+    const uint32_t l = t - 128;
+    const Eq1Row* rows = eq1_rows(ctrl);
+    const Fe P = mont(fe_vgpr(lds_fe(S.cm)), load_words_fe(rows[round - 1].omr));
+    if (l == (uint32_t)NC)
+      lds_put(S.pc, P);
+    else if (round < mu)
+      lds_put(S.u[l], mont(P, load_words_fe(rows[round].c[l])));
   } else if (t >= 192 && t < 192 + (uint32_t)NC + 1) {
-    // next round's precomputation from the eq1 rows, by an otherwise idle wave
-    // while G is formed and the message expanded, so that the compression
-    // runs alone
+    // wave 3: Q = C_i (2 r_i - 1), then V_x = (Q e_x) R and Q R^2
     const uint32_t l = t - 192;
     const Eq1Row* rows = eq1_rows(ctrl);
-    const Fe cm = fe_vgpr(lds_fe(S.cm));
-    const Fe P = mont(cm, load_words_fe(rows[round - 1].omr));
-    const Fe Q = mont(cm, load_words_fe(rows[round - 1].tr));
-    if (l == (uint32_t)NC) {
-      lds_put(S.pc, P);
+    const Fe Q = mont(fe_vgpr(lds_fe(S.cm)), load_words_fe(rows[round - 1].tr));
+    if (l == (uint32_t)NC)
       lds_put(S.q2, fe_to_mont(Q));
-    } else if (round < mu) {
-      lds_put(S.u[l], mont(P, load_words_fe(rows[round].c[l])));
+    else if (round < mu)
       lds_put(S.v[l], mont(Q, load_words_fe(rows[round].m[l])));
-    }
   }
   __syncthreads();
   sha256_schedule_block<LEN>(S.msg, S.kw);
@@ -616,13 +626,15 @@ __device__ __forceinline__ void emit_round(Ctrl* ctrl, uint32_t round, uint32_t 
     }
   }
   if constexpr (D <= 3) {
-    // with lagr, lane 128 + c: L_c(alpha) R = w_c prod_{k != c} (alpha - k) R
-    // for the speculative next round's finisher: the d factors (alpha - k)
-    // canonical, multiplied pairwise onto w_c R^(d+1) (two product levels)
-    if (lagr && t >= 128 && t < 128 + (uint32_t)NH) {
+    // with lagr, L_c(alpha) R = w_c prod_{k != c} (alpha - k) R for the
+    // speculative next round's finisher, from the d factors (alpha - k)
+    // canonical, multiplied pairwise onto w_c R^(d+1): lane 128 + c forms
+    // (w_c R^(d+1)) x, lane 192 + c the rest (y z, or y when d = 2), and lane
+    // 128 + c their product after the barrier below
+    if (lagr && ((t >= 128 && t < 128 + (uint32_t)NH) || (t >= 192 && t < 192 + (uint32_t)NH))) {
       static_assert(D == 2 || D == 3, "two or three factors");
       constexpr LagrangeW<D> W{};
-      const uint32_t c = t - 128;
+      const uint32_t c = t & 63u;
       uint32_t w[8];
 #pragma unroll
       for (int k = 0; k < 8; ++k) w[k] = S.ac[k];
@@ -637,13 +649,14 @@ __device__ __forceinline__ void emit_round(Ctrl* ctrl, uint32_t round, uint32_t 
       };
       Unroll<0, NH>::run(terms);
       // the factors k != c in order: x, y (, z)
-      const Fe x = fe_sel(c == 0, tk[1], tk[0]);
-      const Fe y = fe_sel(c <= 1, tk[2], tk[1]);
-      if constexpr (D == 3) {
-        const Fe z = fe_sel(c <= 2, tk[3], tk[2]);
-        out = mont(mont(ws, x), mont(y, z));
+      if (t < 192) {
+        out = mont(ws, fe_sel(c == 0, tk[1], tk[0]));
       } else {
-        out = mont(mont(ws, x), y);
+        const Fe y = fe_sel(c <= 1, tk[2], tk[1]);
+        if constexpr (D == 3)
+          lds_put(S.lb[c], mont(y, fe_sel(c <= 2, tk[3], tk[2])));
+        else
+          lds_put(S.lb[c], y);
       }
     }
   }
@@ -661,7 +674,7 @@ __device__ __forceinline__ void emit_round(Ctrl* ctrl, uint32_t round, uint32_t 
     alpha_out[t - 64] = S.ac[t - 64];
     if (t == 64) ctrl->round_done = round;
   } else if (D <= 3 && lagr && t >= 128 && t < 128 + (uint32_t)NH) {
-    store_words_fe(ctrl->lagr[t - 128], out);
+    store_words_fe(ctrl->lagr[t - 128], mont(out, lds_fe(S.lb[t - 128])));
   }
 }
 
