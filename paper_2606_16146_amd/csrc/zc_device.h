@@ -45,13 +45,16 @@ static_assert(sizeof(Ctrl) <= kCtrlBytes, "control block size");
 
 // The eq1 factors of every round, computed once from r at setup; the
 // workspace holds kMuMax of these rows right after the control block.  Row i
-// belongs to r_{i+1}.  With NE = d + 2 and NC = 2d + 3 slots:
+// serves the emission of round i+1, which turns C_{i+1} into C_{i+2} and the
+// coefficients of round i+2.  With NE = d + 2 and NC = 2d + 3 slots, e_l the
+// slot-l factor of r_{i+2} (eq1(x, r_{i+2}) for x = l < NE, else
+// eq1(d+1, r_{i+2}) lam_{l-NE}):
 constexpr int kEq1Slots = 2 * kMaxEvals - 1;
 struct Eq1Row {
-  uint32_t c[kEq1Slots][8];  // eq1(x, r) for x < NE, then eq1(d+1, r) lam_k (k <= d): canonical, < p
-  uint32_t m[kEq1Slots][8];  // the same values in Montgomery form
-  uint32_t omr[8];           // 1 - r, Montgomery form
-  uint32_t tr[8];            // 2 r - 1, Montgomery form
+  uint32_t u[kEq1Slots][8];  // (1 - r_{i+1}) e_l, canonical (zero in the last row)
+  uint32_t v[kEq1Slots][8];  // (2 r_{i+1} - 1) e_l R (zero in the last row)
+  uint32_t omr[8];           // (1 - r_{i+1}) R
+  uint32_t tr2[8];           // (2 r_{i+1} - 1) R^2
 };
 constexpr size_t kEq1Bytes = sizeof(Eq1Row) * kMuMax;
 

@@ -479,17 +479,18 @@ __device__ __forceinline__ Fe fe_vgpr(Fe a) {
 // The coefficients of round i+1 depend on alpha_i only through
 // C_{i+1} = C_i eq1(alpha_i, r_i) = P + alpha_i Q, P = C_i (1 - r_i),
 // Q = C_i (2 r_i - 1).  Everything except the final product with alpha_i is
-// computed by an otherwise idle wave before the SHA-256 compression, so after
+// computed by otherwise idle waves before the SHA-256 compression, so after
 // the hash each coefficient costs one product:
 //   coef_{i+1}[x]  = U_x + mont(alpha_i, V_x),  U_x = P e_x,  V_x = (Q e_x) R,
 //   coefl_{i+1}[k] = Ul_k + mont(alpha_i, Vl_k),
 //   C_{i+1} R      = P R + mont(alpha_i, Q R^2),
 // with e_x = eq1(x, r_{i+1}) and alpha_i canonical (mont(a, bR) = ab).  The
-// factors that depend on r only (e_x, e_{d+1} lam_k, 1 - r_i, 2 r_i - 1) come
-// from the eq1 rows filled at setup, so two products per lane remain: P then
-// U on one wave, Q then V on another.  A field product is some 160 64-bit
-// multiply-adds, which one wave issues one after another, so each wave of the
-// block is given at most two products in a row.
+// factors that depend on r only ((1 - r_i) e_x, (2 r_i - 1) e_x R and the
+// same for e_{d+1} lam_k, (1 - r_i) R, (2 r_i - 1) R^2) are the eq1 rows
+// filled at setup, so each of U, V, P R and Q R^2 is one product with C_i R.
+// A field product is some 160 64-bit multiply-adds, which one wave issues one
+// after another, so the products of one step are spread over the block's
+// waves rather than chained in one.
 
 template <int D>
 struct FinLds {
@@ -565,26 +566,19 @@ __device__ __forceinline__ void emit_round(Ctrl* ctrl, uint32_t round, uint32_t 
         evals_out[NH * 8 + k] = w[k];
       }
     }
-  } else if (t >= 128 && t < 128 + (uint32_t)NC + 1) {
-    // wave 2: P = C_i (1 - r_i), then U_x = P e_x (the next round's
-    // precomputation, while G is formed and the message expanded, so that
-    // the compression runs alone)
-    const uint32_t l = t - 128;
-    const Eq1Row* rows = eq1_rows(ctrl);
-    const Fe P = mont(fe_vgpr(lds_fe(S.cm)), load_words_fe(rows[round - 1].omr));
-    if (l == (uint32_t)NC)
-      lds_put(S.pc, P);
-    else if (round < mu)
-      lds_put(S.u[l], mont(P, load_words_fe(rows[round].c[l])));
-  } else if (t >= 192 && t < 192 + (uint32_t)NC + 1) {
-    // wave 3: Q = C_i (2 r_i - 1), then V_x = (Q e_x) R and Q R^2
-    const uint32_t l = t - 192;
-    const Eq1Row* rows = eq1_rows(ctrl);
-    const Fe Q = mont(fe_vgpr(lds_fe(S.cm)), load_words_fe(rows[round - 1].tr));
-    if (l == (uint32_t)NC)
-      lds_put(S.q2, fe_to_mont(Q));
-    else if (round < mu)
-      lds_put(S.v[l], mont(Q, load_words_fe(rows[round].m[l])));
+  } else if (t >= 128 && t < 128 + 2 * ((uint32_t)NC + 1)) {
+    // waves 2 and 3: the next round's precomputation, one product with C_i R
+    // per lane (the eq1 row holds the other factor), while G is formed and the
+    // message expanded, so that the compression runs alone.  Lane 128 + l:
+    // U_l, then P R; lane 128 + NC + 1 + l: V_l, then Q R^2.
+    const uint32_t k = t - 128, l = k % ((uint32_t)NC + 1);
+    const bool qv = k > (uint32_t)NC;
+    const Eq1Row* row = eq1_rows(ctrl) + (round - 1);
+    const uint32_t* f = l == (uint32_t)NC ? (qv ? row->tr2 : row->omr) : (qv ? row->v[l] : row->u[l]);
+    if (l == (uint32_t)NC || round < mu) {
+      const Fe y = mont(fe_vgpr(lds_fe(S.cm)), load_words_fe(f));
+      lds_put(l == (uint32_t)NC ? (qv ? S.q2 : S.pc) : (qv ? S.v[l] : S.u[l]), y);
+    }
   }
   __syncthreads();
   sha256_schedule_block<LEN>(S.msg, S.kw);
@@ -1082,13 +1076,18 @@ __device__ __forceinline__ void finish_body(const RoundArgs& a, const TabPtrs& d
   __syncthreads();
   if (S.skip) return;
   if constexpr (SPEC) {
-    if (t < (uint32_t)NH) {  // lane X: H_i(X) = sum_c L_c H_i(X; c)
+    // H_i(X) = sum_c L_c H_i(X; c): lane c NP + X of wave 0 forms one product
+    // (NP = NH rounded up to a power of two), and shuffles across the lanes NP
+    // apart sum over c (every term < p, so the sum is the same in any order)
+    constexpr uint32_t NP = NH <= 2 ? 2u : 4u;
+    static_assert(NH <= 4, "degree <= 3");
+    if (t < 64) {
+      const uint32_t c = t / NP, X = t % NP;
       Fe h = fe_zero();
-      auto add = [&](auto c) __attribute__((always_inline)) {
-        h = fe_addmod(h, mont(fe_vgpr(lds_fe(lc[c])), lds_fe(hs[c * NH + t])));
-      };
-      Unroll<0, NH>::run(add);
-      lds_put(S.h[t], h);
+      if (c < (uint32_t)NH && X < (uint32_t)NH) h = mont(fe_vgpr(lds_fe(lc[c])), lds_fe(hs[c * NH + X]));
+#pragma unroll
+      for (uint32_t msk = NP; msk < NP * NP; msk <<= 1) h = fe_addmod(h, shfl_xor_fe(h, (int)msk));
+      if (t < (uint32_t)NH) lds_put(S.h[t], h);
     }
     __syncthreads();
   }

@@ -46,31 +46,44 @@ __device__ __forceinline__ void setup_body(const uint32_t* __restrict__ r, uint3
     if (!words_lt_p(w)) set_error(ctrl, -4);
     store_words_fe(ctrl->r_m[i], fe_to_mont(fe_from_words(w)));
   }
-  // eq1 rows: slot l < nc of round i is eq1(x, r_i) = (1 - r_i) + x (2 r_i - 1)
-  // (x = l < ne, else x = d+1 times lam_{l-ne}); slots nc, nc+1 are 1 - r_i and
-  // 2 r_i - 1.  Round 1's slots l < nc are also coef_1 and coefl_1 (C_1 = 1).
+  // eq1 rows (see Eq1Row): with r = r_{i+1}, eq1(x, r) = (1 - r) + x (2 r - 1)
+  // for slot l < nc (x = l < ne, else x = d+1 times lam_{l-ne}).  Round 1's
+  // slots of r_1 are also coef_1 and coefl_1 (C_1 = 1).
   const uint32_t nc = 2 * ne - 1, d = ne - 2, ns = nc + 2;
   Eq1Row* rows = eq1_rows(ctrl);
-  for (uint32_t idx = threadIdx.x; idx < mu * ns; idx += blockDim.x) {
-    const uint32_t i = idx / ns, l = idx % ns;
+  auto rval = [&](uint32_t i) {  // r_{i+1}, canonical (a value >= p, flagged above, as 0)
     uint32_t w[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) w[k] = r[i * 8 + k];
-    Fe rc = fe_from_words(w);
-    if (!words_lt_p(w)) rc = fe_zero();  // flagged above; keep the arithmetic in range
-    Fe one = fe_zero();
-    one.l[0] = 1;
-    const Fe omr = fe_submod(one, rc);
-    const Fe step = fe_submod(fe_addmod(rc, rc), one);
+    return words_lt_p(w) ? fe_from_words(w) : fe_zero();
+  };
+  Fe one = fe_zero();
+  one.l[0] = 1;
+  auto slot = [&](const Fe& rc, uint32_t l) {  // the slot-l factor of rc, canonical
+    const Fe omr = fe_submod(one, rc), step = fe_submod(fe_addmod(rc, rc), one);
+    const uint32_t x = l < ne ? l : d + 1;
+    Fe e = fe_addmod(omr, fe_reduce32(fe_mul_small(step, x)));
+    if (l >= ne) e = fe_reduce2(fe_mul(e, lam_mont(d, l - ne)));
+    return e;
+  };
+  for (uint32_t idx = threadIdx.x; idx < mu * ns; idx += blockDim.x) {
+    const uint32_t i = idx / ns, l = idx % ns;
+    const Fe rc = rval(i);
+    const Fe omr_m = fe_to_mont(fe_submod(one, rc)), tr_m = fe_to_mont(fe_submod(fe_addmod(rc, rc), one));
     if (l < nc) {
-      const uint32_t x = l < ne ? l : d + 1;
-      Fe e = fe_addmod(omr, fe_reduce32(fe_mul_small(step, x)));
-      if (l >= ne) e = fe_reduce2(fe_mul(e, lam_mont(d, l - ne)));
-      store_words_fe(rows[i].c[l], e);
-      store_words_fe(rows[i].m[l], fe_to_mont(e));
-      if (i == 0) store_words_fe(l < ne ? ctrl->coef[l] : ctrl->coefl[l - ne], e);
+      Fe u = fe_zero(), v = fe_zero();
+      if (i + 1 < mu) {
+        const Fe e = slot(rval(i + 1), l);
+        u = fe_reduce2(fe_mul(omr_m, e));             // (1 - r) e
+        v = fe_reduce2(fe_mul(tr_m, fe_to_mont(e)));  // (2 r - 1) e R
+      }
+      store_words_fe(rows[i].u[l], u);
+      store_words_fe(rows[i].v[l], v);
+      if (i == 0) store_words_fe(l < ne ? ctrl->coef[l] : ctrl->coefl[l - ne], slot(rc, l));
+    } else if (l == nc) {
+      store_words_fe(rows[i].omr, omr_m);
     } else {
-      store_words_fe(l == nc ? rows[i].omr : rows[i].tr, fe_to_mont(l == nc ? omr : step));
+      store_words_fe(rows[i].tr2, fe_to_mont(tr_m));
     }
   }
 }
