@@ -205,35 +205,32 @@ __device__ __forceinline__ void sha256_compress_kw(uint32_t h[8], const uint32_t
   for (int i = 0; i < 8; ++i) h[i] += v[i];
 }
 
-// Message schedules of a LEN-byte message (LEN a multiple of 4, compile-time):
-// lane b < NB of the calling block writes k_t + w_t of block b to kw[64 b + t].
-// Call from every thread; a barrier must follow before the compression.
+// Message schedule of block b of a LEN-byte message (LEN a multiple of 4,
+// compile-time): writes k_t + w_t of block b to kw[64 b + t].  One lane per
+// block; a barrier must follow before the compression reads kw.
 template <uint32_t LEN>
-__device__ __forceinline__ void sha256_schedule_block(const uint32_t* msg, uint32_t* kw) {
+__device__ __forceinline__ void sha256_expand_block(const uint32_t* msg, uint32_t* kw, uint32_t b) {
   static_assert(LEN % 4 == 0, "word-aligned messages only");
   constexpr uint32_t NB = (LEN + 9u + 63u) / 64u;
   constexpr uint32_t TW = NB * 16u;
-  if (threadIdx.x < NB) {
-    const uint32_t b = threadIdx.x;
-    uint32_t W[16];
+  uint32_t W[16];
 #pragma unroll
-    for (uint32_t t = 0; t < 16; ++t) {
-      const uint32_t w = b * 16u + t;
-      uint32_t x = 0;
-      if (w * 4u < LEN) x = sha_bswap(msg[w]);
-      if (w * 4u == LEN) x = 0x80000000u;
-      if (w == TW - 1) x = LEN << 3;
-      W[t] = x;
-      kw[b * 64u + t] = x + kSha256K[t];
-    }
+  for (uint32_t t = 0; t < 16; ++t) {
+    const uint32_t w = b * 16u + t;
+    uint32_t x = 0;
+    if (w * 4u < LEN) x = sha_bswap(msg[w]);
+    if (w * 4u == LEN) x = 0x80000000u;
+    if (w == TW - 1) x = LEN << 3;
+    W[t] = x;
+    kw[b * 64u + t] = x + kSha256K[t];
+  }
 #pragma unroll
-    for (int t = 16; t < 64; ++t) {
-      const uint32_t w15 = W[(t - 15) & 15], w2 = W[(t - 2) & 15];
-      const uint32_t s0 = sha_xor3(sha_rotr(w15, 7), sha_rotr(w15, 18), w15 >> 3);
-      const uint32_t s1 = sha_xor3(sha_rotr(w2, 17), sha_rotr(w2, 19), w2 >> 10);
-      W[t & 15] = W[t & 15] + s0 + W[(t - 7) & 15] + s1;
-      kw[b * 64u + t] = W[t & 15] + kSha256K[t];
-    }
+  for (int t = 16; t < 64; ++t) {
+    const uint32_t w15 = W[(t - 15) & 15], w2 = W[(t - 2) & 15];
+    const uint32_t s0 = sha_xor3(sha_rotr(w15, 7), sha_rotr(w15, 18), w15 >> 3);
+    const uint32_t s1 = sha_xor3(sha_rotr(w2, 17), sha_rotr(w2, 19), w2 >> 10);
+    W[t & 15] = W[t & 15] + s0 + W[(t - 7) & 15] + s1;
+    kw[b * 64u + t] = W[t & 15] + kSha256K[t];
   }
 }
 
@@ -263,8 +260,8 @@ __device__ __forceinline__ uint32_t sha256_schedule_var(const uint32_t* msg, uin
   return nb;
 }
 
-// The compression of nb blocks whose schedules sha256_schedule_block left
-// in kw; one lane.  The digest is in the byte order of sha256().
+// The compression of nb blocks whose schedules sha256_schedule_var left in
+// kw; one lane.  The digest is in the byte order of sha256().
 __device__ __forceinline__ void sha256_compress_blocks(const uint32_t* kw, uint32_t nb, uint32_t out[8]) {
   uint32_t h[8];
   sha256_init(h);

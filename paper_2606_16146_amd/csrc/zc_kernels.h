@@ -581,11 +581,26 @@ __device__ __forceinline__ void emit_round(Ctrl* ctrl, uint32_t round, uint32_t 
     }
   }
   __syncthreads();
-  sha256_schedule_block<LEN>(S.msg, S.kw);
+  // T_round = SHA-256(msg): lane 0 compresses block 0 with its schedule formed
+  // on the fly while lanes 64 + b - 1 expand blocks b >= 1 (which takes less
+  // time), then compresses those from their schedules
+  static_assert(LEN >= 64 && NB - 1 <= 64, "block 0 is all message; one wave expands the rest");
+  uint32_t hv[8];
+  if (t == 0) {
+    sha256_init(hv);
+    uint32_t W[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) W[k] = sha_vreg(sha_bswap(S.msg[k]));
+    sha256_compress(hv, W);
+  } else if (t >= 64 && t < 64 + NB - 1) {
+    sha256_expand_block<LEN>(S.msg, S.kw, t - 63);
+  }
   __syncthreads();
   if (t == 0) {
+#pragma unroll 1
+    for (uint32_t b = 1; b < NB; ++b) sha256_compress_kw(hv, S.kw + b * 64u);
     uint32_t dg[8];
-    sha256_compress_blocks(S.kw, NB, dg);
+    sha256_digest(hv, dg);
     // alpha = digest (little-endian 256-bit integer) mod p; digest < 2^256 < 6p
     Fe al = fe_from_words(dg);
     al = fe_csub(fe_csub(fe_csub(al, kP4), kP2), kP);
