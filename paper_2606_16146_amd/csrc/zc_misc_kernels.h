@@ -25,9 +25,9 @@ __device__ __forceinline__ Fe lam_mont(uint32_t d, uint32_t k) {
 }
 
 // One block: resets the control block, checks r, keeps it in canonical and
-// Montgomery form, sets C_1 = 1, fills the eq1 rows of every round and
-// from row 1 coef_1[x] = eq1(x, r_1) for x < ne and coefl_1.  (T_0 is hashed
-// by t0_body, in another block of the same launch.)
+// Montgomery form, sets C_1 = 1, fills the eq1 rows of every round and sets
+// coef_1[x] = eq1(x, r_1) for x < ne and coefl_1.  (T_0 is hashed by
+// t0_body, in another block of the same launch.)
 __device__ __forceinline__ void setup_body(const uint32_t* __restrict__ r, uint32_t mu, uint32_t ne, Ctrl* ctrl) {
   if (threadIdx.x == 0) {
     ctrl->err = 0;
@@ -46,9 +46,11 @@ __device__ __forceinline__ void setup_body(const uint32_t* __restrict__ r, uint3
     if (!words_lt_p(w)) set_error(ctrl, -4);
     store_words_fe(ctrl->r_m[i], fe_to_mont(fe_from_words(w)));
   }
-  // eq1 rows (see Eq1Row): with r = r_{i+1}, eq1(x, r) = (1 - r) + x (2 r - 1)
-  // for slot l < nc (x = l < ne, else x = d+1 times lam_{l-ne}).  Round 1's
-  // slots of r_1 are also coef_1 and coefl_1 (C_1 = 1).
+  // eq1 rows (see Eq1Row).  The slot-l factor of a challenge r (l < nc) is
+  // eq1(x, r) = (1 - r) + x (2 r - 1), x = l < ne, else x = d+1 times
+  // lam_{l-ne}.  Row i takes 1 - r and 2 r - 1 from r_{i+1} and the slot
+  // factors from r_{i+2}; the slot factors of r_1 are coef_1 and coefl_1
+  // (C_1 = 1).
   const uint32_t nc = 2 * ne - 1, d = ne - 2, ns = nc + 2;
   Eq1Row* rows = eq1_rows(ctrl);
   auto rval = [&](uint32_t i) {  // r_{i+1}, canonical (a value >= p, flagged above, as 0)
