@@ -221,3 +221,20 @@ def test_full_size_matches_c_oracle(zc, name):
     assert (res["evals"] == ora["evals"]).all()
     assert (res["alphas"] == ora["alphas"]).all()
     assert (res["openings"] == ora["openings"]).all()
+
+
+@pytest.mark.parametrize("mu,gate,m", [(24, I.GATE_VANILLA, 0), (23, I.GATE_PROD, 8)])
+def test_large_mu_multichunk_lazy_sums_match_c_oracle(zc, mu, gate, m):
+    """mu = 23-24: round 1's grid is one resident generation (one 256-thread
+    block per CU at these kernels' register use), so its 2^(mu-1) pairs give
+    every thread 64 or 128 pairs, several chunks of lazily summed pairs with
+    a reduction between them (mu = 20 has 8 pairs per thread, a single
+    chunk); the grid-stride loops of rounds 2-5 also take several pairs per
+    thread.  Compared with the C oracle."""
+    inst = I.make_instance(7, 0, mu, gate, m, workers=8)
+    res = gpu_prove(inst)
+    assert res["err"] == 0
+    ora = C.prove(inst.mu, inst.gate, inst.m, inst.tables, inst.r)
+    assert (res["evals"] == ora["evals"]).all()
+    assert (res["alphas"] == ora["alphas"]).all()
+    assert (res["openings"] == ora["openings"]).all()
