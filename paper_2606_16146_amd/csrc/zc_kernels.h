@@ -479,7 +479,7 @@ __device__ __forceinline__ Fe fe_vgpr(Fe a) {
 // The coefficients of round i+1 depend on alpha_i only through
 // C_{i+1} = C_i eq1(alpha_i, r_i) = P + alpha_i Q, P = C_i (1 - r_i),
 // Q = C_i (2 r_i - 1).  Everything except the final product with alpha_i is
-// computed by otherwise idle waves before the SHA-256 compression, so after
+// computed by otherwise idle lanes before the SHA-256 compression, so after
 // the hash each coefficient costs one product:
 //   coef_{i+1}[x]  = U_x + mont(alpha_i, V_x),  U_x = P e_x,  V_x = (Q e_x) R,
 //   coefl_{i+1}[k] = Ul_k + mont(alpha_i, Vl_k),
@@ -567,10 +567,11 @@ __device__ __forceinline__ void emit_round(Ctrl* ctrl, uint32_t round, uint32_t 
       }
     }
   } else if (t >= 128 && t < 128 + 2 * ((uint32_t)NC + 1)) {
-    // waves 2 and 3: the next round's precomputation, one product with C_i R
-    // per lane (the eq1 row holds the other factor), while G is formed and the
-    // message expanded, so that the compression runs alone.  Lane 128 + l:
-    // U_l, then P R; lane 128 + NC + 1 + l: V_l, then Q R^2.
+    // lanes 128 on (wave 2, and wave 3 past 64 lanes): the next round's
+    // precomputation, one product with C_i R per lane (the eq1 row holds the
+    // other factor), while G is formed, so that the hash runs alone.  Lanes
+    // 128 + l (l < NC): U_l, lane 128 + NC: P R; lanes 128 + NC + 1 + l: V_l,
+    // lane 128 + 2 NC + 1: Q R^2.
     const uint32_t k = t - 128, l = k % ((uint32_t)NC + 1);
     const bool qv = k > (uint32_t)NC;
     const Eq1Row* row = eq1_rows(ctrl) + (round - 1);
