@@ -387,6 +387,66 @@ def run_serve(name, check=4):
     return out
 
 
+def run_peaks():
+    """Peak-rate microbenchmarks on the GPU: v_mad_u64_u32 (the instruction of
+    the field product), the library's Montgomery product, and the single-lane
+    SHA-256 compression of the transcript.  Each figure is the median of 5
+    event-timed launches after a warm-up."""
+    import torch
+
+    from paper_2606_16146_amd import inputs as I
+    from paper_2606_16146_amd import zc
+
+    dev = torch.device("cuda:0")
+    props = torch.cuda.get_device_properties(dev)
+    cus = props.multi_processor_count
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            b.synchronize()
+            ts.append(a.elapsed_time(b) * 1e-3)
+        return statistics.median(ts)
+
+    sink = torch.zeros(1 << 16, dtype=torch.uint32, device=dev)
+    out = {"cus": cus}
+    # full occupancy: 8 blocks of 256 threads per CU (8 waves per SIMD), 8 chains per thread
+    for blocks_per_cu, chains, iters, key in ((8, 8, 256, "mad_full"), (1, 8, 2048, "mad_1wave_8chains"),
+                                              (1, 1, 4096, "mad_1wave_1chain")):
+        blocks = cus * blocks_per_cu
+        t = timed(lambda: zc.bench_mad(blocks, chains, iters, sink))
+        ops = blocks * 256 * chains * iters * 32
+        out[key] = {"blocks": blocks, "chains": chains, "ops": ops, "s": t, "tops": ops / t / 1e12,
+                    "ns_per_dependent_step": t / (iters * 32) * 1e9}
+    elems = torch.from_numpy(I.draw_elements(1, 0, 0, 64)).to(dev)
+    fo = torch.zeros(1 << 16, dtype=torch.uint32, device=dev)
+    # the round kernels hold one wave per SIMD; 4 waves per SIMD is what a light kernel would get
+    for blocks_per_cu, chains, iters, key in ((4, 4, 512, "fmul_4waves_4chains"), (1, 4, 1024, "fmul_1wave_4chains"),
+                                              (1, 1, 2048, "fmul_1wave_1chain")):
+        blocks = cus * blocks_per_cu
+        t = timed(lambda: zc.bench_fmul(blocks, chains, iters, elems, fo))
+        prods = blocks * 256 * chains * iters
+        out[key] = {"blocks": blocks, "chains": chains, "products": prods, "s": t,
+                    "gprod_per_s": prods / t / 1e9, "ns_per_dependent_product": t / iters * 1e9}
+    so = torch.zeros(16 + 256, dtype=torch.uint32, device=dev)
+    for variant, key in ((0, "sha_block_kw_lds"), (1, "sha_block_on_the_fly"), (2, "sha_block_kw_lds_beside_products")):
+        n = 4000
+        t = timed(lambda: zc.bench_sha(variant, n, elems, so))
+        v = so.cpu().numpy().astype("uint64")
+        cyc, ticks = int(v[8] | (v[9] << 32)), int(v[10] | (v[11] << 32))
+        out[key] = {"blocks": n, "s": t, "us_per_block": t / n * 1e6, "shader_ghz": cyc / (ticks * 10.0),
+                    "cycles_per_round": cyc / (n * 64)}
+    for k, v in out.items():
+        log(f"[peaks] {k}: {v}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -401,6 +461,9 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB three times (the known-size "
                          "kernel against which profiler byte counters are scaled)")
+    ap.add_argument("--peaks", action="store_true",
+                    help="only run the peak-rate microbenchmarks (v_mad_u64_u32, field product, SHA-256) "
+                         "and print them as one JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the prover runs on a single MI355X; "
@@ -413,6 +476,10 @@ def main():
         sys.exit(1)
     from paper_2606_16146_amd import zc
     zc.lib()  # fail loudly if the HIP library is missing
+
+    if args.peaks:
+        print(json.dumps({"peaks": run_peaks()}), flush=True)
+        return
 
     if args.copy_calibration > 0:
         # the source is written first and then pushed out of the caches by an

@@ -53,6 +53,31 @@ int zc_prove_profiled(const zc_shape* shape, const uint32_t* const* tables, cons
    Negative zc_status for a bad shape or i. */
 int zc_prove_round_kernel(const zc_shape* shape, uint32_t i);
 
+/* ---- peak-rate microbenchmarks (timed by the caller with events on `stream`) ----
+
+   zc_bench_mad: `blocks` blocks of 256 threads; each thread runs `chains`
+   (1 or 8) independent chains of iters * 32 dependent v_mad_u64_u32
+   (64-bit multiply-add, the instruction of the field product).  Operations:
+   blocks * 256 * chains * iters * 32.  sink: device, >= blocks words (written
+   only for one improbable value). */
+int zc_bench_mad(uint32_t blocks, uint32_t chains, uint32_t iters, uint32_t* sink, hipStream_t stream);
+
+/* zc_bench_fmul: the library's Montgomery product (radix 2^29 product
+   scanning), `chains` (1 or 4) independent chains of `iters` products per
+   thread over `blocks` blocks of 256 threads.  in: 64 elements (uint32[64][8],
+   limbs < 2^29 after conversion, values < p); out: device, >= 64 * 8 words. */
+int zc_bench_fmul(uint32_t blocks, uint32_t chains, uint32_t iters, const uint32_t* in, uint32_t* out,
+                  hipStream_t stream);
+
+/* zc_bench_sha: one lane chains n SHA-256 compressions of a 64-byte block;
+   variant 0 reads k_t + w_t from LDS, variant 1 expands the message schedule
+   on the fly, variant 2 is variant 0 while the block's three other waves
+   multiply field elements.  in: 64 elements (uint32[64][8], values < p).
+   out: device uint32[16 + 256]: [0..8) the final chaining value, [8..10) the
+   shader clock cycles of lane 0's loop (s_memtime, lo/hi), [10..12) the same
+   interval in 100 MHz ticks (s_memrealtime), the rest scratch. */
+int zc_bench_sha(uint32_t variant, uint32_t n, const uint32_t* in, uint32_t* out, hipStream_t stream);
+
 /* SHA-256 of len bytes (msg: little-endian packed uint32 words); out: 32 bytes as uint32[8]. */
 int zc_test_sha256(const uint32_t* msg, uint32_t len, uint32_t* out, hipStream_t stream);
 

@@ -54,6 +54,9 @@ _SIGS = {
     "zc_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "zc_test_field": (ctypes.c_int, [ctypes.c_int, _VP, _VP, _VP, ctypes.c_uint64, _VP]),
     "zc_test_sha256": (ctypes.c_int, [_VP, ctypes.c_uint32, _VP, _VP]),
+    "zc_bench_mad": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, _VP, _VP]),
+    "zc_bench_fmul": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, _VP, _VP, _VP]),
+    "zc_bench_sha": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32, _VP, _VP, _VP]),
     "zc_prove_round_kernel": (ctypes.c_int, [ctypes.POINTER(Shape), ctypes.c_uint32]),
     "zc_prove_profiled": (ctypes.c_int, [ctypes.POINTER(Shape), _VP, _VP, _VP, _VP, _VP, _VP, _VP,
                                          _VP]),
@@ -308,3 +311,15 @@ def test_sha256(msg_words: torch.Tensor, length: int, stream=None) -> torch.Tens
     _check(lib().zc_test_sha256(_ptr(msg_words), length, _ptr(out), _stream(stream)),
            "zc_test_sha256")
     return out
+
+
+def bench_mad(blocks: int, chains: int, iters: int, sink: torch.Tensor, stream=None):
+    _check(lib().zc_bench_mad(blocks, chains, iters, _ptr(sink), _stream(stream)), "zc_bench_mad")
+
+
+def bench_fmul(blocks: int, chains: int, iters: int, inp: torch.Tensor, out: torch.Tensor, stream=None):
+    _check(lib().zc_bench_fmul(blocks, chains, iters, _ptr(inp), _ptr(out), _stream(stream)), "zc_bench_fmul")
+
+
+def bench_sha(variant: int, n: int, inp: torch.Tensor, out: torch.Tensor, stream=None):
+    _check(lib().zc_bench_sha(variant, n, _ptr(inp), _ptr(out), _stream(stream)), "zc_bench_sha")
