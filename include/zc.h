@@ -50,7 +50,8 @@ typedef enum {
   ZC_EUNSUPPORTED = -2, /* unknown gate or gate parameter */
   ZC_EHIP = -3,         /* a HIP call or kernel launch failed */
   ZC_ERANGE = -4,       /* (device) an input element was >= p */
-  ZC_ESTATE = -5        /* (device) zc_round / zc_fold called out of order */
+  ZC_ESTATE = -5,       /* (device) zc_round / zc_fold called out of order */
+  ZC_ETOOBIG = -6       /* the shape needs more workspace than zc_prove_static holds */
 } zc_status;
 
 typedef enum {
@@ -106,6 +107,26 @@ int zc_unpack(const uint32_t* mont_planar, uint64_t pitch, uint32_t* canon, uint
                column order, then eq_r(alpha), canonical. */
 int zc_prove(const zc_shape* shape, const uint32_t* const* tables, const uint32_t* r, void* ws,
              uint32_t* round_evals, uint32_t* challenges, uint32_t* openings, hipStream_t stream);
+
+/* zc_prove without a workspace argument, for callers that cannot allocate
+   device memory (code under HIP graph capture, tight serving loops, hosts
+   that forbid allocation).  Same launches, same output bytes as zc_prove.
+   The workspace is a 32 MiB array in the library's device code, one per
+   device, held from the library's first use on that device until the
+   process ends; its device address is looked up once per device, on the
+   first call (on the device of `stream`, the current device for the null
+   stream).  No allocating call is made.
+   Limit: shapes with zc_workspace_bytes(shape) <= 32 MiB (every gate up to
+   mu = 17); larger shapes return ZC_ETOOBIG and enqueue nothing.
+   status      out (device, may be NULL): the device-detected status of the
+               proof (ZC_OK, or ZC_ERANGE for an r_i >= p), written last.
+   All calls on one device share the array and its control block: calls
+   that overlap in time on one device (different streams, or host threads)
+   race and must be serialized by the caller.  Each call resets what must
+   start cleared; the array keeps the last call's contents. */
+int zc_prove_static(const zc_shape* shape, const uint32_t* const* tables, const uint32_t* r,
+                    uint32_t* round_evals, uint32_t* challenges, uint32_t* openings, int32_t* status,
+                    hipStream_t stream);
 
 /* Stepping form of the same proof, same bytes as zc_prove.
    zc_round(i), 1 <= i <= mu: evaluates G_i on tables that have been folded

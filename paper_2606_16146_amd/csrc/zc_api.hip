@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cstddef>
 #include <cstdint>
+#include <mutex>
 #include <vector>
 
 #include "../../include/zc.h"
@@ -14,6 +15,11 @@
 #include "zc_misc_kernels.h"
 
 using namespace zc;
+
+// Workspace of zc_prove_static (see static_scratch below): one copy per
+// device, held for the life of the process.
+constexpr size_t kStaticScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) uint8_t zc_static_scratch[kStaticScratchBytes];
 
 namespace {
 
@@ -423,6 +429,49 @@ __global__ __launch_bounds__(kBlock) void k_serve_setup_eq(InstDesc* __restrict_
   }
 }
 
+// ---- the proof that allocates nothing ----------------------------------------
+//
+// zc_prove_static runs zc_prove with the workspace in this file-scope device
+// array instead of a caller buffer.  Each device the library runs on holds
+// its own copy (kStaticScratchBytes) for the life of the process.  The name
+// is only a host-side stand-in for the array: its device address is asked
+// once per device with hipGetSymbolAddress and that address is what the
+// kernels receive.
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void* g_static_ptr[kMaxDevices];
+
+// Device address of zc_static_scratch on the stream's device (the current
+// device for the null stream).
+int static_scratch(hipStream_t stream, void** out) {
+  int dev = 0;
+  if (stream) {
+    if (hipStreamGetDevice(stream, &dev) != hipSuccess) return ZC_EHIP;
+  } else if (hipGetDevice(&dev) != hipSuccess) {
+    return ZC_EHIP;
+  }
+  if (dev < 0 || dev >= kMaxDevices) return ZC_EHIP;
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  if (!g_static_ptr[dev]) {
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess) return ZC_EHIP;
+    if (cur != dev && hipSetDevice(dev) != hipSuccess) return ZC_EHIP;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(zc_static_scratch));
+    if (cur != dev && hipSetDevice(cur) != hipSuccess) return ZC_EHIP;
+    if (e != hipSuccess || !p) return ZC_EHIP;
+    g_static_ptr[dev] = p;
+  }
+  *out = g_static_ptr[dev];
+  return ZC_OK;
+}
+
+// Copies the device-detected status of a proof out of its control block.
+__global__ void k_status_out(const Ctrl* ctrl, int32_t* status) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *status = (int32_t)ctrl->err;
+}
+
 uint32_t last_round(uint32_t mu) { return mu <= 6 ? 1u : mu - 6; }
 
 uint32_t tile_blocks(uint32_t mu, uint32_t round, uint32_t tile) {
@@ -483,6 +532,25 @@ int zc_unpack(const uint32_t* mont_planar, uint64_t pitch, uint32_t* canon, uint
 int zc_prove(const zc_shape* shape, const uint32_t* const* tables, const uint32_t* r, void* ws,
              uint32_t* round_evals, uint32_t* challenges, uint32_t* openings, hipStream_t stream) {
   return prove_impl(shape, tables, r, ws, round_evals, challenges, openings, stream, nullptr);
+}
+
+int zc_prove_static(const zc_shape* shape, const uint32_t* const* tables, const uint32_t* r, uint32_t* round_evals,
+                    uint32_t* challenges, uint32_t* openings, int32_t* status, hipStream_t stream) {
+  Layout L;
+  int rc = make_layout(shape, &L);
+  if (rc != ZC_OK) return rc;
+  if (L.total > kStaticScratchBytes) return ZC_ETOOBIG;
+  if ((rc = check_tables(L, tables)) != ZC_OK) return rc;
+  if (!r || !round_evals || !challenges || !openings) return ZC_EINVAL;
+  void* ws = nullptr;
+  if ((rc = static_scratch(stream, &ws)) != ZC_OK) return rc;
+  if ((rc = prove_impl(shape, tables, r, ws, round_evals, challenges, openings, stream, nullptr)) != ZC_OK)
+    return rc;
+  if (status) {
+    hipLaunchKernelGGL(k_status_out, dim3(1), dim3(64), 0, stream, ctrl_of(ws), status);
+    return launch_ok();
+  }
+  return ZC_OK;
 }
 
 int zc_prove_profiled(const zc_shape* shape, const uint32_t* const* tables, const uint32_t* r, void* ws,
@@ -665,6 +733,7 @@ const char* zc_strerror(int status) {
     case ZC_EHIP: return "HIP call or kernel launch failed";
     case ZC_ERANGE: return "input element not below p";
     case ZC_ESTATE: return "zc_round / zc_fold called out of order";
+    case ZC_ETOOBIG: return "shape needs more workspace than zc_prove_static holds (32 MiB)";
     default: return "unknown status";
   }
 }

@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("ZC_LIB") or os.path.join(HERE, "libzc.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
-ZC_OK, ZC_EINVAL, ZC_EUNSUPPORTED, ZC_EHIP, ZC_ERANGE, ZC_ESTATE = 0, -1, -2, -3, -4, -5
+ZC_OK, ZC_EINVAL, ZC_EUNSUPPORTED, ZC_EHIP, ZC_ERANGE, ZC_ESTATE, ZC_ETOOBIG = 0, -1, -2, -3, -4, -5, -6
 GATE_VANILLA, GATE_PROD, GATE_SUMPROD = 0, 1, 2
 
 
@@ -48,6 +48,7 @@ _SIGS = {
     "zc_pack": (ctypes.c_int, [_VP, _VP, ctypes.c_uint64, _VP, _VP]),
     "zc_unpack": (ctypes.c_int, [_VP, ctypes.c_uint64, _VP, ctypes.c_uint64, _VP]),
     "zc_prove": (ctypes.c_int, [ctypes.POINTER(Shape), _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "zc_prove_static": (ctypes.c_int, [ctypes.POINTER(Shape), _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "zc_round": (ctypes.c_int, [ctypes.POINTER(Shape), _VP, _VP, _VP, ctypes.c_uint32, _VP, _VP, _VP]),
     "zc_fold": (ctypes.c_int, [ctypes.POINTER(Shape), _VP, _VP, ctypes.c_uint32, _VP]),
     "zc_read_error": (ctypes.c_int, [_VP, _VP]),
@@ -174,6 +175,20 @@ def prove(s: Shape, tables, r: torch.Tensor, ws: torch.Tensor, outputs=None, str
     rc = lib().zc_prove(ctypes.byref(s), arr, _ptr(r), _ptr(ws), _ptr(evals), _ptr(alphas),
                         _ptr(openings), _stream(stream))
     _check(rc, "zc_prove")
+    return evals, alphas, openings
+
+
+def prove_static(s: Shape, tables, r: torch.Tensor, outputs=None, status: torch.Tensor | None = None,
+                 stream=None):
+    """zc_prove_static: the whole proof in the library's own per-device
+    workspace (no workspace argument).  Returns (round_evals, challenges,
+    openings); `status` (int32[1] device tensor), if given, receives the
+    device-detected status."""
+    evals, alphas, openings = outputs if outputs is not None else new_outputs(s, r.device)
+    arr = _table_array(tables)
+    rc = lib().zc_prove_static(ctypes.byref(s), arr, _ptr(r), _ptr(evals), _ptr(alphas), _ptr(openings),
+                               _ptr(status) if status is not None else None, _stream(stream))
+    _check(rc, "zc_prove_static")
     return evals, alphas, openings
 
 

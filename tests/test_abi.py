@@ -65,8 +65,30 @@ def test_host_validation_rejects_bad_arguments_without_gpu():
     assert h.zc_unpack(fake, 2, fake, 4, None) == zc.ZC_EINVAL  # pitch < n
 
 
+def test_static_prove_rejects_before_any_gpu_work():
+    """zc_prove_static checks its shape against its fixed 32 MiB workspace and
+    its pointers on the host, before it looks up the device array."""
+    h = zc.lib()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    tabs = (ctypes.c_void_p * 10)(*([0x1000] * 10))
+    for mu, gate, m in ((18, 0, 0), (18, 1, 8), (24, 0, 0), (30, 1, 1)):
+        s = zc.shape(mu, gate, m)
+        assert zc.workspace_bytes(s) > 32 << 20
+        assert h.zc_prove_static(ctypes.byref(s), tabs, fake, fake, fake, fake, None, None) == zc.ZC_ETOOBIG
+    for mu, gate, m in ((17, 0, 0), (17, 1, 8), (18, 2, 50)):  # the largest shapes that fit
+        assert zc.workspace_bytes(zc.shape(mu, gate, m)) <= 32 << 20
+    s = zc.shape(17, 1, 8)
+    null_tabs = (ctypes.c_void_p * 10)(*([0x1000] * 9 + [0]))
+    assert h.zc_prove_static(ctypes.byref(s), null_tabs, fake, fake, fake, fake, None, None) == zc.ZC_EINVAL
+    assert h.zc_prove_static(ctypes.byref(s), tabs, None, fake, fake, fake, None, None) == zc.ZC_EINVAL
+    assert h.zc_prove_static(ctypes.byref(s), tabs, fake, fake, None, fake, None, None) == zc.ZC_EINVAL
+    assert h.zc_prove_static(None, tabs, fake, fake, fake, fake, None, None) == zc.ZC_EINVAL
+    bad = zc.shape(4, 7)
+    assert h.zc_prove_static(ctypes.byref(bad), tabs, fake, fake, fake, fake, None, None) == zc.ZC_EUNSUPPORTED
+
+
 def test_strerror_covers_every_status():
-    for st in (0, -1, -2, -3, -4, -5):
+    for st in (0, -1, -2, -3, -4, -5, -6):
         assert zc.strerror(st) and zc.strerror(st) != "unknown status"
     assert zc.strerror(-99) == "unknown status"
 
