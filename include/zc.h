@@ -87,13 +87,14 @@ size_t zc_workspace_bytes(const zc_shape* shape);
 
 /* Convert n canonical elements (canon: uint32[n][8], 16-byte aligned) into the
    internal limb-planar Montgomery form (mont_planar: uint32[8][n], pitch n),
-   1 <= n <= 2^31.
+   1 <= n <= 2^30 (the table of mu = 30; larger n returns ZC_EINVAL).
    Elements >= p are flagged (ZC_ERANGE via zc_read_error); only the control
    block of ws is used, so a workspace of any valid shape will do. */
 int zc_pack(const uint32_t* canon, uint32_t* mont_planar, uint64_t n, void* ws, hipStream_t stream);
 
 /* Inverse of zc_pack for the first n elements of a limb-planar table with the
-   given pitch (canon: uint32[n][8], 16-byte aligned). */
+   given pitch (canon: uint32[n][8], 16-byte aligned), 1 <= n <= 2^30,
+   pitch >= n. */
 int zc_unpack(const uint32_t* mont_planar, uint64_t pitch, uint32_t* canon, uint64_t n, hipStream_t stream);
 
 /* Whole proof (Fig. 2, right).

@@ -79,6 +79,11 @@ int make_layout(const zc_shape* s, Layout* L) {
   return ZC_OK;
 }
 
+// Largest table (mu = kMuMax): element indices stay below 2^30, so the
+// kernels' 32-bit byte offsets (4 j) cannot wrap.
+constexpr uint64_t kMaxElems = 1ull << kMuMax;
+static_assert(kMuMax <= 30, "element byte offsets are 32-bit");
+
 inline uint32_t grid_for(uint64_t work, uint32_t cap) {
   uint64_t b = (work + kBlock - 1) / kBlock;
   if (b < 1) b = 1;
@@ -516,7 +521,7 @@ size_t zc_workspace_bytes(const zc_shape* shape) {
 }
 
 int zc_pack(const uint32_t* canon, uint32_t* mont_planar, uint64_t n, void* ws, hipStream_t stream) {
-  if (!canon || !mont_planar || !ws || n == 0 || n > (1ull << 31) || !aligned(canon, 16) || !aligned(ws, 256))
+  if (!canon || !mont_planar || !ws || n == 0 || n > kMaxElems || !aligned(canon, 16) || !aligned(ws, 256))
     return ZC_EINVAL;
   hipLaunchKernelGGL(k_pack, dim3(grid_for(n, 8192)), dim3(kBlock), 0, stream, canon, mont_planar, n, n,
                      ctrl_of(ws));
@@ -524,7 +529,7 @@ int zc_pack(const uint32_t* canon, uint32_t* mont_planar, uint64_t n, void* ws, 
 }
 
 int zc_unpack(const uint32_t* mont_planar, uint64_t pitch, uint32_t* canon, uint64_t n, hipStream_t stream) {
-  if (!canon || !mont_planar || n == 0 || n > (1ull << 31) || pitch < n || !aligned(canon, 16)) return ZC_EINVAL;
+  if (!canon || !mont_planar || n == 0 || n > kMaxElems || pitch < n || !aligned(canon, 16)) return ZC_EINVAL;
   hipLaunchKernelGGL(k_unpack, dim3(grid_for(n, 8192)), dim3(kBlock), 0, stream, mont_planar, pitch, canon, n);
   return launch_ok();
 }

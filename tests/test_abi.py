@@ -63,6 +63,11 @@ def test_host_validation_rejects_bad_arguments_without_gpu():
                       None) == zc.ZC_EINVAL
     assert h.zc_pack(None, fake, 4, fake, None) == zc.ZC_EINVAL
     assert h.zc_unpack(fake, 2, fake, 4, None) == zc.ZC_EINVAL  # pitch < n
+    # element indices must stay below 2^30 (32-bit byte offsets in the kernels)
+    big = (1 << 30) + 1
+    assert h.zc_pack(fake, fake, big, fake, None) == zc.ZC_EINVAL
+    assert h.zc_unpack(fake, big, fake, big, None) == zc.ZC_EINVAL
+    assert h.zc_pack(fake, fake, 0, fake, None) == zc.ZC_EINVAL
 
 
 def test_static_prove_rejects_before_any_gpu_work():
