@@ -254,6 +254,22 @@ __device__ __forceinline__ Fe fe_from_words(const uint32_t w[8]) {
   return r;
 }
 
+// 9 words (a value < 2^261) -> 9 x 29-bit limbs.
+__device__ __forceinline__ Fe fe_from_words9(const uint32_t w[9]) {
+  Fe r;
+#pragma unroll
+  for (int i = 0; i < NL; ++i) {
+    const int bit = 29 * i, wi = bit / 32, s = bit % 32;
+    uint32_t x;
+    if (wi + 1 < 9 && s + 29 > 32)
+      x = __builtin_amdgcn_alignbit(w[wi + 1], w[wi], s);
+    else
+      x = w[wi] >> s;
+    r.l[i] = x & LM;
+  }
+  return r;
+}
+
 // Requires normalized limbs and a value < 2^256.
 __device__ __forceinline__ void fe_to_words(const Fe& a, uint32_t w[8]) {
 #pragma unroll

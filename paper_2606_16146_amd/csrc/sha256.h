@@ -177,32 +177,61 @@ __device__ inline void sha256(const uint32_t* msg, uint32_t len, uint32_t out[8]
 // round constants added) into LDS while the compression, the serial part,
 // runs afterwards in lane 0 and reads k_t + w_t from there.
 
+// 16 rounds from the words k[0..15] = k_t + w_t (the eight working
+// variables' roles rotate, so 16 unrolled rounds need no moves).
+__device__ __forceinline__ void sha256_16kw(uint32_t v[8], const uint32_t k[16]) {
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    switch (r & 7) {
+      case 0: ZC_SHA_ROUND(v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7], k[r]); break;
+      case 1: ZC_SHA_ROUND(v[7], v[0], v[1], v[2], v[3], v[4], v[5], v[6], k[r]); break;
+      case 2: ZC_SHA_ROUND(v[6], v[7], v[0], v[1], v[2], v[3], v[4], v[5], k[r]); break;
+      case 3: ZC_SHA_ROUND(v[5], v[6], v[7], v[0], v[1], v[2], v[3], v[4], k[r]); break;
+      case 4: ZC_SHA_ROUND(v[4], v[5], v[6], v[7], v[0], v[1], v[2], v[3], k[r]); break;
+      case 5: ZC_SHA_ROUND(v[3], v[4], v[5], v[6], v[7], v[0], v[1], v[2], k[r]); break;
+      case 6: ZC_SHA_ROUND(v[2], v[3], v[4], v[5], v[6], v[7], v[0], v[1], k[r]); break;
+      default: ZC_SHA_ROUND(v[1], v[2], v[3], v[4], v[5], v[6], v[7], v[0], k[r]); break;
+    }
+  }
+}
+
+// Rounds 16 it0 .. 63 on the working variables v, with k_t + w_t read from
+// kw[0..63] (LDS).  Each group's 16 words are read during the previous
+// group, so the rounds do not wait on LDS.
+__device__ __forceinline__ void sha256_rounds_kw(uint32_t v[8], const uint32_t* kw, int it0) {
+  uint32_t k[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) k[r] = kw[16 * it0 + r];
+#pragma unroll 1
+  for (int it = it0; it < 4; ++it) {
+    const int nx = it < 3 ? it + 1 : 3;
+    uint32_t kn[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) kn[r] = kw[16 * nx + r];
+    sha256_16kw(v, k);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) k[r] = kn[r];
+  }
+}
+
 // Compression rounds with k_t + w_t precomputed (kw[0..63]).
 __device__ __forceinline__ void sha256_compress_kw(uint32_t h[8], const uint32_t* kw) {
   uint32_t v[8];
 #pragma unroll
   for (int i = 0; i < 8; ++i) v[i] = h[i];
-#pragma unroll 1
-  for (int it = 0; it < 4; ++it) {
-    uint32_t k[16];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) k[r] = kw[16 * it + r];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      switch (r & 7) {
-        case 0: ZC_SHA_ROUND(v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7], k[r]); break;
-        case 1: ZC_SHA_ROUND(v[7], v[0], v[1], v[2], v[3], v[4], v[5], v[6], k[r]); break;
-        case 2: ZC_SHA_ROUND(v[6], v[7], v[0], v[1], v[2], v[3], v[4], v[5], k[r]); break;
-        case 3: ZC_SHA_ROUND(v[5], v[6], v[7], v[0], v[1], v[2], v[3], v[4], k[r]); break;
-        case 4: ZC_SHA_ROUND(v[4], v[5], v[6], v[7], v[0], v[1], v[2], v[3], k[r]); break;
-        case 5: ZC_SHA_ROUND(v[3], v[4], v[5], v[6], v[7], v[0], v[1], v[2], k[r]); break;
-        case 6: ZC_SHA_ROUND(v[2], v[3], v[4], v[5], v[6], v[7], v[0], v[1], k[r]); break;
-        default: ZC_SHA_ROUND(v[1], v[2], v[3], v[4], v[5], v[6], v[7], v[0], k[r]); break;
-      }
-    }
-  }
+  sha256_rounds_kw(v, kw, 0);
 #pragma unroll
   for (int i = 0; i < 8; ++i) h[i] += v[i];
+}
+
+// Rounds 0..15 of the first block of a message whose words are msg[0..15]
+// (little-endian packed), the round constants as immediates; v holds the
+// chaining value on entry.
+__device__ __forceinline__ void sha256_first16(uint32_t v[8], const uint32_t* msg) {
+  uint32_t k[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) k[r] = kSha256K[r] + sha_bswap(msg[r]);
+  sha256_16kw(v, k);
 }
 
 // Message schedule of block b of a LEN-byte message (LEN a multiple of 4,

@@ -70,7 +70,7 @@ int make_layout(const zc_shape* s, Layout* L) {
   L->eqrows = off;  // LO (2^ml rows) + HI heap (2^mh) + SUF heap (2^(ml+1)), 32 bytes each
   off = align256(off + (((size_t)1 << L->ml) + ((size_t)1 << L->mh) + ((size_t)2 << L->ml)) * 32);
   L->partials = off;
-  off = align256(off + (size_t)kMaxBlocks * kMaxEvals * 32);
+  off = align256(off + (size_t)kMaxBlocks * kPartStrideMax * 32);
   L->specparts = off;  // two buffers of speculative partial sums (kSpecBlocks x kGroup values)
   off = align256(off + 2 * (size_t)kSpecBlocks * 16 * 32);
   L->scratch = off;  // folded copies of the k witness tables, 2^(mu-1) entries each
@@ -234,7 +234,6 @@ int prove_impl(const zc_shape* shape, const uint32_t* const* tables, const uint3
         RoundArgs fa = round_args(shape, L, ws, i - 1, round_evals, challenges);
         fa.nparts = prev_blocks;
         fa.partials = prev_parts;
-        fa.next_spec = 1;
         sa.partials = spec_buf[i & 1];
         sa.src_pitch = sa.dst_pitch = half;
         rc = dispatch_spec(shape, i == sp.s0 ? kSpecFirst : kSpecNext, fa, fold, sa, fold, fold, stream, &blocks);

@@ -16,6 +16,11 @@ constexpr int kMuMax = 30;
 constexpr int kBlock = 256;
 constexpr int kMaxBlocks = 2048;
 
+// Elements between the partial sums of consecutive blocks of a round kernel
+// that stores nv values per block: the power of two >= nv (at most 16).
+constexpr uint32_t part_stride(int nv) { return nv <= 1 ? 1u : nv <= 2 ? 2u : nv <= 4 ? 4u : nv <= 8 ? 8u : 16u; }
+constexpr uint32_t kPartStrideMax = 16;
+
 // Control block at the start of the workspace.
 //
 // eq_r is never materialized: it factors as
@@ -24,20 +29,27 @@ constexpr int kMaxBlocks = 2048;
 // round kernels accumulate H_i(X) = sum_j E_i[j] f(ext_j(X)) and the round's
 // finisher multiplies by coef_i[X] = C_i * eq1(X, r_i).  H_i has degree d, so
 // G_i(d+1) comes from H_i(0..d) through lam_k = (-1)^(d-k) C(d+1, k).
+//
+// coef_{i+1} and C_{i+1} depend on alpha_i only through
+// C_{i+1} = C_i eq1(alpha_i, r_i) = C_i (1 - r_i) + alpha_i C_i (2 r_i - 1), so
+// the finisher of round i leaves, before its hash, the alpha-free parts
+// (nu, nv, npr, nqr below), and the finisher of round i+1 applies alpha_i
+// with one product per value at its start, beside its partial-sum loads:
+//   coef_{i+1}[l] = nu[l] + mont(alpha_i, nv[l]),  C_{i+1} R = npr + mont(alpha_i, nqr)
+// with alpha_i canonical (mont(a, b R) = a b).  Setup leaves the state of
+// round 1 (C_1 = 1, no alpha_0: nv = nqr = 0).
+constexpr int kMaxCoef = 2 * kMaxEvals - 1;  // slots l: x = l < d+2, then lam_{l-d-2} weights
 struct Ctrl {
   uint32_t err;         // first device-detected error (negative status), 0 if none
   uint32_t round_done;  // last round whose challenge has been derived
   uint32_t fold_done;   // last round whose fold has been applied
   uint32_t reserved;
   uint32_t ts[8];                   // transcript digest T_i (little-endian bytes)
-  uint32_t alpha_m[kMuMax][8];      // alpha_i, Montgomery form, < p
-  uint32_t r_m[kMuMax][8];          // r_i, Montgomery form, < p
-  uint32_t r_c[kMuMax][8];          // r_i, canonical
-  uint32_t c_m[8];                  // C_{round_done+1}, Montgomery form
-  uint32_t coef[kMaxEvals][8];      // C_i * eq1(x, r_i), canonical, i = round_done + 1
-  uint32_t coefl[kMaxEvals][8];     // coef[d+1] * lam_k (k <= d), canonical: G(d+1) = sum_k coefl[k] H(k)
-  uint32_t lagr[4][8];              // L_c(alpha_{round_done}), c <= d <= 3, Montgomery: the Lagrange basis of
-                                    // the nodes 0..d, for a next round evaluated speculatively
+  uint32_t alpha[kMuMax][8];        // alpha_i, canonical
+  uint32_t nu[kMaxCoef][8];         // C_i (1 - r_i) e_l, canonical (e_l: slot l of r_{i+1}), i = round_done
+  uint32_t nv[kMaxCoef][8];         // C_i (2 r_i - 1) e_l R
+  uint32_t npr[8];                  // C_i (1 - r_i) R
+  uint32_t nqr[8];                  // C_i (2 r_i - 1) R^2
 };
 
 constexpr uint32_t kCtrlBytes = 4096;

@@ -427,6 +427,79 @@ __device__ __forceinline__ Fe block_reduce(Fe (&v)[NV]) {
   return s;
 }
 
+// ---- the finisher's sum of the round kernel's partial sums -------------------------
+//
+// A round kernel's block b stores its NV values at partials[b * NVP + x]
+// (32-byte elements, NVP = part_stride(NV), the power of two >= NV).  The
+// finisher's thread t takes value x = t mod NVP of blocks t / NVP,
+// t / NVP + 256 / NVP, ..., so consecutive lanes read consecutive elements,
+// each whole (two 16-byte loads), and adds their words into 64-bit
+// accumulators (no carries between words until the end).
+
+template <int NV>
+struct Gather {
+  static constexpr uint32_t NVP = part_stride(NV);
+  static constexpr uint32_t BPS = kBlock / NVP;  // blocks per sweep of the block's threads
+  uint64_t acc[8];
+  // the loads and 64-bit sums of this thread's share
+  __device__ __forceinline__ void load(const uint32_t* __restrict__ partials, uint32_t nparts) {
+    const uint32_t t = threadIdx.x, x = t % NVP;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[k] = 0;
+    if (x >= (uint32_t)NV) return;
+#pragma unroll 4
+    for (uint32_t b = t / NVP; b < nparts; b += BPS) {
+      const uint4* p = reinterpret_cast<const uint4*>(partials + ((uint64_t)b * NVP + x) * 8);
+      const uint4 w0 = p[0], w1 = p[1];
+      acc[0] += w0.x;
+      acc[1] += w0.y;
+      acc[2] += w0.z;
+      acc[3] += w0.w;
+      acc[4] += w1.x;
+      acc[5] += w1.y;
+      acc[6] += w1.z;
+      acc[7] += w1.w;
+    }
+  }
+  // the block total of value x (< p) into out[x], x < NV; ends with a barrier
+  __device__ __forceinline__ void reduce(uint32_t nparts, uint32_t (*out)[NL]) {
+    __shared__ uint32_t red[kBlock / 64][NVP][NL];
+    const uint32_t t = threadIdx.x, x = t % NVP;
+    // the 64-bit word sums -> 9 words -> limbs; the value is below cnt p with
+    // cnt = the most terms any thread added (<= 128)
+    uint32_t w[9];
+    uint64_t c = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const uint64_t sk = acc[k] + c;
+      w[k] = (uint32_t)sk;
+      c = sk >> 32;
+    }
+    w[8] = (uint32_t)c;
+    Fe v = fe_from_words9(w);
+    const uint32_t cnt = (nparts + BPS - 1) / BPS;
+    if (cnt > 64) v = fe_csub(v, kP64);
+    if (cnt > 32) v = fe_csub(v, kP32);
+    if (cnt > 16) v = fe_csub(v, kP16);
+    if (cnt > 8) v = fe_csub(v, kP8);
+    if (cnt > 4) v = fe_csub(v, kP4);
+    if (cnt > 2) v = fe_csub(v, kP2);
+    if (cnt > 1) v = fe_csub(v, kP);
+    // lanes x, x + NVP, ... of the wave, then the block's waves
+#pragma unroll
+    for (uint32_t msk = NVP; msk < 64; msk <<= 1) v = fe_addmod(v, shfl_xor_fe(v, (int)msk));
+    if ((t & 63u) < NVP) lds_put(red[t >> 6][x], v);
+    __syncthreads();
+    if (t < (uint32_t)NV) {
+      Fe s = lds_fe(red[0][t]);
+#pragma unroll
+      for (int wv = 1; wv < kBlock / 64; ++wv) s = fe_addmod(s, lds_fe(red[wv][t]));
+      lds_put(out[t], s);
+    }
+    __syncthreads();
+  }
+};
+
 // ---- end of a round ------------------------------------------------------------
 
 // The scalars of one round; the tables travel beside it (TabPtrs), as kernel
@@ -444,7 +517,6 @@ struct RoundArgs {
   uint32_t tail;               // 1: the finisher also runs rounds round+1..mu and the openings
   uint32_t* openings;          // tail only: (k+1) x 8 canonical
   EqTabs eq;
-  uint32_t next_spec;          // 1: round+1 is evaluated speculatively (the finisher stores L_c(alpha))
 };
 
 // Montgomery product reduced below p.
@@ -476,21 +548,19 @@ __device__ __forceinline__ Fe fe_vgpr(Fe a) {
 // coefl_i[k] = coef_i[d+1] lam_k (k <= d) are canonical, so one Montgomery
 // product with H (Montgomery form) gives G canonical.
 //
-// The coefficients of round i+1 depend on alpha_i only through
-// C_{i+1} = C_i eq1(alpha_i, r_i) = P + alpha_i Q, P = C_i (1 - r_i),
-// Q = C_i (2 r_i - 1).  Everything except the final product with alpha_i is
-// computed by otherwise idle lanes before the SHA-256 compression, so after
-// the hash each coefficient costs one product:
-//   coef_{i+1}[x]  = U_x + mont(alpha_i, V_x),  U_x = P e_x,  V_x = (Q e_x) R,
-//   coefl_{i+1}[k] = Ul_k + mont(alpha_i, Vl_k),
-//   C_{i+1} R      = P R + mont(alpha_i, Q R^2),
-// with e_x = eq1(x, r_{i+1}) and alpha_i canonical (mont(a, bR) = ab).  The
-// factors that depend on r only ((1 - r_i) e_x, (2 r_i - 1) e_x R and the
-// same for e_{d+1} lam_k, (1 - r_i) R, (2 r_i - 1) R^2) are the eq1 rows
-// filled at setup, so each of U, V, P R and Q R^2 is one product with C_i R.
-// A field product is some 160 64-bit multiply-adds, which one wave issues one
-// after another, so the products of one step are spread over the block's
-// waves rather than chained in one.
+// The only work after the hash is alpha_i = T_i mod p and its stores: the
+// finisher of round i takes coef_i and C_i from the state the finisher of
+// round i-1 left (one product each with alpha_{i-1}, beside its own
+// partial-sum loads, see Ctrl), and leaves the state of round i+1 before its
+// own hash:
+//   nu_l = C_i (1 - r_i) e_l,  nv_l = C_i (2 r_i - 1) e_l R,
+//   npr = C_i (1 - r_i) R,     nqr = C_i (2 r_i - 1) R^2,
+// each one product of C_i R with a factor of the eq1 row of round i filled
+// at setup (e_l = eq1(x, r_{i+1}) or its lam-weighted form).  Consumers of
+// alpha_i in Montgomery form (the folds) convert it themselves, beside their
+// first loads.  A field product is some 160 64-bit multiply-adds, which one
+// wave issues one after another (~0.4 us), so the products of one step are
+// spread over the block's waves rather than chained in one.
 
 template <int D>
 struct FinLds {
@@ -499,40 +569,48 @@ struct FinLds {
   static constexpr uint32_t NB = (LEN + 9u + 63u) / 64u;
   uint32_t h[NH][NL];       // H_i(x), Montgomery, < p
   uint32_t cf[NC][NL];      // coef_i[0..d+1], coefl_i[0..d], canonical
-  uint32_t term[NH][NL];    // coefl_i[k] H_i(k)
-  uint32_t u[NC][NL];       // U (canonical) for round i+1
-  uint32_t v[NC][NL];       // V (Montgomery) for round i+1
-  uint32_t pc[NL], q2[NL];  // P R and Q R^2
-  uint32_t cm[NL];          // C_i R; C_{i+1} R after emit_round
-  uint32_t am[NL];          // alpha_i R after emit_round
-  uint32_t ac[8];           // alpha_i canonical words
-  uint32_t lb[NH][NL];      // second factor of L_c(alpha_i) R
-  uint32_t msg[LEN / 4];
-  uint32_t dg[8];           // T_i
+  uint32_t u[NC][NL];       // nu of round i+1 (canonical)
+  uint32_t v[NC][NL];       // nv of round i+1
+  uint32_t pc[NL], q2[NL];  // npr, nqr of round i+1
+  uint32_t cm[NL];          // C_i R
+  uint32_t ac[8];           // alpha_i canonical words, after emit_round
+  uint32_t msg[LEN / 4];    // T_{i-1} || G_i; T_i in words 0..7 after emit_round
   uint32_t kw[NB * 64];
   uint32_t skip;
 };
 
-// Block state of round `round` from the control block: coefficients, C_i,
-// T_{i-1}.  All threads call it; ends with a barrier.
+// coef_i and C_i R of round `round` from the state in the control block and
+// alpha_{round-1} (none for round 1: the state of round 1 has nv = nqr = 0):
+// lanes l < NC write S.cf[l], lane NC writes S.cm, lanes 64..71 copy
+// T_{round-1} into S.msg.  No barrier.
 template <int D>
-__device__ __forceinline__ void fin_load(const Ctrl* ctrl, FinLds<D>& S) {
-  constexpr int NE = D + 2, NC = FinLds<D>::NC;
+__device__ __forceinline__ void fin_start(const Ctrl* ctrl, uint32_t round, FinLds<D>& S) {
+  constexpr int NC = FinLds<D>::NC;
   const uint32_t t = threadIdx.x;
-  if (t < (uint32_t)NC) lds_put(S.cf[t], load_words_fe(t < (uint32_t)NE ? ctrl->coef[t] : ctrl->coefl[t - NE]));
-  if (t == (uint32_t)NC) lds_put(S.cm, load_words_fe(ctrl->c_m));
+  if (t <= (uint32_t)NC) {
+    const Fe ac = round > 1 ? fe_vgpr(load_words_fe(ctrl->alpha[round - 2])) : fe_zero();
+    if (t < (uint32_t)NC)
+      lds_put(S.cf[t], fe_addmod(load_words_fe(ctrl->nu[t]), mont(ac, load_words_fe(ctrl->nv[t]))));
+    else
+      lds_put(S.cm, fe_addmod(fe_vgpr(load_words_fe(ctrl->npr)), mont(ac, fe_vgpr(load_words_fe(ctrl->nqr)))));
+  }
   if (t >= 64 && t < 72) S.msg[t - 64] = ctrl->ts[t - 64];
 }
 
-// Emits G_round, derives alpha_round, and prepares the next round (see
-// above).  On entry S.h, S.cf, S.cm and S.msg[0..7] hold round `round`'s
-// state; on exit S.cf, S.cm hold round+1's (S.cm = C_{mu+1} R after the last
-// round, the opening of eq), S.am holds alpha_round R and S.msg[0..7] T_round.
-// The control block is updated the same way; its stores come after the last
-// barrier, so no barrier waits for them.  All threads of the block call it.
+// Emits G_round, leaves the state of round+1 (S.u, S.v, S.pc, S.q2 and the
+// control block) and derives alpha_round.  On entry S.h, S.cf, S.cm and
+// S.msg[0..7] hold round `round`'s values; on exit S.ac holds alpha_round
+// (canonical) and S.msg[0..7] T_round.  Ends with a barrier.  All threads of
+// the block call it.
+//
+// The hash: lanes 64 + b expand the schedule of every block b (k_t + w_t,
+// the constants as immediates) into LDS while lane 0 runs rounds 0..15 of
+// block 0 straight from the message; after a barrier lane 0 runs the rest
+// from LDS.  Meanwhile lanes 128 on form the state of round+1, whose factors
+// they load from the eq1 rows then (the hash hides that latency).
 template <int D>
-__device__ __forceinline__ void emit_round(Ctrl* ctrl, uint32_t round, uint32_t mu, FinLds<D>& S,
-                                           uint32_t* evals_out, uint32_t* alpha_out, bool lagr = false) {
+__device__ __forceinline__ void emit_round(Ctrl* ctrl, uint32_t round, FinLds<D>& S, uint32_t* evals_out,
+                                           uint32_t* alpha_out) {
   constexpr int NH = D + 1, NE = D + 2, NC = FinLds<D>::NC;
   constexpr uint32_t LEN = FinLds<D>::LEN, NB = FinLds<D>::NB;
   static_assert(NH <= 16, "one 16-lane group");
@@ -566,38 +644,34 @@ __device__ __forceinline__ void emit_round(Ctrl* ctrl, uint32_t round, uint32_t 
         evals_out[NH * 8 + k] = w[k];
       }
     }
+  }
+  __syncthreads();
+  static_assert(LEN >= 64 && NB <= 64, "block 0 is all message; one wave expands every block");
+  uint32_t hv[8], v[8];
+  if (t == 0) {
+    sha256_init(hv);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = hv[i];
+    sha256_first16(v, S.msg);
+  } else if (t >= 64 && t < 64 + NB) {
+    sha256_expand_block<LEN>(S.msg, S.kw, t - 64);
   } else if (t >= 128 && t < 128 + 2 * ((uint32_t)NC + 1)) {
-    // lanes 128 on (wave 2, and wave 3 past 64 lanes): the next round's
-    // precomputation, one product with C_i R per lane (the eq1 row holds the
-    // other factor), while G is formed, so that the hash runs alone.  Lanes
-    // 128 + l (l < NC): U_l, lane 128 + NC: P R; lanes 128 + NC + 1 + l: V_l,
-    // lane 128 + 2 NC + 1: Q R^2.
+    // the state of round+1, one product with C_i R per lane (the eq1 row
+    // holds the other factor): lanes 128 + l (l < NC): nu_l, lane 128 + NC:
+    // npr, lanes 128 + NC + 1 + l: nv_l, lane 128 + 2 NC + 1: nqr
     const uint32_t k = t - 128, l = k % ((uint32_t)NC + 1);
     const bool qv = k > (uint32_t)NC;
     const Eq1Row* row = eq1_rows(ctrl) + (round - 1);
     const uint32_t* f = l == (uint32_t)NC ? (qv ? row->tr2 : row->omr) : (qv ? row->v[l] : row->u[l]);
-    if (l == (uint32_t)NC || round < mu) {
-      const Fe y = mont(fe_vgpr(lds_fe(S.cm)), load_words_fe(f));
-      lds_put(l == (uint32_t)NC ? (qv ? S.q2 : S.pc) : (qv ? S.v[l] : S.u[l]), y);
-    }
+    const Fe y = mont(fe_vgpr(lds_fe(S.cm)), load_words_fe(f));
+    lds_put(l == (uint32_t)NC ? (qv ? S.q2 : S.pc) : (qv ? S.v[l] : S.u[l]), y);
+    store_words_fe(l == (uint32_t)NC ? (qv ? ctrl->nqr : ctrl->npr) : (qv ? ctrl->nv[l] : ctrl->nu[l]), y);
   }
   __syncthreads();
-  // T_round = SHA-256(msg): lane 0 compresses block 0 with its schedule formed
-  // on the fly while lanes 64 + b - 1 expand blocks b >= 1 (which takes less
-  // time), then compresses those from their schedules
-  static_assert(LEN >= 64 && NB - 1 <= 64, "block 0 is all message; one wave expands the rest");
-  uint32_t hv[8];
   if (t == 0) {
-    sha256_init(hv);
-    uint32_t W[16];
+    sha256_rounds_kw(v, S.kw, 1);
 #pragma unroll
-    for (int k = 0; k < 16; ++k) W[k] = sha_vreg(sha_bswap(S.msg[k]));
-    sha256_compress(hv, W);
-  } else if (t >= 64 && t < 64 + NB - 1) {
-    sha256_expand_block<LEN>(S.msg, S.kw, t - 63);
-  }
-  __syncthreads();
-  if (t == 0) {
+    for (int i = 0; i < 8; ++i) hv[i] += v[i];
 #pragma unroll 1
     for (uint32_t b = 1; b < NB; ++b) sha256_compress_kw(hv, S.kw + b * 64u);
     uint32_t dg[8];
@@ -609,83 +683,15 @@ __device__ __forceinline__ void emit_round(Ctrl* ctrl, uint32_t round, uint32_t 
     fe_to_words(al, w);
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      S.dg[k] = dg[k];
+      S.msg[k] = dg[k];
       S.ac[k] = w[k];
+      ctrl->ts[k] = dg[k];
+      ctrl->alpha[round - 1][k] = w[k];
+      alpha_out[k] = w[k];
     }
+    ctrl->round_done = round;
   }
   __syncthreads();
-  // one product per value with alpha (canonical): coefficients and C of the
-  // next round, alpha R; then T_round heads the next message
-  Fe out = fe_zero();
-  if (t < (uint32_t)NC + 2) {
-    uint32_t w[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) w[k] = S.ac[k];
-    const Fe ac = fe_vgpr(fe_from_words(w));
-    if (t < (uint32_t)NC) {
-      if (round < mu) {
-        out = fe_addmod(lds_fe(S.u[t]), mont(ac, lds_fe(S.v[t])));
-        lds_put(S.cf[t], out);
-      }
-    } else if (t == (uint32_t)NC) {
-      out = fe_addmod(lds_fe(S.pc), mont(ac, lds_fe(S.q2)));
-      lds_put(S.cm, out);
-    } else {
-      out = fe_to_mont(ac);
-      lds_put(S.am, out);
-    }
-  }
-  if constexpr (D <= 3) {
-    // with lagr, L_c(alpha) R = w_c prod_{k != c} (alpha - k) R for the
-    // speculative next round's finisher, from the d factors (alpha - k)
-    // canonical, multiplied pairwise onto w_c R^(d+1): lane 128 + c forms
-    // (w_c R^(d+1)) x, lane 192 + c the rest (y z, or y when d = 2), and lane
-    // 128 + c their product after the barrier below
-    if (lagr && ((t >= 128 && t < 128 + (uint32_t)NH) || (t >= 192 && t < 192 + (uint32_t)NH))) {
-      static_assert(D == 2 || D == 3, "two or three factors");
-      constexpr LagrangeW<D> W{};
-      const uint32_t c = t & 63u;
-      uint32_t w[8];
-#pragma unroll
-      for (int k = 0; k < 8; ++k) w[k] = S.ac[k];
-      const Fe ac = fe_vgpr(fe_from_words(w));
-      Fe tk[NH];  // alpha - k, canonical
-      Fe ws = fe_zero();
-      auto terms = [&](auto k) __attribute__((always_inline)) {
-        Fe kk = fe_zero();
-        kk.l[0] = (uint32_t)k;
-        tk[k] = fe_submod(ac, kk);
-        if (c == (uint32_t)k) ws = fe_const(W.wsh[k]);
-      };
-      Unroll<0, NH>::run(terms);
-      // the factors k != c in order: x, y (, z)
-      if (t < 192) {
-        out = mont(ws, fe_sel(c == 0, tk[1], tk[0]));
-      } else {
-        const Fe y = fe_sel(c <= 1, tk[2], tk[1]);
-        if constexpr (D == 3)
-          lds_put(S.lb[c], mont(y, fe_sel(c <= 2, tk[3], tk[2])));
-        else
-          lds_put(S.lb[c], y);
-      }
-    }
-  }
-  if (t >= 64 && t < 72) S.msg[t - 64] = S.dg[t - 64];
-  __syncthreads();
-  // control block and outputs
-  if (t < (uint32_t)NC) {
-    if (round < mu) store_words_fe(t < (uint32_t)NE ? ctrl->coef[t] : ctrl->coefl[t - NE], out);
-  } else if (t == (uint32_t)NC) {
-    store_words_fe(ctrl->c_m, out);
-  } else if (t == (uint32_t)NC + 1) {
-    store_words_fe(ctrl->alpha_m[round - 1], out);
-  } else if (t >= 64 && t < 72) {
-    ctrl->ts[t - 64] = S.dg[t - 64];
-    alpha_out[t - 64] = S.ac[t - 64];
-    if (t == 64) ctrl->round_done = round;
-  } else if (D <= 3 && lagr && t >= 128 && t < 128 + (uint32_t)NH) {
-    store_words_fe(ctrl->lagr[t - 128], mont(out, lds_fe(S.lb[t - 128])));
-  }
 }
 
 // ---- round kernel, one thread per pair ---------------------------------------------
@@ -718,7 +724,7 @@ __device__ __forceinline__ void round_body(const RoundArgs& a, const TabPtrs& sr
 
   {
     Fe alpha;
-    if (FOLD) alpha = load_words_fe(a.ctrl->alpha_m[a.round - 2]);
+    if (FOLD) alpha = fe_to_mont(fe_vgpr(load_words_fe(a.ctrl->alpha[a.round - 2])));
     const uint32_t q = (uint32_t)a.q;
     const uint32_t stride = nblk * blockDim.x;
     // chunks of kLazyPairs pairs per thread, the sums lowered after each
@@ -755,7 +761,7 @@ __device__ __forceinline__ void round_body(const RoundArgs& a, const TabPtrs& sr
   auto red = [&](auto x) __attribute__((always_inline)) { acc[x] = fe_reduce2(acc[x]); };  // < 2p after lower
   Unroll<0, NH>::run(red);
   const Fe tot = block_reduce<NH>(acc);
-  if (threadIdx.x < NH) store_words_fe(a.partials + ((uint64_t)blk * NH + threadIdx.x) * 8, tot);
+  if (threadIdx.x < NH) store_words_fe(a.partials + ((uint64_t)blk * part_stride(NH) + threadIdx.x) * 8, tot);
 }
 
 template <class Gate, bool FOLD>
@@ -808,11 +814,12 @@ __device__ __forceinline__ Fe group_reduce(Fe c) {
 }
 
 // The last rounds of a proof inside one block, with the tables in LDS.  On
-// entry round a.round has been emitted (S holds round a.round+1's state and
-// alpha_{a.round}) and the tables at dst hold 2q live entries,
+// entry round a.round has been emitted (S holds alpha_{a.round} and the state
+// of round a.round+1) and the tables at dst hold 2q live entries,
 // q = a.q <= 2 kTailQ.  Runs rounds a.round+1 .. mu (fold with the previous
 // challenge, evaluate, emit) and the final fold, whose values are the
-// openings; eq's opening is C_{mu+1}.
+// openings; eq's opening is C_{mu+1}.  The coefficients of each round are
+// formed beside its fold.
 //
 // Evaluation: point x of pair j is one thread's work (SL point slots, the
 // power of two >= d+1, times PP = kBlock / SL pairs per pass); the PP lanes
@@ -824,6 +831,7 @@ template <class Gate>
 __device__ __forceinline__ void run_tail(const RoundArgs& a, const TabPtrs& dst, FinLds<Gate::D>& S, bool prefold) {
   constexpr int K = Gate::K;
   constexpr int NH = Gate::NH;
+  constexpr int NC = FinLds<Gate::D>::NC;
   constexpr uint32_t SL = NH <= 4 ? 4u : (NH <= 8 ? 8u : 16u);
   constexpr uint32_t PP = kBlock / SL;
   static_assert(PP <= 64 && SL * PP == kBlock, "point groups within a wave");
@@ -831,30 +839,41 @@ __device__ __forceinline__ void run_tail(const RoundArgs& a, const TabPtrs& dst,
   constexpr uint32_t CAP = 4 * kTailQ;
   auto T = [&](int t, uint32_t e) -> uint32_t* { return tail_lds + ((uint32_t)t * CAP + e) * NL; };
   uint32_t* eqrow = tail_lds + (uint32_t)K * CAP * NL;
+  const uint32_t tid = threadIdx.x;
   uint32_t L = 2 * (uint32_t)a.q;
-  const Fe pa = prefold ? fe_vgpr(load_words_fe(a.ctrl->alpha_m[a.round - 2])) : fe_zero();
-  for (uint32_t idx = threadIdx.x; idx < K * L; idx += blockDim.x) {
+  const Fe pa = prefold ? fe_to_mont(fe_vgpr(load_words_fe(a.ctrl->alpha[a.round - 2]))) : fe_zero();
+  for (uint32_t idx = tid; idx < K * L; idx += blockDim.x) {
     const uint32_t t = idx / L, e = idx % L;
     Fe v = load_el(dst.p[t], a.dst_pitch, e);
     if (prefold) v = fe_lerp(v, load_el(dst.p[t], a.dst_pitch, e + L), pa);
     lds_put(T(t, e), v);
   }
   // E_r[j] of every tail round r, heap-style: row 2^(mu-r) + j, rows [1, q)
-  for (uint32_t hrow = threadIdx.x; hrow < (uint32_t)a.q; hrow += blockDim.x) {
+  for (uint32_t hrow = tid; hrow < (uint32_t)a.q; hrow += blockDim.x) {
     if (hrow == 0) continue;
     const uint32_t lg = 31u - __builtin_clz(hrow);
     lds_put(eqrow + hrow * NL, eq_factor(a.eq, a.mu - lg, hrow - (1u << lg)));
   }
   __syncthreads();
-  const uint32_t x = threadIdx.x / PP, pp = threadIdx.x % PP;
+  const uint32_t x = tid / PP, pp = tid % PP;
   for (uint32_t r = a.round + 1; r <= a.mu + 1; ++r) {
-    // fold with alpha_{r-1}: L -> L/2 entries
-    const Fe alpha = fe_vgpr(lds_fe(S.am));
+    // fold with alpha_{r-1}: L -> L/2 entries; beside it coef_r and C_r R
+    // from alpha_{r-1} and the state emit_round left
+    uint32_t w[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) w[k] = S.ac[k];
+    const Fe ac = fe_vgpr(fe_from_words(w));
+    const Fe alpha = fe_to_mont(ac);
     const uint32_t h = L / 2;
-    for (uint32_t idx = threadIdx.x; idx < K * h; idx += blockDim.x) {
+    for (uint32_t idx = tid; idx < K * h; idx += blockDim.x) {
       const uint32_t t = idx / h, e = idx % h;
       const Fe u0 = lds_fe(T(t, e)), u1 = lds_fe(T(t, e + h));
       lds_put(T(t, e), fe_lerp(u0, u1, alpha));
+    }
+    if (tid < (uint32_t)NC) {
+      if (r <= a.mu) lds_put(S.cf[tid], fe_addmod(lds_fe(S.u[tid]), mont(ac, lds_fe(S.v[tid]))));
+    } else if (tid == (uint32_t)NC) {
+      lds_put(S.cm, fe_addmod(fe_vgpr(lds_fe(S.pc)), mont(ac, fe_vgpr(lds_fe(S.q2)))));
     }
     __syncthreads();
     L = h;
@@ -877,15 +896,17 @@ __device__ __forceinline__ void run_tail(const RoundArgs& a, const TabPtrs& dst,
         if (e0 + pp < q) c = v;
       }
     }
+    // lanes pp >= q hold 0, so the sum of lanes 0..q-1 needs the levels below q only
 #pragma unroll
-    for (uint32_t msk = PP / 2; msk >= 1; msk >>= 1) c = fe_addmod(c, shfl_xor_fe(c, (int)msk));
+    for (uint32_t msk = PP / 2; msk >= 1; msk >>= 1)
+      if (msk < q) c = fe_addmod(c, shfl_xor_fe(c, (int)msk));
     if (pp == 0 && x < (uint32_t)NH) lds_put(S.h[x], c);
     __syncthreads();
-    emit_round<Gate::D>(a.ctrl, r, a.mu, S, a.evals_out + (uint64_t)(r - a.round) * Gate::NE * 8,
+    emit_round<Gate::D>(a.ctrl, r, S, a.evals_out + (uint64_t)(r - a.round) * Gate::NE * 8,
                         a.alpha_out + (uint64_t)(r - a.round) * 8);
   }
-  if (threadIdx.x < K) store_words_fe(a.openings + threadIdx.x * 8, fe_from_mont(lds_fe(T(threadIdx.x, 0))));
-  if (threadIdx.x == K) store_words_fe(a.openings + K * 8, fe_from_mont(fe_vgpr(lds_fe(S.cm))));
+  if (tid < K) store_words_fe(a.openings + tid * 8, fe_from_mont(lds_fe(T(tid, 0))));
+  if (tid == K) store_words_fe(a.openings + K * 8, fe_from_mont(fe_vgpr(lds_fe(S.cm))));
 }
 
 // Round with 16 lanes per pair; the grid strides over the pairs and is sized
@@ -918,7 +939,7 @@ __global__ __launch_bounds__(kBlock) void k_round_split(RoundArgs a, TabPtrs src
         Unroll<1, K>::run(sel);
         Fe u0, u1;
         if (FOLD) {
-          const Fe alpha = load_words_fe(a.ctrl->alpha_m[a.round - 2]);
+          const Fe alpha = fe_to_mont(fe_vgpr(load_words_fe(a.ctrl->alpha[a.round - 2])));
           const uint64_t sp = a.src_pitch;
           const Fe a0 = load_el(src, sp, j), a2 = load_el(src, sp, j + 2 * q);
           const Fe a1 = load_el(src, sp, j + q), a3 = load_el(src, sp, j + 3 * q);
@@ -946,7 +967,8 @@ __global__ __launch_bounds__(kBlock) void k_round_split(RoundArgs a, TabPtrs src
     }
   }
   const Fe tot = group_reduce<NH>(c);
-  if (threadIdx.x < NH) store_words_fe(a.partials + ((uint64_t)blockIdx.x * NH + threadIdx.x) * 8, tot);
+  if (threadIdx.x < NH)
+    store_words_fe(a.partials + ((uint64_t)blockIdx.x * part_stride(NH) + threadIdx.x) * 8, tot);
 }
 
 // ---- speculative rounds (gates of degree <= 3) -----------------------------------------
@@ -1006,7 +1028,7 @@ __device__ __forceinline__ void spec_body(const RoundArgs& a, const TabPtrs& src
 #pragma unroll
         for (uint32_t k = 0; k < 4; ++k) A[k] = load_el(src, sp, j + k * q);
       } else {
-        const Fe alpha = load_words_fe(a.ctrl->alpha_m[a.round - 3]);  // alpha_{r-2}
+        const Fe alpha = fe_to_mont(fe_vgpr(load_words_fe(a.ctrl->alpha[a.round - 3])));  // alpha_{r-2}
 #pragma unroll
         for (uint32_t k = 0; k < 4; ++k) {
           A[k] = fe_lerp(load_el(src, sp, j + k * q), load_el(src, sp, j + k * q + 4 * q), alpha);
@@ -1038,7 +1060,7 @@ __device__ __forceinline__ void spec_body(const RoundArgs& a, const TabPtrs& src
     __syncthreads();
   }
   const Fe tot = group_reduce<NS>(acc);
-  if (threadIdx.x < (uint32_t)NS) store_words_fe(a.partials + ((uint64_t)blk * NS + threadIdx.x) * 8, tot);
+  if (threadIdx.x < (uint32_t)NS) store_words_fe(a.partials + ((uint64_t)blk * part_stride(NS) + threadIdx.x) * 8, tot);
 }
 
 // ---- end of a round: one block -------------------------------------------------------
@@ -1053,45 +1075,76 @@ __device__ __forceinline__ void spec_body(const RoundArgs& a, const TabPtrs& src
 // SPEC: the partials are spec_body's (d+1)^2 sums per block, H_i(X) for
 // alpha_{i-1} = c; the finisher interpolates them at alpha_{i-1}:
 // H_i(X) = sum_c L_c(alpha_{i-1}) H_i(X; c), L_c the Lagrange basis of the
-// nodes 0..d.  A tail then starts from T_{i-1} (prefold).
+// nodes 0..d, formed beside the partial-sum loads.  A tail then starts from
+// T_{i-1} (prefold).
 template <class Gate, bool SPEC = false>
 __device__ __forceinline__ void finish_body(const RoundArgs& a, const TabPtrs& dst) {
   constexpr int NH = Gate::NH;
+  constexpr int NC = FinLds<Gate::D>::NC;
   constexpr int NV = SPEC ? NH * NH : NH;  // partial sums per block
   __shared__ FinLds<Gate::D> S;
   __shared__ uint32_t hs[SPEC ? NV : 1][NL];  // SPEC: H_i(X; c), slot c NH + X
-  __shared__ uint32_t lc[SPEC ? NH : 1][NL];  // SPEC: L_c(alpha_{i-1})
+  __shared__ uint32_t lc[SPEC ? NH : 1][NL];  // SPEC: L_c(alpha_{i-1}) R (its first factor until the barrier)
+  __shared__ uint32_t lb[SPEC ? NH : 1][NL];  // SPEC: the second factor of L_c(alpha_{i-1}) R
   const uint32_t t = threadIdx.x;
+  // every global load first, so that their latencies overlap: the
+  // control-block values of lanes <= NC (coef_i, C_i), alpha_{i-1} for the
+  // Lagrange lanes, T_{i-1}, then the partial sums
+  const bool coef_lane = t <= (uint32_t)NC;
+  const bool lag_lane = SPEC && ((t >= 128 && t < 128 + (uint32_t)NH) || (t >= 192 && t < 192 + (uint32_t)NH));
+  Fe ca = fe_zero(), cu = fe_zero(), cv = fe_zero();
+  if ((coef_lane || lag_lane) && a.round > 1) ca = fe_vgpr(load_words_fe(a.ctrl->alpha[a.round - 2]));
+  if (coef_lane) {
+    cu = fe_vgpr(load_words_fe(t < (uint32_t)NC ? a.ctrl->nu[t] : a.ctrl->npr));
+    cv = fe_vgpr(load_words_fe(t < (uint32_t)NC ? a.ctrl->nv[t] : a.ctrl->nqr));
+  }
+  uint32_t tsw = 0;
+  if (t >= 64 && t < 72) tsw = a.ctrl->ts[t - 64];
   if (t == 0) {
     const bool ok = a.ctrl->round_done + 1 == a.round;
     S.skip = ok ? 0u : 1u;
     if (!ok) set_error(a.ctrl, -5);
   }
-  fin_load<Gate::D>(a.ctrl, S);
-  // SPEC: L_c(alpha_{i-1}), stored by the finisher of round i-1
+  Gather<NV> gat;
+  gat.load(a.partials, a.nparts);
+  // coef_i[l] = nu_l + alpha_{i-1} nv_l (lanes l < NC), C_i R (lane NC), see Ctrl
+  if (coef_lane) lds_put(t < (uint32_t)NC ? S.cf[t] : S.cm, fe_addmod(cu, mont(ca, cv)));
+  if (t >= 64 && t < 72) S.msg[t - 64] = tsw;
   if constexpr (SPEC) {
-    if (t >= 192 && t < 192 + (uint32_t)NH) lds_put(lc[t - 192], load_words_fe(a.ctrl->lagr[t - 192]));
+    // L_c(alpha) R = w_c prod_{k != c} (alpha - k) R, from the d factors
+    // (alpha - k) canonical multiplied pairwise onto w_c R^(d+1): lane 128 + c
+    // forms (w_c R^(d+1)) x, lane 192 + c the rest (y z, or y when d = 2),
+    // lane 128 + c their product after the barrier below
+    static_assert(Gate::D == 2 || Gate::D == 3, "two or three factors");
+    if (lag_lane) {
+      constexpr LagrangeW<Gate::D> W{};
+      const uint32_t c = t & 63u;
+      Fe tk[NH];  // alpha - k, canonical
+      Fe ws = fe_zero();
+      auto terms = [&](auto k) __attribute__((always_inline)) {
+        Fe kk = fe_zero();
+        kk.l[0] = (uint32_t)k;
+        tk[k] = fe_submod(ca, kk);
+        if (c == (uint32_t)k) ws = fe_const(W.wsh[k]);
+      };
+      Unroll<0, NH>::run(terms);
+      // the factors k != c in order: x, y (, z)
+      if (t < 192) {
+        lds_put(lc[c], mont(ws, fe_sel(c == 0, tk[1], tk[0])));
+      } else {
+        const Fe y = fe_sel(c <= 1, tk[2], tk[1]);
+        if constexpr (Gate::D == 3)
+          lds_put(lb[c], mont(y, fe_sel(c <= 2, tk[3], tk[2])));
+        else
+          lds_put(lb[c], y);
+      }
+    }
   }
-  // point x = t / LP: its LP lanes (the whole block shared by the points,
-  // rounded to powers of two) stride over the partials (each < p), lazily
-  // summed (at most kMaxBlocks / LP <= 128 terms, < 128 p), reduced, then
-  // combined across the group by shuffles
-  constexpr uint32_t NHP = NV <= 4 ? 4u : (NV <= 8 ? 8u : 16u);
-  constexpr uint32_t LP = kBlock / NHP;
-  static_assert(NV <= 16 && NHP * LP == kBlock && LP <= 64 && kMaxBlocks / LP <= 128, "lanes per point");
-  const uint32_t x = t / LP, g = t % LP;
-  Fe v = fe_zero();
-  if (x < (uint32_t)NV) {
-#pragma unroll 8
-    for (uint32_t b = g; b < a.nparts; b += LP) v = fe_add(v, load_words_fe(a.partials + ((uint64_t)b * NV + x) * 8));
-    v = fe_reduce128(v);
-  }
-#pragma unroll
-  for (uint32_t msk = LP / 2; msk >= 1; msk >>= 1) v = fe_add(v, shfl_xor_fe(v, (int)msk));  // < LP p <= 64 p
-  if (x < (uint32_t)NV && g == 0) lds_put(SPEC ? hs[x] : S.h[x], fe_reduce128(v));
-  __syncthreads();
+  gat.reduce(a.nparts, SPEC ? hs : S.h);
   if (S.skip) return;
   if constexpr (SPEC) {
+    if (t >= 128 && t < 128 + (uint32_t)NH) lds_put(lc[t - 128], mont(lds_fe(lc[t - 128]), lds_fe(lb[t - 128])));
+    __syncthreads();
     // H_i(X) = sum_c L_c H_i(X; c): lane c NP + X of wave 0 forms one product
     // (NP = NH rounded up to a power of two), and shuffles across the lanes NP
     // apart sum over c (every term < p, so the sum is the same in any order)
@@ -1107,7 +1160,7 @@ __device__ __forceinline__ void finish_body(const RoundArgs& a, const TabPtrs& d
     }
     __syncthreads();
   }
-  emit_round<Gate::D>(a.ctrl, a.round, a.mu, S, a.evals_out, a.alpha_out, a.next_spec != 0);
+  emit_round<Gate::D>(a.ctrl, a.round, S, a.evals_out, a.alpha_out);
   if (a.tail) run_tail<Gate>(a, dst, S, SPEC);
 }
 
@@ -1205,7 +1258,6 @@ __device__ __forceinline__ RoundArgs batch_round_args(const InstDesc& d, uint32_
   a.tail = round == d.last ? 1u : 0u;
   a.openings = d.openings;
   a.eq = d.eq;
-  a.next_spec = 0;
   return a;
 }
 

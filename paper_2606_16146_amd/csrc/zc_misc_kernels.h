@@ -24,33 +24,29 @@ __device__ __forceinline__ Fe lam_mont(uint32_t d, uint32_t k) {
   return v;
 }
 
-// One block: resets the control block, checks r, keeps it in canonical and
-// Montgomery form, sets C_1 = 1, fills the eq1 rows of every round and sets
-// coef_1[x] = eq1(x, r_1) for x < ne and coefl_1.  (T_0 is hashed by
-// t0_body, in another block of the same launch.)
+// One block: resets the control block, checks r, fills the eq1 rows of
+// every round and leaves the state of round 1: C_1 = 1 and no alpha_0, i.e.
+// nu[l] = eq1(x, r_1) (slot l), nv = 0, npr = R, nqr = 0.  (T_0 is hashed
+// by t0_body, in another block of the same launch.)
 __device__ __forceinline__ void setup_body(const uint32_t* __restrict__ r, uint32_t mu, uint32_t ne, Ctrl* ctrl) {
   if (threadIdx.x == 0) {
     ctrl->err = 0;
     ctrl->round_done = 0;
     ctrl->fold_done = 0;
-    store_words_fe(ctrl->c_m, fe_const(kOne));
+    store_words_fe(ctrl->npr, fe_const(kOne));
+    store_words_fe(ctrl->nqr, fe_zero());
   }
   __syncthreads();  // the reset above must precede any error flagged below
   for (uint32_t i = threadIdx.x; i < mu; i += blockDim.x) {
     uint32_t w[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      w[k] = r[i * 8 + k];
-      ctrl->r_c[i][k] = w[k];
-    }
+    for (int k = 0; k < 8; ++k) w[k] = r[i * 8 + k];
     if (!words_lt_p(w)) set_error(ctrl, -4);
-    store_words_fe(ctrl->r_m[i], fe_to_mont(fe_from_words(w)));
   }
   // eq1 rows (see Eq1Row).  The slot-l factor of a challenge r (l < nc) is
   // eq1(x, r) = (1 - r) + x (2 r - 1), x = l < ne, else x = d+1 times
   // lam_{l-ne}.  Row i takes 1 - r and 2 r - 1 from r_{i+1} and the slot
-  // factors from r_{i+2}; the slot factors of r_1 are coef_1 and coefl_1
-  // (C_1 = 1).
+  // factors from r_{i+2}; the slot factors of r_1 are coef_1 (C_1 = 1).
   const uint32_t nc = 2 * ne - 1, d = ne - 2, ns = nc + 2;
   Eq1Row* rows = eq1_rows(ctrl);
   auto rval = [&](uint32_t i) {  // r_{i+1}, canonical (a value >= p, flagged above, as 0)
@@ -81,7 +77,10 @@ __device__ __forceinline__ void setup_body(const uint32_t* __restrict__ r, uint3
       }
       store_words_fe(rows[i].u[l], u);
       store_words_fe(rows[i].v[l], v);
-      if (i == 0) store_words_fe(l < ne ? ctrl->coef[l] : ctrl->coefl[l - ne], slot(rc, l));
+      if (i == 0) {
+        store_words_fe(ctrl->nu[l], slot(rc, l));
+        store_words_fe(ctrl->nv[l], fe_zero());
+      }
     } else if (l == nc) {
       store_words_fe(rows[i].omr, omr_m);
     } else {
@@ -167,7 +166,7 @@ __global__ __launch_bounds__(kBlock) void k_fold(TabPtrs tabs, uint32_t ntab, ui
   if (ctrl->round_done != round || ctrl->fold_done + 1 != round) return;
   const uint32_t t = blockIdx.y;
   if (t >= ntab) return;
-  const Fe alpha = load_words_fe(ctrl->alpha_m[round - 1]);
+  const Fe alpha = fe_to_mont(load_words_fe(ctrl->alpha[round - 1]));
   uint32_t* base = tabs.p[t];
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < h; j += stride) {
