@@ -165,6 +165,11 @@ typedef struct {
   uint32_t* challenges;
   uint32_t* openings;
   uint32_t tile;
+  /* elements between the limb planes of each table (0 means 2^mu, the layout
+     zc_pack makes).  A larger pitch lets an instance read a 2^mu-element
+     window of a larger packed table in place: tables[t] then points at the
+     window's first element of plane 0 (pitch <= 2^30). */
+  uint64_t pitch;
 } zc_instance;
 
 /* Bytes of device batch workspace (instance descriptors and launch

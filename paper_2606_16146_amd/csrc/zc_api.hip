@@ -320,6 +320,7 @@ int check_instance(const zc_instance& in, Layout* L) {
   if ((rc = check_tables(*L, in.tables)) != ZC_OK) return rc;
   if (!in.r || !in.ws || !in.round_evals || !in.challenges || !in.openings || !aligned(in.ws, 256))
     return ZC_EINVAL;
+  if (in.pitch != 0 && (in.pitch < (1ull << in.shape.mu) || in.pitch > kMaxElems)) return ZC_EINVAL;
   return ZC_OK;
 }
 
@@ -392,6 +393,7 @@ InstDesc make_desc(const zc_instance& in, const Layout& L, uint32_t last) {
   d.m = in.shape.m;
   d.ne = L.d + 2;
   d.last = last;
+  d.pitch = in.pitch ? in.pitch : n;
   return d;
 }
 

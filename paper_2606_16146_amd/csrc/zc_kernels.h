@@ -1209,7 +1209,8 @@ struct InstDesc {
   const uint32_t* r;
   uint32_t mu, gate, m, ne;
   uint32_t last;       // last round with a round kernel; its finisher runs the tail
-  uint32_t pad[3];
+  uint32_t pad;
+  uint64_t pitch;      // plane pitch of the caller tables (elements, >= 2^mu)
 };
 
 // One gate's share of a step: instances inst[0..count) (indices into descs)
@@ -1245,8 +1246,8 @@ static_assert(sizeof(ServeStep) <= 4096 - 64, "kernel argument size");
 __device__ __forceinline__ RoundArgs batch_round_args(const InstDesc& d, uint32_t round, uint32_t nparts) {
   RoundArgs a;
   const uint64_t n = 1ull << d.mu;
-  a.src_pitch = round <= 2 ? n : n / 2;
-  a.dst_pitch = round == 1 ? n : n / 2;
+  a.src_pitch = round <= 2 ? d.pitch : n / 2;
+  a.dst_pitch = round == 1 ? d.pitch : n / 2;
   a.q = 1ull << (d.mu - round);
   a.round = round;
   a.mu = d.mu;

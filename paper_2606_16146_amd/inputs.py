@@ -290,3 +290,10 @@ def serve_arrivals(seed: int, n: int, rate: float, run: int = 0) -> np.ndarray:
     """Poisson arrival times (seconds) of n requests at `rate` per second."""
     rng = _stream(seed, 1 + run, SERVE_TABLE_ID)
     return np.cumsum(rng.exponential(1.0 / rate, size=n)) - 0.0
+
+
+def serve_windows(seed: int, specs, top: int) -> list[int]:
+    """Window index w_i of each request of a served stream: request i (size mu)
+    reads rows [w_i 2^mu, (w_i + 1) 2^mu) of a 2^top-row pool, w_i uniform."""
+    rng = _stream(seed, 2, SERVE_TABLE_ID)
+    return [int(rng.integers(0, 1 << (top - mu))) for mu, _, _ in specs]

@@ -1,8 +1,9 @@
 """Serving loop: proofs admitted by HBM footprint as they arrive, advanced
 together one round per step (continuous batching).
 
-Each request brings a shape, its packed tables (device resident, read only),
-its r and a tile.  The loop
+Each request brings a shape, its packed tables (device resident, read only,
+possibly a 2^mu-element window of a larger packed table: `pitch`), its r and
+a tile.  The loop
 * admits waiting requests in arrival order while a slot is free and their
   device footprint (workspace + outputs, plus a table copy when the request
   arrives with host tables) fits the memory budget;
@@ -38,6 +39,8 @@ class Request:
     r: torch.Tensor             # device, mu x 8
     tile: int = 0
     host_tables: bool = False   # tables live in pinned host memory: copy at admission
+    pitch: int = 0              # plane pitch of the tables (0: 2^mu, as zc_pack makes them)
+    shared_tables: bool = False  # the tables are views into a pool resident for the whole run
     # filled by the loop
     t_admit: float = float("nan")
     t_done: float = float("nan")
@@ -56,10 +59,14 @@ class Request:
 
 
 def footprint(req: Request) -> int:
-    """Device bytes a request holds while admitted."""
+    """Device bytes a request holds while admitted: its workspace, its outputs
+    and its k packed tables (copied to the device at admission for host
+    tables, already resident otherwise).  Tables that are views into a pool
+    resident for the whole run (shared_tables) are the pool's bytes, which the
+    caller keeps out of the budget, so they count 0 here."""
     s = req.shape
     out = (s.mu * (zc.degree(s) + 2) + zc.table_count(s) + 1 + s.mu) * 32
-    tabs = sum(t.numel() * 4 for t in req.tables) if req.host_tables else 0
+    tabs = 0 if req.shared_tables else zc.table_count(s) * (1 << s.mu) * 32
     return zc.workspace_bytes(s) + out + tabs
 
 
@@ -87,7 +94,8 @@ class Server:
         ev, al, op = req.outputs
         req._tabarr = (ctypes.c_void_p * len(req._dev_tables))(*[t.data_ptr() for t in req._dev_tables])
         req._inst = zc.Instance(s, ctypes.cast(req._tabarr, ctypes.c_void_p), req.r.data_ptr(),
-                                req.ws.data_ptr(), ev.data_ptr(), al.data_ptr(), op.data_ptr(), req.tile)
+                                req.ws.data_ptr(), ev.data_ptr(), al.data_ptr(), op.data_ptr(), req.tile,
+                                req.pitch)
         self.pool.admit(slot, req._inst)
         req.t_admit = now
 
@@ -150,9 +158,13 @@ class Server:
         lat = sorted(q.latency for q in requests)
         pts = sum(q.points for q in requests)
 
-        def pct(p):
-            return lat[min(len(lat) - 1, int(round(p / 100.0 * (len(lat) - 1))))]
+        def pct(vals, p):
+            return vals[min(len(vals) - 1, int(round(p / 100.0 * (len(vals) - 1))))]
 
+        by_mu = {}
+        for mu in sorted({q.shape.mu for q in requests}):
+            lm = sorted(q.latency for q in requests if q.shape.mu == mu)
+            by_mu[str(mu)] = {"n": len(lm), "p50_ms": pct(lm, 50) * 1e3, "p99_ms": pct(lm, 99) * 1e3}
         return {"requests": len(requests), "points": pts, "wall_s": wall, "points_per_s": pts / wall,
-                "p50_ms": pct(50) * 1e3, "p99_ms": pct(99) * 1e3, "steps": steps,
-                "errors": sum(1 for q in requests if q.err != 0)}
+                "p50_ms": pct(lat, 50) * 1e3, "p99_ms": pct(lat, 99) * 1e3, "steps": steps,
+                "errors": sum(1 for q in requests if q.err != 0), "by_mu": by_mu}

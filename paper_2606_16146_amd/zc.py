@@ -30,7 +30,7 @@ class Instance(ctypes.Structure):
     """zc_instance: one proof of a batch."""
     _fields_ = [("shape", Shape), ("tables", ctypes.c_void_p), ("r", ctypes.c_void_p), ("ws", ctypes.c_void_p),
                 ("round_evals", ctypes.c_void_p), ("challenges", ctypes.c_void_p),
-                ("openings", ctypes.c_void_p), ("tile", ctypes.c_uint32)]
+                ("openings", ctypes.c_void_p), ("tile", ctypes.c_uint32), ("pitch", ctypes.c_uint64)]
 
 
 class ZcError(RuntimeError):

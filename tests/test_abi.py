@@ -146,6 +146,10 @@ def test_batch_host_validation_without_gpu():
     assert h.zc_batch_upload(1, arr, ctypes.c_void_p(0x100004), None) == zc.ZC_EINVAL  # misaligned batch ws
     assert h.zc_batch_upload(3, arr, bws, None) == zc.ZC_EUNSUPPORTED  # the second instance's gate
     assert h.zc_batch_launch(3, arr, bws, None) == zc.ZC_EUNSUPPORTED
-    for one in (no_r, misaligned_ws):
+    short_pitch = zc.Instance(zc.shape(4, 0), ctypes.cast(tabs, ctypes.c_void_p), fake, fake, fake, fake, fake, 0,
+                              8)  # pitch below 2^mu
+    huge_pitch = zc.Instance(zc.shape(4, 0), ctypes.cast(tabs, ctypes.c_void_p), fake, fake, fake, fake, fake, 0,
+                             (1 << 30) + 1)
+    for one in (no_r, misaligned_ws, short_pitch, huge_pitch):
         a1 = (zc.Instance * 1)(one)
         assert h.zc_batch_prove(1, a1, bws, None) == zc.ZC_EINVAL

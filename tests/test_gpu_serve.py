@@ -1,12 +1,13 @@
 """Serving loop (zc_serve_* through paper_2606_16146_amd.serve): requests of
 mixed size and gate that arrive while others are on the GPU are admitted as
 slots and memory free up and share each step's launches; every result must
-be byte-identical to the same proof made alone with zc_prove (which the
-GPU parity tests tie to the oracle)."""
+be byte-identical to the same proof made alone with zc_prove and, for the
+mixed-size stream with mu up to 20, to the C oracle."""
 import numpy as np
 import pytest
 import torch
 
+from oracle import c_oracle as C
 from paper_2606_16146_amd import inputs as I
 from paper_2606_16146_amd import serve as S
 from paper_2606_16146_amd import zc
@@ -75,3 +76,52 @@ def test_host_tables_copied_at_admission():
     for q, inst in zip(reqs, insts):
         got = [o.cpu().numpy() for o in q.outputs]
         assert all(np.array_equal(a, b) for a, b in zip(got, _alone(inst)))
+
+
+def test_served_large_mix_with_pool_windows_matches_c_oracle():
+    """mu 17-20 requests of the degree-3 and degree-9 gates among small ones of
+    other gates, arriving staggered.  Half of them read a 2^mu-aligned window
+    of a shared mu = 20 packed pool in place (pitch 2^20; every row of the
+    pool satisfies its gate), the others own their tables.  Each result is
+    compared with the C oracle on the same rows and with zc_prove alone."""
+    dev_ = torch.device("cuda:0")
+    gates = [(0, 0), (1, 8)]
+    base = {g: I.make_instance(44, 7 + gi, 20, g[0], g[1], workers=8) for gi, g in enumerate(gates)}
+    scratch = zc.new_workspace(zc.shape(4, 0))
+    pool = {g: [zc.pack(dev(t), scratch) for t in base[g].tables] for g in gates}
+    # (mu, gate, m, arrival s, window index or None for own tables)
+    mix = [(20, 0, 0, 0.0, 0), (18, 1, 8, 0.0, 3), (9, 1, 4, 0.0005, None), (17, 0, 0, 0.001, None),
+           (19, 1, 8, 0.001, None), (12, 0, 0, 0.002, 5), (20, 1, 8, 0.002, 0), (6, 2, 34, 0.003, None),
+           (17, 1, 8, 0.003, 6), (14, 0, 0, 0.004, 2), (18, 0, 0, 0.004, 1), (11, 1, 2, 0.005, None)]
+    reqs, refs = [], []
+    for i, (mu, g, m, arr, win) in enumerate(mix):
+        s = zc.shape(mu, g, m)
+        r = I.draw_elements(45, i, I.R_TABLE_ID, mu)
+        if win is not None:
+            off, n = win << mu, 1 << mu
+            canon = base[(g, m)].tables[:, off:off + n]
+            tabs = [t[:, off:off + n] for t in pool[(g, m)]]
+            reqs.append(S.Request(i, arr, s, tabs, dev(r), tile=i % 3, pitch=1 << 20, shared_tables=True))
+        else:
+            inst = I.make_instance(46, i, mu, g, m)
+            canon = inst.tables
+            reqs.append(S.Request(i, arr, s, [zc.pack(dev(t), scratch) for t in canon], dev(r), tile=i % 3))
+        refs.append((np.ascontiguousarray(canon), r))
+    torch.cuda.synchronize()
+    stats = S.Server(slots=6).run(reqs)
+    assert stats["errors"] == 0 and stats["requests"] == len(mix)
+    for q, (canon, r) in zip(reqs, refs):
+        mu, g, m = q.shape.mu, q.shape.gate, q.shape.m
+        print(f"request {q.rid} mu={mu} gate={g} m={m} pitch={q.pitch}", flush=True)
+        got = [o.cpu().numpy() for o in q.outputs]
+        ora = C.prove(mu, g, m, canon, r)
+        assert np.array_equal(got[0], ora["evals"]) and np.array_equal(got[1], ora["alphas"])
+        assert np.array_equal(got[2], ora["openings"])
+        alone = _alone(I.Instance(0, 0, mu, g, m, canon, r))
+        assert all(np.array_equal(a, b) for a, b in zip(got, alone))
+    # the admission footprint counts a request's own tables, not a shared pool's
+    for q in reqs:
+        k, n = zc.table_count(q.shape), 1 << q.shape.mu
+        own = 0 if q.shared_tables else k * n * 32
+        outs = (q.shape.mu * (zc.degree(q.shape) + 2) + k + 1 + q.shape.mu) * 32
+        assert S.footprint(q) == zc.workspace_bytes(q.shape) + outs + own
