@@ -72,6 +72,54 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def host_cpu():
+    """The host the CPU baseline ran on: logical CPUs, the ones this process
+    may use, the OpenMP thread count it used, and the CPU model."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return {"nproc": os.cpu_count(), "usable_cpus": usable, "omp_num_threads": os.environ.get("OMP_NUM_THREADS"),
+            "model": model}
+
+
+# v_mad_u64_u32 rate demonstrated on this GPU by the microbenchmark
+# (zc_bench_mad, full occupancy), measured at the start of the run
+MAD_PEAK_DEMONSTRATED = None
+
+
+def measure_mad_peak():
+    """T v_mad_u64_u32/s at full occupancy (8 waves per SIMD, 8 independent
+    chains per thread), median of 5 event-timed launches."""
+    import torch
+
+    from paper_2606_16146_amd import zc
+
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    sink = torch.zeros(1 << 16, dtype=torch.uint32, device="cuda:0")
+    blocks, iters = cus * 8, 256
+    zc.bench_mad(blocks, 8, iters, sink)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(5):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        zc.bench_mad(blocks, 8, iters, sink)
+        b.record()
+        b.synchronize()
+        ts.append(a.elapsed_time(b) * 1e-3)
+    return blocks * 256 * 8 * iters * 32 / statistics.median(ts) / 1e12
+
+
 def round_work(mu, gate, m, k, d, i):
     """Algorithmic (bytes, field products) of the round-i kernel launch.
 
@@ -110,7 +158,8 @@ def run_workload(name, steps, warmup, cpu_baseline):
     outs = zc.new_outputs(s, dev)
     if zc.read_error(ws) != 0:
         raise RuntimeError("pack flagged an input")
-    ev = zc.HipEvents(2 * mu * steps)
+    per = 2 * mu + 2  # one event before each profiled proof, 2 mu around its round kernels, one after
+    ev = zc.HipEvents(per * steps)
 
     for _ in range(warmup):
         zc.prove(s, tabs, r, ws, outs)
@@ -131,7 +180,9 @@ def run_workload(name, steps, warmup, cpu_baseline):
     # (each event record also delays the next launch by a few microseconds, so
     # these proofs are not the timed ones)
     for st in range(steps):
-        zc.prove_profiled(s, tabs, r, ws, ev, outs, first_event=st * 2 * mu)
+        ev.record(st * per)
+        zc.prove_profiled(s, tabs, r, ws, ev, outs, first_event=st * per + 1)
+        ev.record(st * per + per - 1)
     torch.cuda.synchronize()
     if zc.read_error(ws) != 0:
         raise RuntimeError("device error in the profiled proofs")
@@ -147,9 +198,26 @@ def run_workload(name, steps, warmup, cpu_baseline):
     kinds = [zc.lib().zc_prove_round_kernel(ctypes.byref(s), i) for i in range(1, mu + 1)]
     fused_t, fused_b, fused_p, first_t, split_t = 0.0, 0, 0, 0.0, 0.0
     launches = 0
+    # the split of a proof in the manner of Table 3 (round 1, round 2 -- the
+    # first round that folds --, rounds 3..mu), each round counted from the
+    # start of its round kernel to the start of the next one (so with its
+    # finisher), plus the setup before round 1
+    split = {"setup": 0.0, "round1": 0.0, "round2": 0.0, "rounds3_to_mu": 0.0}
+    for st in range(steps):
+        b0 = st * per
+        e = lambda i: b0 + 1 + 2 * (i - 1)  # event before round i's kernel
+        split["setup"] += ev.elapsed_ms(b0, e(1)) * 1e-3
+        split["round1"] += ev.elapsed_ms(e(1), e(2)) * 1e-3
+        split["round2"] += ev.elapsed_ms(e(2), e(3)) * 1e-3
+        split["rounds3_to_mu"] += ev.elapsed_ms(e(3), b0 + per - 1) * 1e-3
+    prof_total = sum(split.values())
+    table3 = {k + "_us": round(v / steps * 1e6, 1) for k, v in split.items()}
+    table3.update({k + "_pct": round(100 * v / prof_total, 1) for k, v in split.items()})
+    table3["note"] = ("from the event-bracketed proofs (each event record delays the next launch by a few "
+                      "microseconds, so their total exceeds ms_per_step)")
     for st in range(steps):
         for i in range(1, mu + 1):
-            a = st * 2 * mu + 2 * (i - 1)
+            a = st * per + 1 + 2 * (i - 1)
             dt = ev.elapsed_ms(a, a + 1) * 1e-3
             b, p = round_work(mu, gate, m, k, d, i)
             if i == 1:
@@ -181,11 +249,24 @@ def run_workload(name, steps, warmup, cpu_baseline):
     bound, other = (alu, hbm) if alu["frac"] >= hbm["frac"] else (hbm, alu)
 
     points = 1 << mu
+    # whole proof: the algorithmic bytes and multiply-adds of every round
+    wb = sum(round_work(mu, gate, m, k, d, i)[0] for i in range(1, mu + 1))
+    wp = sum(round_work(mu, gate, m, k, d, i)[1] for i in range(1, mu + 1))
+    proof_s = elapsed / steps
+    whole = {"algorithmic_bytes": wb, "algorithmic_mads": wp * MADS_PER_MUL,
+             "hbm_frac": round(wb / proof_s / (HBM_PEAK_GBS * 1e9), 4),
+             "alu_frac": round(wp * MADS_PER_MUL / proof_s / (MAD_PEAK_TOPS * 1e12), 4)}
+    if MAD_PEAK_DEMONSTRATED:
+        whole["alu_frac_of_demonstrated"] = round(wp * MADS_PER_MUL / proof_s / (MAD_PEAK_DEMONSTRATED * 1e12), 4)
+        for rf in (hbm, alu):
+            rf["alu_frac_of_demonstrated"] = round(fused_p * MADS_PER_MUL / fused_t / (MAD_PEAK_DEMONSTRATED * 1e12), 4)
     res = {
         "value": steps * points / elapsed,
         "ms_per_step": elapsed / steps * 1e3,
         "roofline": bound,
         "roofline_other": other,
+        "whole_proof": whole,
+        "table3_split": table3,
         "round1_avg_us": round(first_t / steps * 1e6, 2),
         "split_rounds_us": round(split_t / steps * 1e6, 2),
         "round_kernels_share": round((fused_t + first_t + split_t) / elapsed, 4),
@@ -210,7 +291,8 @@ def run_workload(name, steps, warmup, cpu_baseline):
                                "kind": "oracle",
                                "sample": f"C oracle (OpenMP), whole {name} proof on the same inputs, "
                                          f"median of 3 runs ({tmed:.2f} s each, about "
-                                         f"{3 * tmed * C.max_threads():.0f} core-seconds in all)"}
+                                         f"{3 * tmed * C.max_threads():.0f} core-seconds in all)",
+                               "host": host_cpu()}
         res["parity_vs_oracle"] = "bit-exact" if same else "MISMATCH"
         log(f"[bench] {name}: C oracle {tmed:.2f}s on {C.max_threads()} threads, parity={same}")
         if not same:
@@ -516,6 +598,9 @@ def main():
         log(f"[bench] copy calibration: 3 x {args.copy_calibration} MiB device copies")
         del src, dst, flush
 
+    global MAD_PEAK_DEMONSTRATED
+    MAD_PEAK_DEMONSTRATED = measure_mad_peak()
+    log(f"[bench] v_mad_u64_u32 demonstrated: {MAD_PEAK_DEMONSTRATED:.2f} T/s")
     main_res = run_workload(args.workload, args.steps, args.warmup, not args.no_cpu_baseline)
     out = {
         "metric": METRIC,
@@ -534,8 +619,10 @@ def main():
         "roofline": main_res["roofline"],
         "roofline_other": main_res["roofline_other"],
     }
-    for key in ("cpu_baseline", "parity_vs_oracle", "round1_avg_us", "split_rounds_us",
-                "round_kernels_share"):
+    out["roofline"]["peak_demonstrated"] = round(MAD_PEAK_DEMONSTRATED, 2)
+    out["roofline_other"]["peak_demonstrated"] = round(MAD_PEAK_DEMONSTRATED, 2)
+    for key in ("cpu_baseline", "parity_vs_oracle", "whole_proof", "table3_split", "round1_avg_us",
+                "split_rounds_us", "round_kernels_share"):
         if key in main_res:
             out[key] = main_res[key]
     if args.secondary:

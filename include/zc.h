@@ -51,8 +51,20 @@ typedef enum {
   ZC_EHIP = -3,         /* a HIP call or kernel launch failed */
   ZC_ERANGE = -4,       /* (device) an input element was >= p */
   ZC_ESTATE = -5,       /* (device) zc_round / zc_fold called out of order */
-  ZC_ETOOBIG = -6       /* the shape needs more workspace than zc_prove_static holds */
+  ZC_ETOOBIG = -6,      /* the shape needs more workspace than zc_prove_static holds */
+  ZC_ECLAIM = -7        /* (device, ZC_FLAG_CHECK_CLAIMS) a round failed the verifier's claim check */
 } zc_status;
+
+/* zc_shape.flags */
+enum {
+  /* Self-checks on the device (debug): each round checks
+     G_i(0) + G_i(1) = G_{i-1}(alpha_{i-1}) (Sec. 3.4; 0 for i = 1, which a
+     witness that does not satisfy the gate fails), and the proof's last step
+     checks G_mu(alpha_mu) = f_M(openings) eq_r(alpha).  A failure is stored
+     as ZC_ECLAIM (zc_read_error); the outputs are unchanged.  Costs a
+     Lagrange evaluation per round on an otherwise idle lane. */
+  ZC_FLAG_CHECK_CLAIMS = 1
+};
 
 typedef enum {
   /* f = qM*a*b + qL*a + qR*b + qO*c + qC, degree 3,
@@ -66,11 +78,13 @@ typedef enum {
   ZC_GATE_SUMPROD = 2
 } zc_gate;
 
-/* Instance shape: 1 <= mu <= 30, gate in zc_gate, m used by ZC_GATE_PROD. */
+/* Instance shape: 1 <= mu <= 30, gate in zc_gate, m used by ZC_GATE_PROD and
+   ZC_GATE_SUMPROD, flags a set of ZC_FLAG_* (0 for none). */
 typedef struct {
   uint32_t mu;
   uint32_t gate;
   uint32_t m;
+  uint32_t flags;
 } zc_shape;
 
 /* Number of witness tables k of the gate (eq not counted), or a negative zc_status. */

@@ -215,6 +215,32 @@ struct LagrangeW {
     }
   }
 };
+// Lagrange weights of the nodes 0..N-1 in Montgomery form, for any N <= 12:
+// w_k = (-1)^(N-1-k) / (k! (N-1-k)!), from the inverses of the small
+// factorials (products of exact inverses of small integers).
+template <int N>
+struct LagrangeN {
+  L9 w[N];     // w_k R
+  L9 node[N];  // k R
+  constexpr LagrangeN() : w{}, node{} {
+    L9 invf[N]{};  // (1 / j!) R
+    invf[0] = kOne;
+    for (int j = 1; j < N; ++j)
+      invf[j] = detail::mont_mul(invf[j - 1], detail::mont_mul(detail::inv_small((uint32_t)j), kR2));
+    for (int k = 0; k < N; ++k) {
+      L9 v = detail::mont_mul(invf[k], invf[N - 1 - k]);
+      if ((N - 1 - k) % 2 == 1 && !detail::same(v, L9{})) v = detail::sub(kP, v);
+      w[k] = v;
+      L9 c{};
+      for (int t = 0; t < k; ++t) {
+        c = detail::add(c, kOne);
+        if (detail::geq(c, kP)) c = detail::sub(c, kP);
+      }
+      node[k] = c;
+    }
+  }
+};
+
 static_assert(detail::same(detail::mont_mul(kR2, detail::pow2_mod(0)), kOne), "R^2 R^-1 = R");
 static_assert(detail::same(kRPow.v[1], kR2) && detail::same(kRPow.v[2], detail::pow2_mod(783)),
               "powers of R from products equal those from doublings");

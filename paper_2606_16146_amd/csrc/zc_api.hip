@@ -60,7 +60,7 @@ int shape_d(const zc_shape* s) {
 int make_layout(const zc_shape* s, Layout* L) {
   const int k = shape_k(s);
   if (k < 0) return k;
-  if (s->mu < 1 || s->mu > (uint32_t)kMuMax) return ZC_EINVAL;
+  if (s->mu < 1 || s->mu > (uint32_t)kMuMax || (s->flags & ~(uint32_t)ZC_FLAG_CHECK_CLAIMS)) return ZC_EINVAL;
   L->k = (uint32_t)k;
   L->d = (uint32_t)shape_d(s);
   L->ml = s->mu / 2;
@@ -166,6 +166,7 @@ RoundArgs round_args(const zc_shape* s, const Layout& L, void* ws, uint32_t i,
   a.eq.ml = L.ml;
   a.eq.mh = L.mh;
   a.eq.mu = s->mu;
+  a.check = (s->flags & ZC_FLAG_CHECK_CLAIMS) ? 1u : 0u;
   return a;
 }
 
@@ -394,6 +395,7 @@ InstDesc make_desc(const zc_instance& in, const Layout& L, uint32_t last) {
   d.ne = L.d + 2;
   d.last = last;
   d.pitch = in.pitch ? in.pitch : n;
+  d.flags = in.shape.flags;
   return d;
 }
 
@@ -740,6 +742,7 @@ const char* zc_strerror(int status) {
     case ZC_ERANGE: return "input element not below p";
     case ZC_ESTATE: return "zc_round / zc_fold called out of order";
     case ZC_ETOOBIG: return "shape needs more workspace than zc_prove_static holds (32 MiB)";
+    case ZC_ECLAIM: return "a round polynomial failed the verifier's claim check (ZC_FLAG_CHECK_CLAIMS)";
     default: return "unknown status";
   }
 }

@@ -517,6 +517,7 @@ struct RoundArgs {
   uint32_t tail;               // 1: the finisher also runs rounds round+1..mu and the openings
   uint32_t* openings;          // tail only: (k+1) x 8 canonical
   EqTabs eq;
+  uint32_t check;              // 1: the verifier's claim checks on the device (ZC_FLAG_CHECK_CLAIMS)
 };
 
 // Montgomery product reduced below p.
@@ -538,6 +539,39 @@ __device__ __forceinline__ Fe fe_vgpr(Fe a) {
 #pragma unroll
   for (int i = 0; i < NL; ++i) asm("" : "+v"(a.l[i]));
   return a;
+}
+
+// ---- the verifier's claims, for the optional self-checks ---------------------------
+
+__device__ __forceinline__ bool fe_eq(const Fe& a, const Fe& b) {
+  uint32_t o = 0;
+#pragma unroll
+  for (int i = 0; i < NL; ++i) o |= a.l[i] ^ b.l[i];
+  return o == 0;
+}
+
+// sum_k y_k L_k(x) for the polynomial of degree < N whose values at the nodes
+// 0..N-1 are y (N canonical elements, 8 words each), at x (canonical): the
+// claim G_i(alpha_i) of Sec. 3.4.  One lane; canonical result < p.  L_k(x) =
+// w_k prod_{j != k} (x - j) from prefix and suffix products.
+template <int N>
+__device__ __noinline__ Fe lagrange_at(const uint32_t* y, Fe x) {
+  constexpr LagrangeN<N> W{};
+  const Fe xm = fe_to_mont(fe_vgpr(x));
+  Fe dif[N], pre[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) dif[k] = fe_submod(xm, fe_const(W.node[k]));  // (x - k) R
+  pre[0] = fe_const(kOne);
+#pragma unroll
+  for (int k = 1; k < N; ++k) pre[k] = mont(pre[k - 1], dif[k - 1]);
+  Fe suf = fe_const(kOne), acc = fe_zero();
+#pragma unroll
+  for (int k = N - 1; k >= 0; --k) {
+    const Fe lk = mont(fe_const(W.w[k]), mont(pre[k], suf));  // L_k(x) R
+    acc = fe_addmod(acc, mont(lk, fe_to_mont(load_words_fe(y + 8 * k))));
+    suf = mont(suf, dif[k]);
+  }
+  return fe_from_mont(acc);
 }
 
 // ---- the end of a round ---------------------------------------------------------
@@ -610,7 +644,7 @@ __device__ __forceinline__ void fin_start(const Ctrl* ctrl, uint32_t round, FinL
 // they load from the eq1 rows then (the hash hides that latency).
 template <int D>
 __device__ __forceinline__ void emit_round(Ctrl* ctrl, uint32_t round, FinLds<D>& S, uint32_t* evals_out,
-                                           uint32_t* alpha_out) {
+                                           uint32_t* alpha_out, bool check) {
   constexpr int NH = D + 1, NE = D + 2, NC = FinLds<D>::NC;
   constexpr uint32_t LEN = FinLds<D>::LEN, NB = FinLds<D>::NB;
   static_assert(NH <= 16, "one 16-lane group");
@@ -666,6 +700,13 @@ __device__ __forceinline__ void emit_round(Ctrl* ctrl, uint32_t round, FinLds<D>
     const Fe y = mont(fe_vgpr(lds_fe(S.cm)), load_words_fe(f));
     lds_put(l == (uint32_t)NC ? (qv ? S.q2 : S.pc) : (qv ? S.v[l] : S.u[l]), y);
     store_words_fe(l == (uint32_t)NC ? (qv ? ctrl->nqr : ctrl->npr) : (qv ? ctrl->nv[l] : ctrl->nu[l]), y);
+  } else if (check && t == kBlock - 1) {
+    // self-check (Sec. 3.4): G_i(0) + G_i(1) = G_{i-1}(alpha_{i-1}), the claim
+    // of round i-1 (0 before round 1)
+    static_assert(128 + 2 * (NC + 1) < kBlock, "the last lane is free");
+    Fe claim = fe_zero();
+    if (round > 1) claim = lagrange_at<NE>(evals_out - NE * 8, load_words_fe(ctrl->alpha[round - 2]));
+    if (!fe_eq(claim, fe_addmod(load_words_fe(S.msg + 8), load_words_fe(S.msg + 16)))) set_error(ctrl, -7);
   }
   __syncthreads();
   if (t == 0) {
@@ -903,7 +944,21 @@ __device__ __forceinline__ void run_tail(const RoundArgs& a, const TabPtrs& dst,
     if (pp == 0 && x < (uint32_t)NH) lds_put(S.h[x], c);
     __syncthreads();
     emit_round<Gate::D>(a.ctrl, r, S, a.evals_out + (uint64_t)(r - a.round) * Gate::NE * 8,
-                        a.alpha_out + (uint64_t)(r - a.round) * 8);
+                        a.alpha_out + (uint64_t)(r - a.round) * 8, a.check != 0);
+  }
+  if (a.check && tid == 0) {
+    // self-check of the final identity (Sec. 3.3, 3.4): G_mu(alpha_mu) =
+    // f_M(openings) eq(alpha, r), the openings being entry 0 of each table
+    // and eq(alpha, r) = C_{mu+1}
+    uint32_t w[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) w[k] = S.ac[k];
+    const Fe claim = lagrange_at<Gate::NE>(a.evals_out + (uint64_t)(a.mu - a.round) * Gate::NE * 8, fe_from_words(w));
+    Fe e[K];
+#pragma unroll
+    for (int t = 0; t < K; ++t) e[t] = lds_fe(T(t, 0));
+    const Fe f = fe_reduce32(Gate::point(e));  // f_M(openings) R
+    if (!fe_eq(claim, fe_from_mont(mont(f, fe_vgpr(lds_fe(S.cm)))))) set_error(a.ctrl, -7);
   }
   if (tid < K) store_words_fe(a.openings + tid * 8, fe_from_mont(lds_fe(T(tid, 0))));
   if (tid == K) store_words_fe(a.openings + K * 8, fe_from_mont(fe_vgpr(lds_fe(S.cm))));
@@ -1160,7 +1215,7 @@ __device__ __forceinline__ void finish_body(const RoundArgs& a, const TabPtrs& d
     }
     __syncthreads();
   }
-  emit_round<Gate::D>(a.ctrl, a.round, S, a.evals_out, a.alpha_out);
+  emit_round<Gate::D>(a.ctrl, a.round, S, a.evals_out, a.alpha_out, a.check != 0);
   if (a.tail) run_tail<Gate>(a, dst, S, SPEC);
 }
 
@@ -1209,7 +1264,7 @@ struct InstDesc {
   const uint32_t* r;
   uint32_t mu, gate, m, ne;
   uint32_t last;       // last round with a round kernel; its finisher runs the tail
-  uint32_t pad;
+  uint32_t flags;      // zc_shape.flags
   uint64_t pitch;      // plane pitch of the caller tables (elements, >= 2^mu)
 };
 
@@ -1259,6 +1314,7 @@ __device__ __forceinline__ RoundArgs batch_round_args(const InstDesc& d, uint32_
   a.tail = round == d.last ? 1u : 0u;
   a.openings = d.openings;
   a.eq = d.eq;
+  a.check = d.flags & 1u;
   return a;
 }
 

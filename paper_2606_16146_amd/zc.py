@@ -18,12 +18,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("ZC_LIB") or os.path.join(HERE, "libzc.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
-ZC_OK, ZC_EINVAL, ZC_EUNSUPPORTED, ZC_EHIP, ZC_ERANGE, ZC_ESTATE, ZC_ETOOBIG = 0, -1, -2, -3, -4, -5, -6
+ZC_OK, ZC_EINVAL, ZC_EUNSUPPORTED, ZC_EHIP, ZC_ERANGE, ZC_ESTATE, ZC_ETOOBIG, ZC_ECLAIM = 0, -1, -2, -3, -4, -5, -6, -7
+ZC_FLAG_CHECK_CLAIMS = 1
 GATE_VANILLA, GATE_PROD, GATE_SUMPROD = 0, 1, 2
 
 
 class Shape(ctypes.Structure):
-    _fields_ = [("mu", ctypes.c_uint32), ("gate", ctypes.c_uint32), ("m", ctypes.c_uint32)]
+    _fields_ = [("mu", ctypes.c_uint32), ("gate", ctypes.c_uint32), ("m", ctypes.c_uint32),
+                ("flags", ctypes.c_uint32)]
 
 
 class Instance(ctypes.Structure):
@@ -115,8 +117,8 @@ def _ptr(t: torch.Tensor):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def shape(mu: int, gate: int, m: int = 0) -> Shape:
-    return Shape(mu, gate, m)
+def shape(mu: int, gate: int, m: int = 0, flags: int = 0) -> Shape:
+    return Shape(mu, gate, m, flags)
 
 
 def table_count(s: Shape) -> int:
@@ -297,6 +299,13 @@ class HipEvents:
             rc = self.hip.hipEventCreate(ctypes.c_void_p(base + i * ctypes.sizeof(ctypes.c_void_p)))
             if rc != 0:
                 raise ZcError(ZC_EHIP, "hipEventCreate")
+
+    def record(self, i: int, stream=None):
+        """hipEventRecord of event i on the stream (torch's current one by default)."""
+        self.hip.hipEventRecord.argtypes = [_VP, _VP]
+        rc = self.hip.hipEventRecord(ctypes.c_void_p(self.arr[i]), _stream(stream))
+        if rc != 0:
+            raise ZcError(ZC_EHIP, "hipEventRecord")
 
     def elapsed_ms(self, a: int, b: int) -> float:
         self.hip.hipEventSynchronize(self.arr[b])

@@ -41,6 +41,11 @@ def test_invalid_shapes(mu, gate, m):
         assert zc.table_count(s) == zc.ZC_EUNSUPPORTED
 
 
+def test_unknown_flags_are_rejected():
+    assert zc.workspace_bytes(zc.shape(10, 0, 0, 2)) == 0
+    assert zc.workspace_bytes(zc.shape(10, 0, 0, zc.ZC_FLAG_CHECK_CLAIMS)) == zc.workspace_bytes(zc.shape(10, 0))
+
+
 def test_host_validation_rejects_bad_arguments_without_gpu():
     h = zc.lib()
     s = zc.shape(4, 0)
@@ -93,7 +98,7 @@ def test_static_prove_rejects_before_any_gpu_work():
 
 
 def test_strerror_covers_every_status():
-    for st in (0, -1, -2, -3, -4, -5, -6):
+    for st in (0, -1, -2, -3, -4, -5, -6, -7):
         assert zc.strerror(st) and zc.strerror(st) != "unknown status"
     assert zc.strerror(-99) == "unknown status"
 
