@@ -13,7 +13,19 @@ inline int launch_ok() { return hipGetLastError() == hipSuccess ? 0 : -3; }
 
 template <class Gate>
 size_t tail_lds_bytes() {
-  return (size_t)(Gate::K + 1) * 4 * kTailQ * NL * sizeof(uint32_t);
+  return (size_t)tail_lds_words<Gate>() * sizeof(uint32_t);
+}
+
+// The tail's dynamic LDS can pass 64 KiB (gfx950 has 160 KiB per CU): allow
+// it for a kernel once, before its first launch with a tail.
+template <class KernelTag>
+void allow_tail_lds(const void* kernel, size_t bytes) {
+  static const bool done = [kernel, bytes] {
+    (void)hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    (void)hipGetLastError();
+    return true;
+  }();
+  (void)done;
 }
 
 // Blocks of `kernel` (kBlock threads, no dynamic LDS) resident per CU; the
@@ -30,6 +42,14 @@ int resident_blocks(const void* kernel) {
 
 template <class Gate, bool FOLD, bool SPLIT>
 struct RoundTag {};
+template <class Gate>
+struct FinishTag {};
+template <class Gate>
+struct FinishSpecTag {};
+template <class Gate>
+struct BatchFinishTag {};
+template <class Gate>
+struct ServeFinishTag {};
 
 // Grid of a round kernel: enough blocks for the work, at most one resident
 // generation (CUs x resident blocks per CU) and at most kMaxBlocks.
@@ -82,6 +102,7 @@ int launch_round(bool fold, RoundKind kind, RoundArgs a, const TabPtrs& src, con
   a.nparts = blocks;
   a.tail = (kind == kSplitTail) ? 1u : 0u;
   const size_t lds = a.tail ? tail_lds_bytes<Gate>() : 0;
+  if (lds) allow_tail_lds<FinishTag<Gate>>(reinterpret_cast<const void*>(&k_finish<Gate>), lds);
   hipLaunchKernelGGL((k_finish<Gate>), dim3(1), dim3(kBlock), lds, st, a, dst);
   return launch_ok();
 }
@@ -103,6 +124,7 @@ int launch_spec(ZC_SPEC_ARGS) {
       hipLaunchKernelGGL((k_round<Gate, true>), dim3(b), dim3(kBlock), 0, st, sa, src, dst);
       *blocks = b;
     } else if (step == kSpecFinishTail) {
+      allow_tail_lds<FinishSpecTag<Gate>>(reinterpret_cast<const void*>(&k_finish_spec<Gate>), tail_lds_bytes<Gate>());
       hipLaunchKernelGGL((k_finish_spec<Gate>), dim3(1), dim3(kBlock), tail_lds_bytes<Gate>(), st, fa, fdst);
     } else {
       const bool first = step == kSpecFirst;
@@ -135,6 +157,7 @@ int launch_batch(const BatchStep& bs, uint32_t blocks, bool fold, bool tail, hip
     hipLaunchKernelGGL((k_batch_round<Gate, false>), dim3(blocks), dim3(kBlock), 0, st, bs);
   int rc = launch_ok();
   if (rc != 0) return rc;
+  if (tail) allow_tail_lds<BatchFinishTag<Gate>>(reinterpret_cast<const void*>(&k_batch_finish<Gate>), tail_lds_bytes<Gate>());
   hipLaunchKernelGGL((k_batch_finish<Gate>), dim3(bs.count), dim3(kBlock), tail ? tail_lds_bytes<Gate>() : 0, st, bs);
   return launch_ok();
 }
@@ -148,6 +171,7 @@ int launch_serve(const ServeStep& ss, uint32_t blocks, bool fold, bool tail, hip
     hipLaunchKernelGGL((k_serve_round<Gate, false>), dim3(blocks), dim3(kBlock), 0, st, ss);
   int rc = launch_ok();
   if (rc != 0) return rc;
+  if (tail) allow_tail_lds<ServeFinishTag<Gate>>(reinterpret_cast<const void*>(&k_serve_finish<Gate>), tail_lds_bytes<Gate>());
   hipLaunchKernelGGL((k_serve_finish<Gate>), dim3(ss.count), dim3(kBlock), tail ? tail_lds_bytes<Gate>() : 0, st, ss);
   return launch_ok();
 }

@@ -642,9 +642,15 @@ __device__ __forceinline__ void fin_start(const Ctrl* ctrl, uint32_t round, FinL
 // block 0 straight from the message; after a barrier lane 0 runs the rest
 // from LDS.  Meanwhile lanes 128 on form the state of round+1, whose factors
 // they load from the eq1 rows then (the hash hides that latency).
-template <int D>
+struct NoSideWork {
+  __device__ void operator()() const {}
+};
+
+// `side` runs on waves 1..3 while lane 0 compresses the message after its
+// first 16 rounds (the hash's serial part); it must not use __syncthreads.
+template <int D, class Side = NoSideWork>
 __device__ __forceinline__ void emit_round(Ctrl* ctrl, uint32_t round, FinLds<D>& S, uint32_t* evals_out,
-                                           uint32_t* alpha_out, bool check) {
+                                           uint32_t* alpha_out, bool check, Side side = Side{}) {
   constexpr int NH = D + 1, NE = D + 2, NC = FinLds<D>::NC;
   constexpr uint32_t LEN = FinLds<D>::LEN, NB = FinLds<D>::NB;
   static_assert(NH <= 16, "one 16-lane group");
@@ -731,6 +737,8 @@ __device__ __forceinline__ void emit_round(Ctrl* ctrl, uint32_t round, FinLds<D>
       alpha_out[k] = w[k];
     }
     ctrl->round_done = round;
+  } else if (t >= 64) {
+    side();
   }
   __syncthreads();
 }
@@ -868,6 +876,111 @@ __device__ __forceinline__ Fe group_reduce(Fe c) {
 //
 // With prefold the tables at dst hold T_{a.round - 1} (4q entries) instead:
 // they are folded with alpha_{a.round - 1} on the way into LDS.
+// ---- speculation inside the tail (gates of degree <= 3) ------------------------------
+//
+// While lane 0 hashes round r, waves 1..3 evaluate round r+1 for every
+// candidate alpha_r = c in 0..d (the tables folded with c, like spec_body);
+// round r+1 then takes H_{r+1}(X) = sum_c L_c(alpha_r) H_{r+1}(X; c), one
+// product per lane, instead of a fold, an evaluation and a reduction on its
+// critical path.  H_{r+1}(X) has degree <= d in alpha_r (the folded tables
+// are affine in it, f_M has degree d), so the interpolation is exact.
+template <class Gate>
+struct TailSpec {
+  static constexpr bool kOn = Gate::NH * Gate::NH <= 16 && Gate::D >= 2;
+};
+
+// LDS words of the tail: K tables and the eq rows (4 kTailQ entries each),
+// then with speculation the candidate tables (K x (d+1) x kTailQ entries),
+// 16 speculative sums, 3 x 16 per-wave sums and a barrier counter.
+template <class Gate>
+constexpr uint32_t tail_lds_words() {
+  uint32_t w = (uint32_t)(Gate::K + 1) * 4u * kTailQ * NL;
+  if (TailSpec<Gate>::kOn) w += (uint32_t)(Gate::K * Gate::NH) * kTailQ * NL + 16u * NL + 3u * 16u * NL + 1u;
+  return w;
+}
+
+// L_c(x) R for the nodes 0..D (D = 2, 3), x canonical: w_c R^(D+1) times the
+// D factors (x - k), k != c, canonical, in D Montgomery products.
+template <int D>
+__device__ __forceinline__ Fe lagrange_basis(const Fe& x, uint32_t c) {
+  static_assert(D == 2 || D == 3, "two or three factors");
+  constexpr LagrangeW<D> W{};
+  Fe tk[D + 1];
+  Fe ws = fe_zero();
+  auto terms = [&](auto k) __attribute__((always_inline)) {
+    Fe kk = fe_zero();
+    kk.l[0] = (uint32_t)k;
+    tk[k] = fe_submod(x, kk);
+    if (c == (uint32_t)k) ws = fe_const(W.wsh[k]);
+  };
+  Unroll<0, D + 1>::run(terms);
+  const Fe f0 = fe_sel(c == 0, tk[1], tk[0]);
+  const Fe f1 = fe_sel(c <= 1, tk[2], tk[1]);
+  if constexpr (D == 3) return mont(mont(ws, f0), mont(f1, fe_sel(c <= 2, tk[3], tk[2])));
+  else return mont(mont(ws, f0), f1);
+}
+
+// A barrier of waves 1..3 (wave 0 is hashing meanwhile): each wave adds 1 to
+// the counter and waits for `target` arrivals; targets grow by 3 per use, so
+// the counter is never reset.  All three waves reach every use.
+__device__ __forceinline__ void waves123_barrier(uint32_t* ctr, uint32_t target) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  if ((threadIdx.x & 63u) == 0) __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < target) __builtin_amdgcn_s_sleep(1);
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Waves 1..3 during round r's hash: H_{r+1}(x; c) for x, c in 0..d into
+// HSP[4 c + x], from the tables of round r (L entries) folded with c.
+// Nothing to do after the last round.
+template <class Gate, class TF, class UF>
+__device__ __forceinline__ void tail_speculate(uint32_t r, uint32_t L, uint32_t mu, TF T, UF U, const uint32_t* eqrow,
+                                               uint32_t* HSP, uint32_t* RED3, uint32_t* CTR, uint32_t& bar_target) {
+  constexpr int K = Gate::K;
+  constexpr int NH = Gate::NH;
+  if (r >= mu) return;
+  const uint32_t tt = threadIdx.x - 64;  // 0..191
+  const uint32_t h2 = L / 2, qs = L / 4;  // T_{r+1}(c) has h2 entries, round r+1 qs pairs
+  // the candidate tables: T(k, e) + c (T(k, e + h2) - T(k, e)), e < h2
+  for (uint32_t idx = tt; idx < (uint32_t)K * h2; idx += 192) {
+    const uint32_t k = idx / h2, e = idx % h2;
+    const Fe t0 = lds_fe(T(k, e));
+    const Fe dd = fe_submod(lds_fe(T(k, e + h2)), t0);
+    Fe u = t0;
+#pragma unroll
+    for (int c = 0; c < NH; ++c) {
+      lds_put(U(k, c, e), u);
+      if (c + 1 < NH) u = fe_addmod(u, dd);
+    }
+  }
+  bar_target += 3;
+  waves123_barrier(CTR, bar_target);
+  // lane slot (x, c) = tt mod 16; the 12 lanes of a slot stride over the pairs
+  const uint32_t x = tt & 3u, c = (tt >> 2) & 3u;
+  Fe acc = fe_zero();
+  if (x < (uint32_t)NH && c < (uint32_t)NH) {
+    for (uint32_t e = tt >> 4; e < qs; e += 12) {
+      auto get = [&](int t, Fe& u0, Fe& u1) __attribute__((always_inline)) {
+        u0 = lds_fe(U(t, c, e));
+        u1 = lds_fe(U(t, c, e + qs));
+      };
+      acc = fe_addmod(acc, mont(point_f<Gate>(get, x), lds_fe(eqrow + (qs + e) * NL)));
+    }
+  }
+  acc = fe_addmod(acc, shfl_xor_fe(acc, 16));
+  acc = fe_addmod(acc, shfl_xor_fe(acc, 32));
+  if ((tt & 63u) < 16) lds_put(RED3 + ((tt >> 6) * 16 + (tt & 15u)) * NL, acc);
+  bar_target += 3;
+  waves123_barrier(CTR, bar_target);
+  if (tt < 16) {
+    Fe sum = lds_fe(RED3 + tt * NL);
+    sum = fe_addmod(sum, lds_fe(RED3 + (16 + tt) * NL));
+    sum = fe_addmod(sum, lds_fe(RED3 + (32 + tt) * NL));
+    lds_put(HSP + tt * NL, sum);
+  }
+}
+
 template <class Gate>
 __device__ __forceinline__ void run_tail(const RoundArgs& a, const TabPtrs& dst, FinLds<Gate::D>& S, bool prefold) {
   constexpr int K = Gate::K;
@@ -876,11 +989,23 @@ __device__ __forceinline__ void run_tail(const RoundArgs& a, const TabPtrs& dst,
   constexpr uint32_t SL = NH <= 4 ? 4u : (NH <= 8 ? 8u : 16u);
   constexpr uint32_t PP = kBlock / SL;
   static_assert(PP <= 64 && SL * PP == kBlock, "point groups within a wave");
-  extern __shared__ uint32_t tail_lds[];  // [K][4 kTailQ][NL] tables, then [2 kTailQ][NL] eq rows
+  extern __shared__ uint32_t tail_lds[];  // tail_lds_words<Gate>(): [K][4 kTailQ][NL] tables, eq rows, ...
   constexpr uint32_t CAP = 4 * kTailQ;
   auto T = [&](int t, uint32_t e) -> uint32_t* { return tail_lds + ((uint32_t)t * CAP + e) * NL; };
   uint32_t* eqrow = tail_lds + (uint32_t)K * CAP * NL;
+  constexpr bool SPECT = TailSpec<Gate>::kOn;
+  // speculation: candidate tables SU(k, c, e), sums HSP[c 4 + x], per-wave
+  // sums RED3[w][c 4 + x], the barrier counter
+  uint32_t* SU = eqrow + CAP * NL;
+  auto U = [&](int t, uint32_t c, uint32_t e) -> uint32_t* {
+    return SU + (((uint32_t)t * (uint32_t)NH + c) * kTailQ + e) * NL;
+  };
+  uint32_t* HSP = SU + (uint32_t)(K * NH) * kTailQ * NL;
+  uint32_t* RED3 = HSP + 16 * NL;
+  uint32_t* CTR = RED3 + 3 * 16 * NL;
   const uint32_t tid = threadIdx.x;
+  if (SPECT && tid == 0) *CTR = 0;
+  uint32_t bar_target = 0;
   uint32_t L = 2 * (uint32_t)a.q;
   const Fe pa = prefold ? fe_to_mont(fe_vgpr(load_words_fe(a.ctrl->alpha[a.round - 2]))) : fe_zero();
   for (uint32_t idx = tid; idx < K * L; idx += blockDim.x) {
@@ -916,10 +1041,35 @@ __device__ __forceinline__ void run_tail(const RoundArgs& a, const TabPtrs& dst,
     } else if (tid == (uint32_t)NC) {
       lds_put(S.cm, fe_addmod(fe_vgpr(lds_fe(S.pc)), mont(ac, fe_vgpr(lds_fe(S.q2)))));
     }
+    // round r was evaluated during round r-1's hash: the weights L_c(alpha_{r-1})
+    const bool spec_r = SPECT && r >= a.round + 2 && r <= a.mu;
+    Fe lcr = fe_zero();
+    const uint32_t sx = tid & 3u, sc = (tid >> 2) & 3u;
+    if constexpr (SPECT) {
+      if (spec_r && tid >= 64 + 16 && tid < 64 + 16 + 16 && sx < (uint32_t)NH && sc < (uint32_t)NH)
+        lcr = lagrange_basis<Gate::D>(ac, sc);
+    }
     __syncthreads();
     L = h;
     if (r > a.mu) break;  // the final fold: entry 0 of each table is its opening
     const uint32_t q = L / 2;
+    if (spec_r) {
+      // lanes 80..95 (wave 1): H_r(x) R = sum_c L_c R H_r(x; c) R / R
+      if (tid >= 80 && tid < 96) {
+        Fe hv = fe_zero();
+        if (sx < (uint32_t)NH && sc < (uint32_t)NH) hv = mont(fe_vgpr(lcr), lds_fe(HSP + (tid & 15u) * NL));
+        hv = fe_addmod(hv, shfl_xor_fe(hv, 4));
+        hv = fe_addmod(hv, shfl_xor_fe(hv, 8));
+        if (sc == 0 && sx < (uint32_t)NH) lds_put(S.h[sx], hv);
+      }
+      __syncthreads();
+      auto side = [&]() __attribute__((always_inline)) {
+        if constexpr (SPECT) tail_speculate<Gate>(r, L, a.mu, T, U, eqrow, HSP, RED3, CTR, bar_target);
+      };
+      emit_round<Gate::D>(a.ctrl, r, S, a.evals_out + (uint64_t)(r - a.round) * Gate::NE * 8,
+                          a.alpha_out + (uint64_t)(r - a.round) * 8, a.check != 0, side);
+      continue;
+    }
     Fe c = fe_zero();
     if (x < (uint32_t)NH) {
       // uniform trip count; lanes past q evaluate pair e mod q (q is a power
@@ -943,8 +1093,11 @@ __device__ __forceinline__ void run_tail(const RoundArgs& a, const TabPtrs& dst,
       if (msk < q) c = fe_addmod(c, shfl_xor_fe(c, (int)msk));
     if (pp == 0 && x < (uint32_t)NH) lds_put(S.h[x], c);
     __syncthreads();
+    auto side = [&]() __attribute__((always_inline)) {
+      if constexpr (SPECT) tail_speculate<Gate>(r, L, a.mu, T, U, eqrow, HSP, RED3, CTR, bar_target);
+    };
     emit_round<Gate::D>(a.ctrl, r, S, a.evals_out + (uint64_t)(r - a.round) * Gate::NE * 8,
-                        a.alpha_out + (uint64_t)(r - a.round) * 8, a.check != 0);
+                        a.alpha_out + (uint64_t)(r - a.round) * 8, a.check != 0, side);
   }
   if (a.check && tid == 0) {
     // self-check of the final identity (Sec. 3.3, 3.4): G_mu(alpha_mu) =
