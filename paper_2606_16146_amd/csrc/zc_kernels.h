@@ -292,14 +292,40 @@ struct GateProd {
     Unroll<2, M + 1>::run(f);
     return fe_csub(fe_sub_plus(prod, e[M + 1], kP11), kP8);
   }
-  template <class Src>
-  __device__ static __forceinline__ void eval(const Src& src, const EqRows& er, Fe (&acc)[NH]) {
+  // From m = 3 on (NH >= 5 points), E multiplies s's pair (2 products)
+  // instead of every point's value (NH products), and o's part of the sum,
+  // sum_j E_j o_j(X) = sum_j E_j o_j[lo] + X sum_j E_j o_j[dl], is kept as
+  // two extra sums (2 products) that finalize() subtracts once per thread.
+  // The field elements summed are the same.
+  static constexpr bool kEqInS = M >= 3;
+  static constexpr int kExtraAcc = kEqInS ? 2 : 0;
+  template <int NA>
+  __device__ static __forceinline__ void finalize(Fe (&acc)[NA]) {
+    if constexpr (kEqInS) {
+      // acc[x] -= acc[NH] + x acc[NH+1]  (all < p: the sums were reduced)
+      auto f = [&](auto x) __attribute__((always_inline)) {
+        const Fe t = fe_reduce32(fe_add(acc[NH], fe_mul_small(acc[NH + 1], (uint32_t)x)));  // < p + 10p
+        acc[x] = fe_submod(acc[x], t);
+      };
+      Unroll<0, NH>::run(f);
+    }
+  }
+  template <class Src, int NA>
+  __device__ static __forceinline__ void eval(const Src& src, const EqRows& er, Fe (&acc)[NA]) {
     // s and w1 with strict differences (extensions at X <= m+1 < (m+2) p <= 10p,
     // so their product fits: 10*10), the other tables lazy (< 2(m+1) p <= 18p)
     Fe pr[NH], lo, dl, e;
     typename Src::Raw cur = src.issue(0);  // s
     typename Src::Raw nxt = src.issue(1);  // w1
     src.get(cur, 0, lo, dl);
+    Fe E;
+    if constexpr (kEqInS) {
+      // E s(X) = E s[lo] + X E s[dl], each product < p (mont), so the
+      // extensions keep the strict bound (X + 1) p
+      E = resolve_eq(er);
+      lo = fe_reduce2(fe_mul(E, lo));
+      dl = fe_reduce2(fe_mul(E, dl));
+    }
     auto f0 = [&](auto x) __attribute__((always_inline)) {
       pr[x] = (x == 0) ? lo : fe_add(pr[x > 0 ? x - 1 : 0], dl);
     };
@@ -320,14 +346,21 @@ struct GateProd {
       Unroll<0, NH>::run(fk);
     }
     src.getl(nxt, M + 1, lo, dl);  // o (< 18p): pr + 18p - o < 20p
-    const Fe E = resolve_eq(er);
-    e = lo;
-    auto fo = [&](auto x) __attribute__((always_inline)) {
-      const Fe f = fe_sub_plus(pr[x], e, kP18);
-      acc[x] = fe_add(acc[x], fe_mul(f, E));  // product < 2p (20*1)
-      e = fe_add(e, dl);
-    };
-    Unroll<0, NH>::run(fo);
+    if constexpr (kEqInS) {
+      auto fe = [&](auto x) __attribute__((always_inline)) { acc[x] = fe_add(acc[x], pr[x]); };  // pr < 2p
+      Unroll<0, NH>::run(fe);
+      acc[NH] = fe_add(acc[NH], fe_reduce2(fe_mul(E, lo)));          // < p (o[lo] < p)
+      acc[NH + 1] = fe_add(acc[NH + 1], fe_reduce2(fe_mul(E, dl)));  // < p (1*2 <= 128, then reduced)
+    } else {
+      E = resolve_eq(er);
+      e = lo;
+      auto fo = [&](auto x) __attribute__((always_inline)) {
+        const Fe f = fe_sub_plus(pr[x], e, kP18);
+        acc[x] = fe_add(acc[x], fe_mul(f, E));  // product < 2p (20*1)
+        e = fe_add(e, dl);
+      };
+      Unroll<0, NH>::run(fo);
+    }
   }
 };
 
@@ -762,13 +795,31 @@ __device__ __forceinline__ void emit_round(Ctrl* ctrl, uint32_t round, FinLds<D>
 // pair adds < 2p, so they stay < 2p + 32 * 2p < 128p.
 constexpr uint32_t kLazyPairs = 32;
 
+// Accumulators a gate's eval() keeps per thread: the NH point sums, plus
+// GateAcc<Gate>::kExtra of its own, which finalize() folds into them.
+template <class Gate, class = void>
+struct GateAcc {
+  static constexpr int kExtra = 0;
+  template <int NA>
+  __device__ static __forceinline__ void finalize(Fe (&)[NA]) {}
+};
+template <class Gate>
+struct GateAcc<Gate, std::void_t<decltype(Gate::kExtraAcc)>> {
+  static constexpr int kExtra = Gate::kExtraAcc;
+  template <int NA>
+  __device__ static __forceinline__ void finalize(Fe (&acc)[NA]) {
+    Gate::finalize(acc);
+  }
+};
+
 template <class Gate, bool FOLD>
 __device__ __forceinline__ void round_body(const RoundArgs& a, const TabPtrs& src, const TabPtrs& dst, uint32_t blk,
                                            uint32_t nblk) {
   constexpr int NH = Gate::NH;
-  Fe acc[NH];
+  constexpr int NA = NH + GateAcc<Gate>::kExtra;
+  Fe acc[NA];
   auto z = [&](auto x) __attribute__((always_inline)) { acc[x] = fe_zero(); };
-  Unroll<0, NH>::run(z);
+  Unroll<0, NA>::run(z);
   auto lower = [&](auto x) __attribute__((always_inline)) { acc[x] = fe_reduce128_to2(acc[x]); };
 
   {
@@ -804,12 +855,16 @@ __device__ __forceinline__ void round_body(const RoundArgs& a, const TabPtrs& sr
           Gate::eval(PairSrcT<true>{src, a.src_pitch, j, q}, er, acc);
         }
       }
-      Unroll<0, NH>::run(lower);
+      Unroll<0, NA>::run(lower);
     }
   }
   auto red = [&](auto x) __attribute__((always_inline)) { acc[x] = fe_reduce2(acc[x]); };  // < 2p after lower
-  Unroll<0, NH>::run(red);
-  const Fe tot = block_reduce<NH>(acc);
+  Unroll<0, NA>::run(red);
+  GateAcc<Gate>::finalize(acc);  // every acc[x] < p again
+  Fe pts[NH];
+  auto cp = [&](auto x) __attribute__((always_inline)) { pts[x] = acc[x]; };
+  Unroll<0, NH>::run(cp);
+  const Fe tot = block_reduce<NH>(pts);
   if (threadIdx.x < NH) store_words_fe(a.partials + ((uint64_t)blk * part_stride(NH) + threadIdx.x) * 8, tot);
 }
 
