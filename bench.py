@@ -392,7 +392,10 @@ def run_serve(name):
     its own r.  The plain serial form proves each request's window (copied
     out to a table of its own, outside the timed region) with zc_prove, timed
     with HIP events around each proof; every served result of every run is
-    compared byte for byte with it."""
+    compared byte for byte with it.  At each rho the same arrivals are also
+    fed to a plain first-come-first-served server (one proof at a time with
+    zc_prove_pitch, no batching), the throughput and latency a server without
+    the serving loop's policies would reach on that stream."""
     import numpy as np
     import torch
 
@@ -465,10 +468,15 @@ def run_serve(name):
         st = S.Server(slots=256).run(reqs)
         st.update({"rho": rho, "arrival_rate_per_s": rho / mean_t, "mismatches_vs_alone": mismatches(reqs)})
         bad += st["mismatches_vs_alone"] + st["errors"]
+        reqs = requests(arr)
+        fc = S.Server(slots=256, lanes=1, order="fcfs", fast_queue=len(specs)).run(reqs)
+        bad += mismatches(reqs) + fc["errors"]
+        st["plain_fcfs_same_arrivals"] = {k: fc[k] for k in ("points_per_s", "p50_ms", "p99_ms")}
         out["runs"].append(st)
         log(f"[bench] {name}: rho {rho}: {st['points_per_s'] / 1e6:.1f} M points/s, "
             f"p50 {st['p50_ms']:.2f} ms, p99 {st['p99_ms']:.2f} ms, errors {st['errors']}, "
-            f"mismatches {st['mismatches_vs_alone']}")
+            f"mismatches {st['mismatches_vs_alone']}; plain FCFS on the same arrivals "
+            f"{fc['points_per_s'] / 1e6:.1f} M points/s, p50 {fc['p50_ms']:.2f} ms")
     reqs = requests(np.zeros(len(specs)))
     st = S.Server(slots=256).run(reqs)
     st.update({"rho": "saturated", "mismatches_vs_alone": mismatches(reqs)})
@@ -479,9 +487,12 @@ def run_serve(name):
     log(f"[bench] {name}: saturated {st['points_per_s'] / 1e6:.1f} M points/s vs plain serial "
         f"{points / serial_s / 1e6:.1f} M points/s, p50 {st['p50_ms']:.2f} ms, p99 {st['p99_ms']:.2f} ms")
     out["parity_vs_alone"] = "bit-exact" if bad == 0 else "MISMATCH"
-    out["checked_vs_alone"] = f"all {len(specs)} requests in each of {len(out['runs'])} runs"
+    out["checked_vs_alone"] = (f"all {len(specs)} requests in each of {len(out['runs'])} served runs and "
+                               f"{len(cfg['rhos'])} plain FCFS runs")
     out["config"] = {"workload": name, "mu": [cfg["mu_lo"], cfg["mu_hi"]], "p_degree3": cfg["p_d3"],
                      "seed": cfg["seed"], "field": "BN254 Fr", "slots": 256,
+                     "policy": "fast path up to 16 waiting (4 lanes, shortest first, at most one mu >= 21 "
+                               "proof at a time), continuous batching beyond",
                      "inputs": f"one mu={top} instance per gate packed once into a device pool; request i reads "
                                f"its own window, rows [w_i 2^mu, (w_i+1) 2^mu) with w_i uniform (seeded), in "
                                f"place (pitch 2^{top}); its own r"}

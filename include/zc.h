@@ -123,6 +123,14 @@ int zc_unpack(const uint32_t* mont_planar, uint64_t pitch, uint32_t* canon, uint
 int zc_prove(const zc_shape* shape, const uint32_t* const* tables, const uint32_t* r, void* ws,
              uint32_t* round_evals, uint32_t* challenges, uint32_t* openings, hipStream_t stream);
 
+/* zc_prove on tables whose limb planes are `pitch` elements apart (each
+   table: uint32[8][pitch], the proof reading its first 2^mu entries), e.g. a
+   2^mu-row window of a larger packed table, read in place.  pitch = 0 means
+   2^mu (zc_prove); otherwise 2^mu <= pitch <= 2^30, else ZC_EINVAL.  Same
+   launches and output bytes as zc_prove on a copy of the window. */
+int zc_prove_pitch(const zc_shape* shape, const uint32_t* const* tables, uint64_t pitch, const uint32_t* r, void* ws,
+                   uint32_t* round_evals, uint32_t* challenges, uint32_t* openings, hipStream_t stream);
+
 /* zc_prove without a workspace argument, for callers that cannot allocate
    device memory (code under HIP graph capture, tight serving loops, hosts
    that forbid allocation).  Same launches, same output bytes as zc_prove.

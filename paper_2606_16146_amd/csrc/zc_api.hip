@@ -194,7 +194,7 @@ int check_tables(const Layout& L, const uint32_t* const* tables) {
 // finisher) is bracketed by ev[2(i-1)] and ev[2(i-1)+1] on the same stream.
 int prove_impl(const zc_shape* shape, const uint32_t* const* tables, const uint32_t* r, void* ws,
                uint32_t* round_evals, uint32_t* challenges, uint32_t* openings, hipStream_t stream,
-               hipEvent_t* ev) {
+               hipEvent_t* ev, uint64_t pitch = 0) {
   Layout L;
   int rc = make_layout(shape, &L);
   if (rc != ZC_OK) return rc;
@@ -202,6 +202,8 @@ int prove_impl(const zc_shape* shape, const uint32_t* const* tables, const uint3
   if (!r || !ws || !round_evals || !challenges || !openings || !aligned(ws, 256)) return ZC_EINVAL;
   const uint32_t mu = shape->mu;
   const uint64_t n = 1ull << mu;
+  if (pitch != 0 && (pitch < n || pitch > kMaxElems)) return ZC_EINVAL;
+  const uint64_t tp = pitch ? pitch : n;  // plane pitch of the caller's tables
   uint32_t* scratch = reinterpret_cast<uint32_t*>(bytes(ws) + L.scratch);
   const uint64_t half = n / 2;
 
@@ -224,7 +226,7 @@ int prove_impl(const zc_shape* shape, const uint32_t* const* tables, const uint3
       // round i-1 beside the speculative round i, then round r's finisher
       // with the tail (tables: the folded copies, T_{i-1} or T_{i-2})
       RoundArgs sa = round_args(shape, L, ws, i, round_evals, challenges);
-      sa.src_pitch = i <= 2 ? n : half;
+      sa.src_pitch = i <= 2 ? tp : half;
       sa.dst_pitch = half;
       if (ev && hipEventRecord(ev[2 * (i - 1)], stream) != hipSuccess) return ZC_EHIP;
       uint32_t blocks = 0;
@@ -262,8 +264,8 @@ int prove_impl(const zc_shape* shape, const uint32_t* const* tables, const uint3
     }
     RoundArgs a = round_args(shape, L, ws, i, round_evals, challenges);
     a.openings = openings;
-    a.src_pitch = i <= 2 ? n : half;
-    a.dst_pitch = i == 1 ? n : half;
+    a.src_pitch = i <= 2 ? tp : half;
+    a.dst_pitch = i == 1 ? tp : half;
     const TabPtrs& src = i <= 2 ? orig : fold;
     const TabPtrs& dst = i == 1 ? orig : fold;
     if (ev && hipEventRecord(ev[2 * (i - 1)], stream) != hipSuccess) return ZC_EHIP;
@@ -540,6 +542,11 @@ int zc_unpack(const uint32_t* mont_planar, uint64_t pitch, uint32_t* canon, uint
 int zc_prove(const zc_shape* shape, const uint32_t* const* tables, const uint32_t* r, void* ws,
              uint32_t* round_evals, uint32_t* challenges, uint32_t* openings, hipStream_t stream) {
   return prove_impl(shape, tables, r, ws, round_evals, challenges, openings, stream, nullptr);
+}
+
+int zc_prove_pitch(const zc_shape* shape, const uint32_t* const* tables, uint64_t pitch, const uint32_t* r, void* ws,
+                   uint32_t* round_evals, uint32_t* challenges, uint32_t* openings, hipStream_t stream) {
+  return prove_impl(shape, tables, r, ws, round_evals, challenges, openings, stream, nullptr, pitch);
 }
 
 int zc_prove_static(const zc_shape* shape, const uint32_t* const* tables, const uint32_t* r, uint32_t* round_evals,

@@ -14,6 +14,23 @@ a tile.  The loop
 * retires requests whose last step has completed on the device (HIP events),
   frees their workspace and slot, and records their completion time.
 At most `ahead` steps are in flight, so admission keeps up with arrivals.
+
+Fast path (`fast_queue` > 0, the default): while no step is running and at
+most `fast_queue` requests wait, waiting requests are proved whole with
+zc_prove (zc_prove_pitch for a window) instead of being stepped, up to
+`lanes` proofs at once, each on a stream of its own (all at the default
+priority).  A step runs every (gate, fold) group's round and finisher
+launches for one round of each admitted request, which at low concurrency
+costs a request several times its proof alone; zc_prove runs the
+single-proof schedule (lane-split and speculative rounds, the LDS tail in one
+launch).  Proofs on distinct streams share the GPU: a small proof's chain of
+short kernels runs in the gaps of a large proof's wide rounds rather than
+after it.  The fast path takes the waiting request with the fewest hypercube
+points (`order="sjf"`, shortest job first) unless the oldest has waited
+`max_wait_s`, or the oldest (`order="fcfs"`); requests of 2^big_mu points
+or more hold at most `big_lanes` lanes at once, so that the others stay free
+for small requests.  A queue longer than `fast_queue`, and arrivals while
+steps run, go to continuous batching.
 Outputs stay on the device.  Every request's bytes equal its zc_prove proof
 (each instance owns its workspace; sharing a launch changes nothing it
 computes).
@@ -47,6 +64,7 @@ class Request:
     outputs: tuple = ()
     ws: torch.Tensor | None = None
     err: int = 0
+    fast_path: bool = False     # proved whole by the fast path rather than stepped
     _dev_tables: list = field(default_factory=list)
 
     @property
@@ -70,9 +88,23 @@ def footprint(req: Request) -> int:
     return zc.workspace_bytes(s) + out + tabs
 
 
+_LANES: dict = {}
+
+
+def _lane_streams(dev: torch.device, n: int) -> list:
+    """Streams of `dev` at the default priority, created once per process and
+    reused by every server: [0] carries only the loop's error-word reads,
+    [1..n-1] are fast-path lanes beside the serving stream."""
+    have = _LANES.setdefault(dev.index if dev.index is not None else torch.cuda.current_device(), [])
+    while len(have) < max(n, 1):
+        have.append(torch.cuda.Stream(dev))
+    return have[:max(n, 1)]
+
+
 class Server:
     def __init__(self, slots: int = 256, mem_budget: int | None = None, ahead: int = 2, device="cuda",
-                 stream: torch.cuda.Stream | None = None):
+                 stream: torch.cuda.Stream | None = None, fast_queue: int = 16, order: str = "sjf",
+                 max_wait_s: float = 0.05, lanes: int = 4, big_mu: int | None = 21, big_lanes: int = 1):
         self.dev = torch.device(device)
         self.pool = zc.ServePool(slots, self.dev)
         self.slots = slots
@@ -82,15 +114,61 @@ class Server:
         self.mem_budget = mem_budget
         self.ahead = ahead
         self.stream = stream or torch.cuda.current_stream(self.dev)
+        if order not in ("sjf", "fcfs"):
+            raise ValueError(f"order must be 'sjf' or 'fcfs', not {order!r}")
+        if lanes < 1:
+            raise ValueError("lanes must be >= 1")
+        self.fast_queue = fast_queue
+        self.lanes = [self.stream] + _lane_streams(self.dev, lanes)[1:]
+        self.big_mu = big_mu          # requests with mu >= big_mu ...
+        self.big_lanes = big_lanes    # ... hold at most this many lanes at once
+        self.book = _lane_streams(self.dev, 1)[0]  # runs only the error-word reads
+        self.order = order
+        self.max_wait_s = max_wait_s
+
+    def _device_state(self, req: Request, stream: torch.cuda.Stream):
+        """Workspace and outputs of a request that runs on `stream`.  They come
+        from the serving stream's pool of the caching allocator whatever the
+        lane (one pool rather than one per lane, so blocks freed by one lane
+        serve the next request of any lane), marked as used on `stream`.  The
+        workspace is not cleared: zc_prove and serve admission reset its
+        control block."""
+        s = req.shape
+        with torch.cuda.stream(self.stream):
+            req.ws = torch.empty(zc.workspace_bytes(s), dtype=torch.uint8, device=self.dev)
+            req.outputs = zc.new_outputs(s, self.dev)
+        if stream is not self.stream:
+            for t in (req.ws, *req.outputs):
+                t.record_stream(stream)
+        if req.host_tables:
+            with torch.cuda.stream(stream):
+                req._dev_tables = [t.to(self.dev, non_blocking=True) for t in req.tables]
+        else:
+            req._dev_tables = req.tables
+
+    def _big(self, req: Request) -> bool:
+        return self.big_mu is not None and req.shape.mu >= self.big_mu
+
+    def _pick(self, waiting, now: float, allow_big: bool) -> int:
+        """Index in `waiting` of the request the fast path proves next, or -1."""
+        ok = [j for j in range(len(waiting)) if allow_big or not self._big(waiting[j])]
+        if not ok:
+            return -1
+        if self.order == "fcfs" or now - waiting[ok[0]].arrival >= self.max_wait_s:
+            return ok[0]
+        return min(ok, key=lambda j: (waiting[j].points, waiting[j].arrival))
+
+    def _prove_alone(self, req: Request, now: float, stream: torch.cuda.Stream):
+        """The fast path: the whole proof, single-proof schedule, on `stream`
+        (its workspace and outputs allocated in that stream's order)."""
+        self._device_state(req, stream)
+        zc.prove(req.shape, req._dev_tables, req.r, req.ws, outputs=req.outputs, stream=stream, pitch=req.pitch)
+        req.t_admit = now
+        req.fast_path = True
 
     def _admit(self, req: Request, slot: int, now: float):
         s = req.shape
-        req.ws = zc.new_workspace(s, self.dev)
-        req.outputs = zc.new_outputs(s, self.dev)
-        if req.host_tables:
-            req._dev_tables = [t.to(self.dev, non_blocking=True) for t in req.tables]
-        else:
-            req._dev_tables = req.tables
+        self._device_state(req, self.stream)
         ev, al, op = req.outputs
         req._tabarr = (ctypes.c_void_p * len(req._dev_tables))(*[t.data_ptr() for t in req._dev_tables])
         req._inst = zc.Instance(s, ctypes.cast(req._tabarr, ctypes.c_void_p), req.r.data_ptr(),
@@ -104,17 +182,62 @@ class Server:
         pending = collections.deque(sorted(requests, key=lambda q: q.arrival))
         waiting: collections.deque = collections.deque()
         active: list = []           # [req, slot, round, last]
-        in_flight: collections.deque = collections.deque()  # (event, [finished reqs])
+        in_flight: list = []        # [event, [reqs it completes], lane or -1 for a step], oldest first
+        lane_busy = [0] * len(self.lanes)
+        big_running = 0
         free_slots = list(range(self.slots - 1, -1, -1))
         mem_used = 0
         steps = 0
+        fast_n = 0
+
+        def retire(entry):
+            nonlocal mem_used, big_running
+            ev, done, lane = entry
+            ev.synchronize()
+            t = time.perf_counter() - t0
+            if lane >= 0:
+                lane_busy[lane] -= 1
+                big_running -= sum(self._big(q) for q in done)
+            for req in done:
+                req.t_done = t
+                mem_used -= req._bytes
+                # the error word, read now on a stream that runs nothing else (so the
+                # read is not queued behind a proof); the workspace is released after it
+                with torch.cuda.stream(self.book):
+                    self.book.wait_event(ev)
+                    req.err = int(req.ws[:4].view(torch.int32).cpu()[0])
+                req.ws = None
+                req._dev_tables = []
+
         with torch.cuda.stream(self.stream):
             t0 = time.perf_counter()
             while pending or waiting or active or in_flight:
                 now = time.perf_counter() - t0
                 while pending and pending[0].arrival <= now:
                     waiting.append(pending.popleft())
-                while waiting and free_slots:
+                launched = False
+                fast = not active and 0 < len(waiting) <= self.fast_queue
+                depth = 2 if len(self.lanes) == 1 else 1
+                while fast and waiting:
+                    lane = min(range(len(self.lanes)), key=lambda j: lane_busy[j])
+                    if lane_busy[lane] >= depth:
+                        break
+                    pick = self._pick(waiting, now, big_running < self.big_lanes)
+                    if pick < 0 or (mem_used + footprint(waiting[pick]) > self.mem_budget and in_flight):
+                        break
+                    req = waiting[pick]
+                    del waiting[pick]
+                    self._prove_alone(req, now, self.lanes[lane])
+                    req._bytes = footprint(req)
+                    mem_used += req._bytes
+                    ev = torch.cuda.Event()
+                    ev.record(self.lanes[lane])
+                    lane_busy[lane] += 1
+                    big_running += self._big(req)
+                    in_flight.append([ev, [req], lane])
+                    fast_n += 1
+                    launched = True
+                while waiting and free_slots and not fast:
                     need = footprint(waiting[0])
                     if mem_used + need > self.mem_budget and (active or in_flight):
                         break  # admit when memory frees up (an idle server admits anything)
@@ -129,32 +252,26 @@ class Server:
                     ev = torch.cuda.Event()
                     ev.record(self.stream)
                     steps += 1
+                    launched = True
                     done = [a for a in active if a[2] == a[3]]
                     for a in active:
                         a[2] += 1
                     active = [a for a in active if a[2] <= a[3]]
                     for a in done:  # later launches are ordered after this step on the stream
                         free_slots.append(a[1])
-                    in_flight.append((ev, [a[0] for a in done]))
-                # retire completed steps; block when too far ahead or when idle otherwise
-                while in_flight and (in_flight[0][0].query() or len(in_flight) > self.ahead or
-                                     (not active and not waiting)):
-                    ev, done = in_flight.popleft()
-                    ev.synchronize()
-                    t = time.perf_counter() - t0
-                    for req in done:
-                        req.t_done = t
-                        mem_used -= req._bytes
-                        # keep the error word (a stream-ordered copy), release the workspace
-                        req._err_word = req.ws[:4].clone()
-                        req.ws = None
-                        req._dev_tables = []
-                if not active and not in_flight and not waiting and pending:
+                    in_flight.append([ev, [a[0] for a in done], -1])
+                # retire completed work; block on the oldest step when too many are in flight
+                for entry in [e for e in in_flight if e[0].query()]:
+                    in_flight.remove(entry)
+                    retire(entry)
+                while sum(1 for e in in_flight if e[2] < 0) > self.ahead:
+                    entry = next(e for e in in_flight if e[2] < 0)
+                    in_flight.remove(entry)
+                    retire(entry)
+                if not launched and not in_flight and not waiting and pending:
                     time.sleep(max(0.0, min(pending[0].arrival - (time.perf_counter() - t0), 0.001)))
             wall = time.perf_counter() - t0
         torch.cuda.synchronize(self.dev)
-        for req in requests:
-            req.err = int(req._err_word.view(torch.int32)[0].item())
         lat = sorted(q.latency for q in requests)
         pts = sum(q.points for q in requests)
 
@@ -167,4 +284,5 @@ class Server:
             by_mu[str(mu)] = {"n": len(lm), "p50_ms": pct(lm, 50) * 1e3, "p99_ms": pct(lm, 99) * 1e3}
         return {"requests": len(requests), "points": pts, "wall_s": wall, "points_per_s": pts / wall,
                 "p50_ms": pct(lat, 50) * 1e3, "p99_ms": pct(lat, 99) * 1e3, "steps": steps,
+                "fast_path_requests": fast_n,
                 "errors": sum(1 for q in requests if q.err != 0), "by_mu": by_mu}

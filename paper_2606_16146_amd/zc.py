@@ -50,6 +50,7 @@ _SIGS = {
     "zc_pack": (ctypes.c_int, [_VP, _VP, ctypes.c_uint64, _VP, _VP]),
     "zc_unpack": (ctypes.c_int, [_VP, ctypes.c_uint64, _VP, ctypes.c_uint64, _VP]),
     "zc_prove": (ctypes.c_int, [ctypes.POINTER(Shape), _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "zc_prove_pitch": (ctypes.c_int, [ctypes.POINTER(Shape), _VP, ctypes.c_uint64, _VP, _VP, _VP, _VP, _VP, _VP]),
     "zc_prove_static": (ctypes.c_int, [ctypes.POINTER(Shape), _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "zc_round": (ctypes.c_int, [ctypes.POINTER(Shape), _VP, _VP, _VP, ctypes.c_uint32, _VP, _VP, _VP]),
     "zc_fold": (ctypes.c_int, [ctypes.POINTER(Shape), _VP, _VP, ctypes.c_uint32, _VP]),
@@ -170,13 +171,20 @@ def new_outputs(s: Shape, device="cuda"):
     return evals, alphas, openings
 
 
-def prove(s: Shape, tables, r: torch.Tensor, ws: torch.Tensor, outputs=None, stream=None):
-    """Whole proof; returns (round_evals, challenges, openings) device tensors."""
+def prove(s: Shape, tables, r: torch.Tensor, ws: torch.Tensor, outputs=None, stream=None, pitch: int = 0):
+    """Whole proof; returns (round_evals, challenges, openings) device tensors.
+    pitch != 0: the tables' limb planes are `pitch` elements apart
+    (zc_prove_pitch), e.g. 2^mu-row windows of larger packed tables."""
     evals, alphas, openings = outputs if outputs is not None else new_outputs(s, r.device)
     arr = _table_array(tables)
-    rc = lib().zc_prove(ctypes.byref(s), arr, _ptr(r), _ptr(ws), _ptr(evals), _ptr(alphas),
-                        _ptr(openings), _stream(stream))
-    _check(rc, "zc_prove")
+    if pitch:
+        rc = lib().zc_prove_pitch(ctypes.byref(s), arr, pitch, _ptr(r), _ptr(ws), _ptr(evals), _ptr(alphas),
+                                  _ptr(openings), _stream(stream))
+        _check(rc, "zc_prove_pitch")
+    else:
+        rc = lib().zc_prove(ctypes.byref(s), arr, _ptr(r), _ptr(ws), _ptr(evals), _ptr(alphas),
+                            _ptr(openings), _stream(stream))
+        _check(rc, "zc_prove")
     return evals, alphas, openings
 
 

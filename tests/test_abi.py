@@ -66,6 +66,10 @@ def test_host_validation_rejects_bad_arguments_without_gpu():
     # misaligned workspace
     assert h.zc_prove(ctypes.byref(s), tabs, fake, ctypes.c_void_p(0x1004), fake, fake, fake,
                       None) == zc.ZC_EINVAL
+    # zc_prove_pitch: plane pitch below 2^mu or above 2^30
+    assert h.zc_prove_pitch(ctypes.byref(s), tabs, 8, fake, fake, fake, fake, fake, None) == zc.ZC_EINVAL
+    assert h.zc_prove_pitch(ctypes.byref(s), tabs, (1 << 30) + 1, fake, fake, fake, fake, fake,
+                            None) == zc.ZC_EINVAL
     assert h.zc_pack(None, fake, 4, fake, None) == zc.ZC_EINVAL
     assert h.zc_unpack(fake, 2, fake, 4, None) == zc.ZC_EINVAL  # pitch < n
     # element indices must stay below 2^30 (32-bit byte offsets in the kernels)

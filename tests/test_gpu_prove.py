@@ -238,3 +238,38 @@ def test_large_mu_multichunk_lazy_sums_match_c_oracle(zc, mu, gate, m):
     assert (res["evals"] == ora["evals"]).all()
     assert (res["alphas"] == ora["alphas"]).all()
     assert (res["openings"] == ora["openings"]).all()
+
+
+@pytest.mark.parametrize("mu,gate,m,top,win,extra", [
+    (17, 0, 0, 18, 1, 96),   # speculative rounds, plane pitch not a power of two
+    (12, 1, 8, 14, 3, 0),    # degree 9, window 3 of a mu = 14 pool
+    (9, 2, 34, 10, 1, 5),    # a Table 1 polynomial, odd pitch
+    (1, 0, 0, 3, 3, 0),      # one round, the last window
+])
+def test_prove_pitch_on_a_window_matches_c_oracle_and_copy(zc, mu, gate, m, top, win, extra):
+    """zc_prove_pitch reads a 2^mu-row window of larger packed tables in place
+    (planes `pitch` apart): the same bytes as zc_prove on a copy of the window
+    and as the C oracle on those rows; the pool is left untouched."""
+    base = I.make_instance(81, mu, top, gate, m, workers=8)
+    s = zc.shape(mu, gate, m)
+    ws = zc.new_workspace(s)
+    pitch = (1 << top) + extra
+    pool = []
+    for t in base.tables:
+        wide = torch.zeros((8, pitch), dtype=torch.uint32, device="cuda")
+        wide[:, :1 << top] = zc.pack(dev(t), ws)
+        pool.append(wide)
+    before = [p.clone() for p in pool]
+    off, n = win << mu, 1 << mu
+    r = I.draw_elements(82, mu, I.R_TABLE_ID, mu)
+    got = zc.prove(s, [p[:, off:off + n] for p in pool], dev(r), ws, pitch=pitch)
+    got = [o.cpu().numpy() for o in got]
+    assert zc.read_error(ws) == 0
+    canon = np.ascontiguousarray(base.tables[:, off:off + n])
+    ora = C.prove(mu, gate, m, canon, r)
+    assert np.array_equal(got[0], ora["evals"]) and np.array_equal(got[1], ora["alphas"])
+    assert np.array_equal(got[2], ora["openings"])
+    ws2 = zc.new_workspace(s)
+    copy = zc.prove(s, [p[:, off:off + n].contiguous() for p in pool], dev(r), ws2)
+    assert all(np.array_equal(a, b.cpu().numpy()) for a, b in zip(got, copy))
+    assert all(torch.equal(a, b) for a, b in zip(pool, before))

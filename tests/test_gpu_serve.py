@@ -47,10 +47,18 @@ SPECS = [  # (mu, gate, m, arrival seconds): staggered, overlapping, several gat
 ]
 
 
-def test_served_results_equal_alone():
+@pytest.mark.parametrize("fast_queue,order", [(0, "sjf"), (2, "fcfs"), (64, "sjf")])
+def test_served_results_equal_alone(fast_queue, order):
+    """fast_queue 0: every request stepped; 64: every request proved whole by
+    the fast path (one at a time, shortest first); 2: both, as the queue
+    length changes."""
     reqs, insts = _requests(SPECS)
-    stats = S.Server(slots=8).run(reqs)
+    stats = S.Server(slots=8, fast_queue=fast_queue, order=order).run(reqs)
     assert stats["errors"] == 0 and stats["requests"] == len(SPECS)
+    nfast = sum(q.fast_path for q in reqs)
+    assert nfast == stats["fast_path_requests"]
+    assert nfast == {0: 0, 64: len(SPECS)}.get(fast_queue, nfast)
+    assert stats["steps"] == 0 or fast_queue != 64
     for q, inst in zip(reqs, insts):
         print(f"request {q.rid} mu={inst.mu} gate={inst.gate} m={inst.m}", flush=True)
         got = [o.cpu().numpy() for o in q.outputs]
@@ -62,7 +70,7 @@ def test_tight_slots_and_memory_still_correct():
     reqs, insts = _requests(SPECS[:6], seed=32)
     # two slots and a budget below two footprints: requests wait for admission
     budget = max(S.footprint(q) for q in reqs) + 1
-    stats = S.Server(slots=2, mem_budget=budget).run(reqs)
+    stats = S.Server(slots=2, mem_budget=budget, fast_queue=1).run(reqs)
     assert stats["errors"] == 0
     for q, inst in zip(reqs, insts):
         got = [o.cpu().numpy() for o in q.outputs]
@@ -82,9 +90,11 @@ def test_served_large_mix_with_pool_windows_matches_c_oracle():
     """mu 17-20 requests of the degree-3 and degree-9 gates among small ones of
     other gates, arriving staggered.  Half of them read a 2^mu-aligned window
     of a shared mu = 20 packed pool in place (pitch 2^20; every row of the
-    pool satisfies its gate), the others own their tables.  Each result is
-    compared with the C oracle on the same rows and with zc_prove alone."""
-    dev_ = torch.device("cuda:0")
+    pool satisfies its gate), the others own their tables.  The stream is
+    served twice, all stepped (fast_queue 0) and with the fast path proving
+    whole while the queue is short (fast_queue 2, windows through
+    zc_prove_pitch); each result is compared with the C oracle on the same
+    rows and with zc_prove alone."""
     gates = [(0, 0), (1, 8)]
     base = {g: I.make_instance(44, 7 + gi, 20, g[0], g[1], workers=8) for gi, g in enumerate(gates)}
     scratch = zc.new_workspace(zc.shape(4, 0))
@@ -93,35 +103,71 @@ def test_served_large_mix_with_pool_windows_matches_c_oracle():
     mix = [(20, 0, 0, 0.0, 0), (18, 1, 8, 0.0, 3), (9, 1, 4, 0.0005, None), (17, 0, 0, 0.001, None),
            (19, 1, 8, 0.001, None), (12, 0, 0, 0.002, 5), (20, 1, 8, 0.002, 0), (6, 2, 34, 0.003, None),
            (17, 1, 8, 0.003, 6), (14, 0, 0, 0.004, 2), (18, 0, 0, 0.004, 1), (11, 1, 2, 0.005, None)]
-    reqs, refs = [], []
+    refs = []
     for i, (mu, g, m, arr, win) in enumerate(mix):
-        s = zc.shape(mu, g, m)
         r = I.draw_elements(45, i, I.R_TABLE_ID, mu)
         if win is not None:
             off, n = win << mu, 1 << mu
-            canon = base[(g, m)].tables[:, off:off + n]
-            tabs = [t[:, off:off + n] for t in pool[(g, m)]]
-            reqs.append(S.Request(i, arr, s, tabs, dev(r), tile=i % 3, pitch=1 << 20, shared_tables=True))
+            canon = np.ascontiguousarray(base[(g, m)].tables[:, off:off + n])
         else:
-            inst = I.make_instance(46, i, mu, g, m)
-            canon = inst.tables
-            reqs.append(S.Request(i, arr, s, [zc.pack(dev(t), scratch) for t in canon], dev(r), tile=i % 3))
-        refs.append((np.ascontiguousarray(canon), r))
-    torch.cuda.synchronize()
-    stats = S.Server(slots=6).run(reqs)
-    assert stats["errors"] == 0 and stats["requests"] == len(mix)
-    for q, (canon, r) in zip(reqs, refs):
-        mu, g, m = q.shape.mu, q.shape.gate, q.shape.m
-        print(f"request {q.rid} mu={mu} gate={g} m={m} pitch={q.pitch}", flush=True)
-        got = [o.cpu().numpy() for o in q.outputs]
+            canon = I.make_instance(46, i, mu, g, m).tables
         ora = C.prove(mu, g, m, canon, r)
-        assert np.array_equal(got[0], ora["evals"]) and np.array_equal(got[1], ora["alphas"])
-        assert np.array_equal(got[2], ora["openings"])
         alone = _alone(I.Instance(0, 0, mu, g, m, canon, r))
-        assert all(np.array_equal(a, b) for a, b in zip(got, alone))
+        assert np.array_equal(alone[0], ora["evals"]) and np.array_equal(alone[1], ora["alphas"])
+        assert np.array_equal(alone[2], ora["openings"])
+        refs.append((canon, r, alone))
+
+    def requests():
+        reqs = []
+        for i, (mu, g, m, arr, win) in enumerate(mix):
+            s, (canon, r, _) = zc.shape(mu, g, m), refs[i]
+            if win is not None:
+                off, n = win << mu, 1 << mu
+                tabs = [t[:, off:off + n] for t in pool[(g, m)]]
+                reqs.append(S.Request(i, arr, s, tabs, dev(r), tile=i % 3, pitch=1 << 20, shared_tables=True))
+            else:
+                reqs.append(S.Request(i, arr, s, [zc.pack(dev(t), scratch) for t in canon], dev(r),
+                                      tile=i % 3))
+        torch.cuda.synchronize()
+        return reqs
+
+    policies = [dict(fast_queue=0), dict(fast_queue=2),
+                dict(fast_queue=16, lanes=3, big_mu=19, big_lanes=1)]  # every request on the fast path
+    for pol in policies:
+        reqs = requests()
+        stats = S.Server(slots=6, **pol).run(reqs)
+        assert stats["errors"] == 0 and stats["requests"] == len(mix)
+        assert (stats["fast_path_requests"] == 0) == (pol["fast_queue"] == 0)
+        for q, (_, _, alone) in zip(reqs, refs):
+            print(f"policy {pol} request {q.rid} mu={q.shape.mu} gate={q.shape.gate} "
+                  f"m={q.shape.m} pitch={q.pitch} fast={q.fast_path}", flush=True)
+            got = [o.cpu().numpy() for o in q.outputs]
+            assert all(np.array_equal(a, b) for a, b in zip(got, alone))
     # the admission footprint counts a request's own tables, not a shared pool's
     for q in reqs:
         k, n = zc.table_count(q.shape), 1 << q.shape.mu
         own = 0 if q.shared_tables else k * n * 32
         outs = (q.shape.mu * (zc.degree(q.shape) + 2) + k + 1 + q.shape.mu) * 32
         assert S.footprint(q) == zc.workspace_bytes(q.shape) + outs + own
+
+
+@pytest.mark.parametrize("fast_queue", [0, 16])
+def test_device_errors_reach_their_own_request(fast_queue):
+    """A request whose r holds an element >= p is flagged (ZC_ERANGE) by the
+    device; the loop reports it for that request only, stepped or proved on
+    a fast-path lane."""
+    reqs, insts = _requests(SPECS[:8], seed=34)
+    bad = {2, 5}
+    for i in bad:
+        r = np.array(insts[i].r, dtype=np.uint32)
+        r[0, :] = 0xFFFFFFFF
+        reqs[i].r = dev(r)
+    torch.cuda.synchronize()
+    stats = S.Server(slots=4, fast_queue=fast_queue, lanes=3).run(reqs)
+    assert stats["errors"] == len(bad)
+    for q, inst in zip(reqs, insts):
+        print(f"request {q.rid} err={q.err} fast={q.fast_path}", flush=True)
+        assert q.err == (zc.ZC_ERANGE if q.rid in bad else 0)
+        if q.rid not in bad:
+            got = [o.cpu().numpy() for o in q.outputs]
+            assert all(np.array_equal(a, b) for a, b in zip(got, _alone(inst)))
