@@ -380,6 +380,47 @@ def run_batch(name, steps, warmup, tune=True):
     return res
 
 
+def queue_model_p50(arrivals, service, policy):
+    """Median latency of one ideal server fed `arrivals` (sorted, seconds)
+    with job sizes `service` (seconds, each job's time alone), no overheads:
+    "fcfs" one job at a time in arrival order; "ps" processor sharing (every
+    job present progresses at 1/n of the rate); "srpt" preemptive shortest
+    remaining work first.  Event-driven and exact for these models."""
+    n = len(arrivals)
+    done = [0.0] * n
+    if policy == "fcfs":
+        free = 0.0
+        for j in range(n):
+            free = max(arrivals[j], free) + service[j]
+            done[j] = free
+    else:
+        rem = list(service)
+        active, t, i = [], 0.0, 0
+        while i < n or active:
+            if not active:
+                t = max(t, arrivals[i])
+            while i < n and arrivals[i] <= t:
+                active.append(i)
+                i += 1
+            nxt = arrivals[i] if i < n else float("inf")
+            if policy == "ps":
+                k = len(active)
+                j = min(active, key=lambda a: rem[a])
+                dt = min(rem[j] * k, nxt - t)
+                for a in active:
+                    rem[a] -= dt / k
+            else:
+                j = min(active, key=lambda a: (rem[a], a))
+                dt = min(rem[j], nxt - t)
+                rem[j] -= dt
+            t += dt
+            for a in [a for a in active if rem[a] <= 1e-15]:
+                done[a] = t
+                active.remove(a)
+    lat = sorted(d - a for d, a in zip(done, arrivals))
+    return lat[(n - 1) // 2] if n % 2 else 0.5 * (lat[n // 2 - 1] + lat[n // 2])
+
+
 def run_serve(name):
     """The served stream: Poisson arrivals at rho x the plain serial service
     rate, plus one saturated run (every request waiting at t = 0), against
@@ -467,6 +508,9 @@ def run_serve(name):
         reqs = requests(arr)
         st = S.Server(slots=256).run(reqs)
         st.update({"rho": rho, "arrival_rate_per_s": rho / mean_t, "mismatches_vs_alone": mismatches(reqs)})
+        # the same arrivals and the requests' own times alone through ideal one-server models
+        st["ideal_server_p50_ms"] = {pol: 1e3 * queue_model_p50([float(a) for a in arr], plain_t, pol)
+                                     for pol in ("fcfs", "ps", "srpt")}
         bad += st["mismatches_vs_alone"] + st["errors"]
         reqs = requests(arr)
         fc = S.Server(slots=256, lanes=1, order="fcfs", fast_queue=len(specs)).run(reqs)
