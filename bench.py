@@ -535,8 +535,9 @@ def run_serve(name):
                                f"{len(cfg['rhos'])} plain FCFS runs")
     out["config"] = {"workload": name, "mu": [cfg["mu_lo"], cfg["mu_hi"]], "p_degree3": cfg["p_d3"],
                      "seed": cfg["seed"], "field": "BN254 Fr", "slots": 256,
-                     "policy": "fast path up to 16 waiting (4 lanes, shortest first, at most one mu >= 21 "
-                               "proof at a time), continuous batching beyond",
+                     "policy": "fast path up to 16 waiting (4 streams, shortest first, at most one mu >= 21 "
+                               "proof at a time, launched with ZC_FLAG_SHARED_GPU grids), continuous "
+                               "batching beyond",
                      "inputs": f"one mu={top} instance per gate packed once into a device pool; request i reads "
                                f"its own window, rows [w_i 2^mu, (w_i+1) 2^mu) with w_i uniform (seeded), in "
                                f"place (pitch 2^{top}); its own r"}

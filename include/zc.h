@@ -63,7 +63,15 @@ enum {
      checks G_mu(alpha_mu) = f_M(openings) eq_r(alpha).  A failure is stored
      as ZC_ECLAIM (zc_read_error); the outputs are unchanged.  Costs a
      Lagrange evaluation per round on an otherwise idle lane. */
-  ZC_FLAG_CHECK_CLAIMS = 1
+  ZC_FLAG_CHECK_CLAIMS = 1,
+  /* The GPU is shared with other streams (e.g. several proofs at once):
+     thread-per-pair round kernels are launched with up to 2048 blocks of at
+     least 2 pairs a thread, instead of one generation of blocks resident for
+     the whole round, so that compute units come free during a round for
+     other streams' kernels.  The proof's bytes do not change; alone, a large
+     proof takes a few percent longer.  zc_prove / zc_prove_pitch /
+     zc_prove_static only (batches and serving size their own grids). */
+  ZC_FLAG_SHARED_GPU = 2
 };
 
 typedef enum {

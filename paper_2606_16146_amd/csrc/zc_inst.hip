@@ -52,8 +52,15 @@ template <class Gate>
 struct ServeFinishTag {};
 
 // Grid of a round kernel: enough blocks for the work, at most one resident
-// generation (CUs x resident blocks per CU) and at most kMaxBlocks.
-inline uint32_t round_grid(uint64_t blocks_for_work, int per_cu, int* rc) {
+// generation (CUs x resident blocks per CU) and at most kMaxBlocks.  With
+// `share` (ZC_FLAG_SHARED_GPU) a round may use more generations, down to
+// kSharePairs pairs per thread, still at most kMaxBlocks: shorter-lived
+// blocks, so that compute units come free during the round for the kernels
+// of other streams (the sums are exact, so the bytes do not change).  Each
+// generation costs a block start and a block reduction; kSharePairs keeps
+// that overhead to a few percent of the round.
+constexpr uint64_t kSharePairs = 2;
+inline uint32_t round_grid(uint64_t blocks_for_work, int per_cu, int* rc, bool share = false) {
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) {
@@ -61,6 +68,8 @@ inline uint32_t round_grid(uint64_t blocks_for_work, int per_cu, int* rc) {
     return 0;
   }
   uint64_t cap = (uint64_t)cus * (uint64_t)per_cu;
+  if (share && (blocks_for_work + kSharePairs - 1) / kSharePairs > cap)
+    cap = (blocks_for_work + kSharePairs - 1) / kSharePairs;
   if (cap > (uint64_t)kMaxBlocks) cap = kMaxBlocks;
   if (blocks_for_work < 1) blocks_for_work = 1;
   return (uint32_t)(blocks_for_work < cap ? blocks_for_work : cap);
@@ -79,7 +88,7 @@ int launch_round(bool fold, RoundKind kind, RoundArgs a, const TabPtrs& src, con
                             : reinterpret_cast<const void*>(&k_round<Gate, false>);
     const int per_cu = fold ? resident_blocks<RoundTag<Gate, true, false>>(kern)
                             : resident_blocks<RoundTag<Gate, false, false>>(kern);
-    blocks = round_grid((a.q + kBlock - 1) / kBlock, per_cu, &rc);
+    blocks = round_grid((a.q + kBlock - 1) / kBlock, per_cu, &rc, a.share != 0);
     if (rc) return rc;
     if (fold)
       hipLaunchKernelGGL((k_round<Gate, true>), dim3(blocks), dim3(kBlock), 0, st, a, src, dst);
@@ -119,7 +128,7 @@ int launch_spec(ZC_SPEC_ARGS) {
     if (step == kSpecRoundOnly) {
       const void* kern = reinterpret_cast<const void*>(&k_round<Gate, true>);
       const int per_cu = resident_blocks<RoundTag<Gate, true, false>>(kern);
-      const uint32_t b = round_grid((sa.q + kBlock - 1) / kBlock, per_cu, &rc);
+      const uint32_t b = round_grid((sa.q + kBlock - 1) / kBlock, per_cu, &rc, sa.share != 0);
       if (rc) return rc;
       hipLaunchKernelGGL((k_round<Gate, true>), dim3(b), dim3(kBlock), 0, st, sa, src, dst);
       *blocks = b;

@@ -551,6 +551,7 @@ struct RoundArgs {
   uint32_t* openings;          // tail only: (k+1) x 8 canonical
   EqTabs eq;
   uint32_t check;              // 1: the verifier's claim checks on the device (ZC_FLAG_CHECK_CLAIMS)
+  uint32_t share;              // host only: round grids sized for a shared GPU (ZC_FLAG_SHARED_GPU)
 };
 
 // Montgomery product reduced below p.

@@ -29,7 +29,9 @@ after it.  The fast path takes the waiting request with the fewest hypercube
 points (`order="sjf"`, shortest job first) unless the oldest has waited
 `max_wait_s`, or the oldest (`order="fcfs"`); requests of 2^big_mu points
 or more hold at most `big_lanes` lanes at once, so that the others stay free
-for small requests.  A queue longer than `fast_queue`, and arrivals while
+for small requests, and (`share_big`) run with ZC_FLAG_SHARED_GPU grids,
+whose shorter-lived blocks free compute units for the small proofs' kernels
+during a large round.  A queue longer than `fast_queue`, and arrivals while
 steps run, go to continuous batching.
 Outputs stay on the device.  Every request's bytes equal its zc_prove proof
 (each instance owns its workspace; sharing a launch changes nothing it
@@ -104,7 +106,8 @@ def _lane_streams(dev: torch.device, n: int) -> list:
 class Server:
     def __init__(self, slots: int = 256, mem_budget: int | None = None, ahead: int = 2, device="cuda",
                  stream: torch.cuda.Stream | None = None, fast_queue: int = 16, order: str = "sjf",
-                 max_wait_s: float = 0.05, lanes: int = 4, big_mu: int | None = 21, big_lanes: int = 1):
+                 max_wait_s: float = 0.05, lanes: int = 4, big_mu: int | None = 21, big_lanes: int = 1,
+                 share_big: bool = True):
         self.dev = torch.device(device)
         self.pool = zc.ServePool(slots, self.dev)
         self.slots = slots
@@ -122,6 +125,7 @@ class Server:
         self.lanes = [self.stream] + _lane_streams(self.dev, lanes)[1:]
         self.big_mu = big_mu          # requests with mu >= big_mu ...
         self.big_lanes = big_lanes    # ... hold at most this many lanes at once
+        self.share_big = share_big and lanes > 1  # ... with ZC_FLAG_SHARED_GPU grids
         self.book = _lane_streams(self.dev, 1)[0]  # runs only the error-word reads
         self.order = order
         self.max_wait_s = max_wait_s
@@ -162,7 +166,10 @@ class Server:
         """The fast path: the whole proof, single-proof schedule, on `stream`
         (its workspace and outputs allocated in that stream's order)."""
         self._device_state(req, stream)
-        zc.prove(req.shape, req._dev_tables, req.r, req.ws, outputs=req.outputs, stream=stream, pitch=req.pitch)
+        s = req.shape
+        if self.share_big and self._big(req):
+            s = zc.shape(s.mu, s.gate, s.m, s.flags | zc.ZC_FLAG_SHARED_GPU)
+        zc.prove(s, req._dev_tables, req.r, req.ws, outputs=req.outputs, stream=stream, pitch=req.pitch)
         req.t_admit = now
         req.fast_path = True
 

@@ -273,3 +273,19 @@ def test_prove_pitch_on_a_window_matches_c_oracle_and_copy(zc, mu, gate, m, top,
     copy = zc.prove(s, [p[:, off:off + n].contiguous() for p in pool], dev(r), ws2)
     assert all(np.array_equal(a, b.cpu().numpy()) for a, b in zip(got, copy))
     assert all(torch.equal(a, b) for a, b in zip(pool, before))
+
+
+@pytest.mark.parametrize("mu,gate,m", [(20, 0, 0), (21, 1, 8), (17, 0, 0), (12, 2, 34)])
+def test_shared_gpu_grids_give_the_same_bytes(zc, mu, gate, m):
+    """ZC_FLAG_SHARED_GPU launches the thread-per-pair rounds with up to 2048
+    short-lived blocks instead of one resident generation; the block sums
+    are exact field additions, so every output byte is the same."""
+    inst = I.make_instance(83, mu, mu, gate, m, workers=8)
+    outs = []
+    for flags in (0, zc.ZC_FLAG_SHARED_GPU):
+        s = zc.shape(mu, gate, m, flags)
+        ws = zc.new_workspace(s)
+        tabs = [zc.pack(dev(t), ws) for t in inst.tables]
+        outs.append([o.cpu().numpy() for o in zc.prove(s, tabs, dev(inst.r), ws)])
+        assert zc.read_error(ws) == 0
+    assert all(np.array_equal(a, b) for a, b in zip(*outs))
