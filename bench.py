@@ -594,7 +594,8 @@ def run_peaks():
         out[key] = {"blocks": blocks, "chains": chains, "products": prods, "s": t,
                     "gprod_per_s": prods / t / 1e9, "ns_per_dependent_product": t / iters * 1e9}
     so = torch.zeros(16 + 256, dtype=torch.uint32, device=dev)
-    for variant, key in ((0, "sha_block_kw_lds"), (1, "sha_block_on_the_fly"), (2, "sha_block_kw_lds_beside_products")):
+    for variant, key in ((0, "sha_block_kw_lds"), (1, "sha_block_on_the_fly"), (2, "sha_block_kw_lds_beside_products"),
+                         (3, "sha_block_kw_lds_scalar_unit")):
         n = 4000
         t = timed(lambda: zc.bench_sha(variant, n, elems, so))
         v = so.cpu().numpy().astype("uint64")

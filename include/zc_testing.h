@@ -72,7 +72,8 @@ int zc_bench_fmul(uint32_t blocks, uint32_t chains, uint32_t iters, const uint32
 /* zc_bench_sha: one lane chains n SHA-256 compressions of a 64-byte block;
    variant 0 reads k_t + w_t from LDS, variant 1 expands the message schedule
    on the fly, variant 2 is variant 0 while the block's three other waves
-   multiply field elements.  in: 64 elements (uint32[64][8], values < p).
+   multiply field elements, variant 3 is variant 0 on the scalar unit (the
+   whole of one wave, uniform operands).  in: 64 elements (uint32[64][8], values < p).
    out: device uint32[16 + 256]: [0..8) the final chaining value, [8..10) the
    shader clock cycles of lane 0's loop (s_memtime, lo/hi), [10..12) the same
    interval in 100 MHz ticks (s_memrealtime), the rest scratch. */

@@ -214,6 +214,79 @@ __device__ __forceinline__ void sha256_rounds_kw(uint32_t v[8], const uint32_t* 
   }
 }
 
+// ---- the same rounds on the scalar unit -------------------------------------------
+//
+// With wave-uniform operands (SGPRs) every lane of one wave runs the code and
+// the scalar unit executes it once.  The scalar unit has no rotate: rotr(x, n)
+// is the low word of the 64-bit (x:x) >> n, one s_lshr_b64 (pure ALU, no
+// memory access).  A round is ~25 scalar instructions against 14 vector ones,
+// but scalar instructions issue without the vector pipeline's dependency
+// stalls.
+template <int N>
+__device__ __forceinline__ uint32_t sha_srotr(uint32_t x) {
+  x = __builtin_amdgcn_readfirstlane(x);  // no instruction when x is already uniform
+  const uint64_t xx = ((uint64_t)x << 32) | x;
+  uint64_t r;
+  asm("s_lshr_b64 %0, %1, %2" : "=s"(r) : "s"(xx), "n"(N));
+  return (uint32_t)r;
+}
+
+#define ZC_SHA_ROUND_S(a, b, c, d, e, f, g, h, kw)                                          \
+  do {                                                                                       \
+    const uint32_t S1_ = sha_srotr<6>(e) ^ sha_srotr<11>(e) ^ sha_srotr<25>(e);               \
+    const uint32_t ch_ = g ^ (e & (f ^ g));                                                  \
+    const uint32_t t1_ = h + S1_ + ch_ + (kw);                                               \
+    const uint32_t S0_ = sha_srotr<2>(a) ^ sha_srotr<13>(a) ^ sha_srotr<22>(a);               \
+    d += t1_;                                                                                \
+    h = t1_ + S0_ + ((a & b) | (c & (a | b)));                                               \
+  } while (0)
+
+__device__ __forceinline__ void sha256_16kw_s(uint32_t v[8], const uint32_t k[16]) {
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    switch (r & 7) {
+      case 0: ZC_SHA_ROUND_S(v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7], k[r]); break;
+      case 1: ZC_SHA_ROUND_S(v[7], v[0], v[1], v[2], v[3], v[4], v[5], v[6], k[r]); break;
+      case 2: ZC_SHA_ROUND_S(v[6], v[7], v[0], v[1], v[2], v[3], v[4], v[5], k[r]); break;
+      case 3: ZC_SHA_ROUND_S(v[5], v[6], v[7], v[0], v[1], v[2], v[3], v[4], k[r]); break;
+      case 4: ZC_SHA_ROUND_S(v[4], v[5], v[6], v[7], v[0], v[1], v[2], v[3], k[r]); break;
+      case 5: ZC_SHA_ROUND_S(v[3], v[4], v[5], v[6], v[7], v[0], v[1], v[2], k[r]); break;
+      case 6: ZC_SHA_ROUND_S(v[2], v[3], v[4], v[5], v[6], v[7], v[0], v[1], k[r]); break;
+      default: ZC_SHA_ROUND_S(v[1], v[2], v[3], v[4], v[5], v[6], v[7], v[0], k[r]); break;
+    }
+  }
+}
+
+// sha256_rounds_kw on the scalar unit: v wave-uniform, kw in LDS read as
+// uniform values (the next group's 16 words read during the current group);
+// every lane of the wave must run it.
+__device__ __forceinline__ void sha256_rounds_kw_s(uint32_t v[8], const uint32_t* kw, int it0) {
+  uint32_t k[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) k[r] = __builtin_amdgcn_readfirstlane(kw[16 * it0 + r]);
+#pragma unroll 1
+  for (int it = it0; it < 4; ++it) {
+    const int nx = it < 3 ? it + 1 : 3;
+    uint32_t kn[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) kn[r] = kw[16 * nx + r];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = __builtin_amdgcn_readfirstlane(v[i]);
+    sha256_16kw_s(v, k);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) k[r] = __builtin_amdgcn_readfirstlane(kn[r]);
+  }
+}
+
+__device__ __forceinline__ void sha256_compress_kw_s(uint32_t h[8], const uint32_t* kw) {
+  uint32_t v[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) v[i] = h[i];
+  sha256_rounds_kw_s(v, kw, 0);
+#pragma unroll
+  for (int i = 0; i < 8; ++i) h[i] += v[i];
+}
+
 // Compression rounds with k_t + w_t precomputed (kw[0..63]).
 __device__ __forceinline__ void sha256_compress_kw(uint32_t h[8], const uint32_t* kw) {
   uint32_t v[8];

@@ -118,6 +118,23 @@ __global__ __launch_bounds__(kBlock) void k_bench_sha(uint32_t variant, uint32_t
     if (fe_is_zero(x)) out[16 + threadIdx.x] = k;
     return;
   }
+  if (variant == 3) {
+    // the scalar-unit rounds: the whole of wave 0, uniform operands
+    const uint64_t c0 = __builtin_amdgcn_s_memtime(), r0 = __builtin_amdgcn_s_memrealtime();
+    uint32_t h[8];
+    sha256_init(h);
+    for (uint32_t i = 0; i < n; ++i) sha256_compress_kw_s(h, kw);
+    const uint64_t c1 = __builtin_amdgcn_s_memtime(), r1 = __builtin_amdgcn_s_memrealtime();
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) out[k] = h[k];
+      out[8] = (uint32_t)(c1 - c0);
+      out[9] = (uint32_t)((c1 - c0) >> 32);
+      out[10] = (uint32_t)(r1 - r0);
+      out[11] = (uint32_t)((r1 - r0) >> 32);
+    }
+    return;
+  }
   if (threadIdx.x != 0) return;
   const uint64_t c0 = __builtin_amdgcn_s_memtime(), r0 = __builtin_amdgcn_s_memrealtime();
   uint32_t h[8];
@@ -170,7 +187,7 @@ int zc_bench_fmul(uint32_t blocks, uint32_t chains, uint32_t iters, const uint32
 }
 
 int zc_bench_sha(uint32_t variant, uint32_t n, const uint32_t* in, uint32_t* out, hipStream_t stream) {
-  if (!in || !out || variant > 2) return -1;
+  if (!in || !out || variant > 3) return -1;
   hipLaunchKernelGGL(k_bench_sha, dim3(1), dim3(kBlock), 0, stream, variant, n, in, out);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
