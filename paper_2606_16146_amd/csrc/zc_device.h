@@ -50,6 +50,11 @@ struct Ctrl {
   uint32_t nv[kMaxCoef][8];         // C_i (2 r_i - 1) e_l R
   uint32_t npr[8];                  // C_i (1 - r_i) R
   uint32_t nqr[8];                  // C_i (2 r_i - 1) R^2
+  // Mailbox of a launch whose block 0 finishes round i-1 while its other
+  // blocks wait to evaluate round i: alpha_{i-1} and then i-1, both written
+  // and read with device-coherent (agent-scope) accesses.
+  uint32_t mbox_alpha[8];
+  uint32_t mbox_round;
 };
 
 constexpr uint32_t kCtrlBytes = 4096;

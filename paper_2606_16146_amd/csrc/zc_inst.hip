@@ -120,19 +120,47 @@ template <class Gate, bool FIRST>
 struct SpecTag {};
 
 template <class Gate>
+struct WaitTag {};
+
+// The launches of a fused schedule (see zc_launch.h): speculative for gates
+// whose (d+1)^2 evaluations per pair fit a 16-lane group (k_fin_spec,
+// k_finish_spec), waiting for the challenge otherwise (k_fin_wait, then a
+// plain k_finish with the tail).
+template <class Gate>
 int launch_spec(ZC_SPEC_ARGS) {
+  int rc = 0;
+  if (step == kSpecRoundOnly) {
+    const void* kern = reinterpret_cast<const void*>(&k_round<Gate, true>);
+    const int per_cu = resident_blocks<RoundTag<Gate, true, false>>(kern);
+    const uint32_t b = round_grid((sa.q + kBlock - 1) / kBlock, per_cu, &rc, sa.share != 0);
+    if (rc) return rc;
+    hipLaunchKernelGGL((k_round<Gate, true>), dim3(b), dim3(kBlock), 0, st, sa, src, dst);
+    *blocks = b;
+    return launch_ok();
+  }
   if constexpr (!SpecShape<Gate>::kOk) {
-    return -1;
-  } else {
-    int rc = 0;
-    if (step == kSpecRoundOnly) {
-      const void* kern = reinterpret_cast<const void*>(&k_round<Gate, true>);
-      const int per_cu = resident_blocks<RoundTag<Gate, true, false>>(kern);
-      const uint32_t b = round_grid((sa.q + kBlock - 1) / kBlock, per_cu, &rc, sa.share != 0);
+    if (step == kSpecFinishTail) {
+      if (!fa.tail) return -1;
+      allow_tail_lds<FinishTag<Gate>>(reinterpret_cast<const void*>(&k_finish<Gate>), tail_lds_bytes<Gate>());
+      hipLaunchKernelGGL((k_finish<Gate>), dim3(1), dim3(kBlock), tail_lds_bytes<Gate>(), st, fa, fdst);
+    } else {
+      const void* kern = reinterpret_cast<const void*>(&k_fin_wait<Gate>);
+      const int per_cu = resident_blocks<WaitTag<Gate>>(kern);
+      // one resident generation including the finisher block
+      uint32_t b = round_grid((sa.q + kSplitPairs - 1) / kSplitPairs + 1, per_cu, &rc) - 1;
       if (rc) return rc;
-      hipLaunchKernelGGL((k_round<Gate, true>), dim3(b), dim3(kBlock), 0, st, sa, src, dst);
+      if (b < 1) b = 1;
+      if (b > kSpecBlocks) b = kSpecBlocks;
+      // the finisher has no tail here and the round folds in place
+      if (fa.tail || src.p[0] != dst.p[0]) return -1;
+      RoundArgs f = fa;
+      f.signal = 1;
+      hipLaunchKernelGGL((k_fin_wait<Gate>), dim3(b + 1), dim3(kBlock), 0, st, f, sa, src);
       *blocks = b;
-    } else if (step == kSpecFinishTail) {
+    }
+    return launch_ok();
+  } else {
+    if (step == kSpecFinishTail) {
       allow_tail_lds<FinishSpecTag<Gate>>(reinterpret_cast<const void*>(&k_finish_spec<Gate>), tail_lds_bytes<Gate>());
       hipLaunchKernelGGL((k_finish_spec<Gate>), dim3(1), dim3(kBlock), tail_lds_bytes<Gate>(), st, fa, fdst);
     } else {

@@ -552,6 +552,7 @@ struct RoundArgs {
   EqTabs eq;
   uint32_t check;              // 1: the verifier's claim checks on the device (ZC_FLAG_CHECK_CLAIMS)
   uint32_t share;              // host only: round grids sized for a shared GPU (ZC_FLAG_SHARED_GPU)
+  uint32_t signal;             // 1: the finisher also posts alpha_i to the mailbox (k_fin_wait)
 };
 
 // Montgomery product reduced below p.
@@ -682,9 +683,15 @@ struct NoSideWork {
 
 // `side` runs on waves 1..3 while lane 0 compresses the message after its
 // first 16 rounds (the hash's serial part); it must not use __syncthreads.
+//
+// With `signal`, lane 0 also posts alpha_i and then i to the control block's
+// mailbox with device-coherent stores, the second only once the first have
+// completed, for the blocks of the same launch that wait for alpha_i
+// (k_fin_wait).
 template <int D, class Side = NoSideWork>
 __device__ __forceinline__ void emit_round(Ctrl* ctrl, uint32_t round, FinLds<D>& S, uint32_t* evals_out,
-                                           uint32_t* alpha_out, bool check, Side side = Side{}) {
+                                           uint32_t* alpha_out, bool check, Side side = Side{},
+                                           bool signal = false) {
   constexpr int NH = D + 1, NE = D + 2, NC = FinLds<D>::NC;
   constexpr uint32_t LEN = FinLds<D>::LEN, NB = FinLds<D>::NB;
   static_assert(NH <= 16, "one 16-lane group");
@@ -771,6 +778,12 @@ __device__ __forceinline__ void emit_round(Ctrl* ctrl, uint32_t round, FinLds<D>
       alpha_out[k] = w[k];
     }
     ctrl->round_done = round;
+    if (signal) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) __hip_atomic_store(&ctrl->mbox_alpha[k], w[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the alpha words have completed
+      __hip_atomic_store(&ctrl->mbox_round, round, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
   } else if (t >= 64) {
     side();
   }
@@ -1173,56 +1186,101 @@ __device__ __forceinline__ void run_tail(const RoundArgs& a, const TabPtrs& dst,
   if (tid == K) store_words_fe(a.openings + K * 8, fe_from_mont(fe_vgpr(lds_fe(S.cm))));
 }
 
-// Round with 16 lanes per pair; the grid strides over the pairs and is sized
-// like k_round's.
-template <class Gate, bool FOLD>
-__global__ __launch_bounds__(kBlock) void k_round_split(RoundArgs a, TabPtrs srct, TabPtrs dstt) {
+// alpha_{round} for the blocks of a k_fin_wait launch: lane 0 polls the
+// mailbox (device-coherent loads) until block 0 has posted round `round`, or
+// a device error is set, or ~10 ms have passed (then ZC_ESTATE: the bytes are
+// wrong but every block ends); the block then reads alpha from LDS.  All
+// threads of the block call it (it has a barrier).
+constexpr uint64_t kWaitTicks = 1000000;  // s_memrealtime runs at 100 MHz
+__device__ __forceinline__ Fe wait_alpha(Ctrl* ctrl, uint32_t round, uint32_t* box) {
+  if (threadIdx.x == 0) {
+    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+    while (__hip_atomic_load(&ctrl->mbox_round, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < round) {
+      if (__hip_atomic_load(&ctrl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+      if (__builtin_amdgcn_s_memrealtime() - t0 > kWaitTicks) {
+        set_error(ctrl, -5);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) box[k] = __hip_atomic_load(&ctrl->mbox_alpha[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  uint32_t w[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) w[k] = box[k];
+  return fe_to_mont(fe_vgpr(fe_from_words(w)));
+}
+
+// Round with 16 lanes per pair: block `blk` of `nblk` strides over the pairs.
+// WAIT (FOLD only): alpha_{i-1} comes from the mailbox once block 0 of the
+// same launch has posted it; the block's first loads are issued before the
+// wait, so their latency overlaps the hash.
+template <class Gate, bool FOLD, bool WAIT>
+__device__ __forceinline__ void split_body(const RoundArgs& a, const TabPtrs& srct, const TabPtrs& dstt, uint32_t blk,
+                                           uint32_t nblk) {
+  static_assert(FOLD || !WAIT, "only a folding round waits for its challenge");
   constexpr int K = Gate::K;
   constexpr int NH = Gate::NH;
   __shared__ uint32_t sh[kSplitPairs][K][2][NL];
+  __shared__ uint32_t box[WAIT ? 8 : 1];
   const uint32_t g = threadIdx.x % kGroup, pl = threadIdx.x / kGroup;
   Fe c = fe_zero();
+  Fe walpha = fe_zero();
+  bool have_alpha = !WAIT;
   {
     const uint32_t q = (uint32_t)a.q;
-    const uint64_t stride = (uint64_t)gridDim.x * kSplitPairs;
-    for (uint64_t base = (uint64_t)blockIdx.x * kSplitPairs; base < q; base += stride) {
+    const uint64_t stride = (uint64_t)nblk * kSplitPairs;
+    for (uint64_t base = (uint64_t)blk * kSplitPairs; base < q; base += stride) {
       const uint32_t j = (uint32_t)(base + pl);
       // the eq rows of the pair are loaded now, used after the exchange
       EqRows er{};
       if (j < q && g < (uint32_t)NH) er = issue_eq(a.eq, a.round, j);
-      if (j < q && g < (uint32_t)K) {
-        // table g's pointers, selected without indexing the argument array per lane
-        const uint32_t* src = srct.p[0];
-        uint32_t* dst = dstt.p[0];
-        auto sel = [&](auto t) __attribute__((always_inline)) {
-          if (g == (uint32_t)t) {
-            src = srct.p[t];
-            dst = dstt.p[t];
-          }
-        };
-        Unroll<1, K>::run(sel);
-        Fe u0, u1;
+      // table g's pointers, selected without indexing the argument array per lane
+      const uint32_t* src = srct.p[0];
+      uint32_t* dst = dstt.p[0];
+      auto sel = [&](auto t) __attribute__((always_inline)) {
+        if (g == (uint32_t)t) {
+          src = srct.p[t];
+          dst = dstt.p[t];
+        }
+      };
+      Unroll<1, K>::run(sel);
+      const bool mine = j < q && g < (uint32_t)K;
+      Fe u0, u1, a0, a1, a2, a3;
+      if (mine) {
         if (FOLD) {
-          const Fe alpha = fe_to_mont(fe_vgpr(load_words_fe(a.ctrl->alpha[a.round - 2])));
           const uint64_t sp = a.src_pitch;
-          const Fe a0 = load_el(src, sp, j), a2 = load_el(src, sp, j + 2 * q);
-          const Fe a1 = load_el(src, sp, j + q), a3 = load_el(src, sp, j + 3 * q);
+          a0 = load_el(src, sp, j);
+          a2 = load_el(src, sp, j + 2 * q);
+          a1 = load_el(src, sp, j + q);
+          a3 = load_el(src, sp, j + 3 * q);
+        } else {
+          u0 = load_el(src, a.src_pitch, j);
+          u1 = load_el(src, a.src_pitch, j + q);
+        }
+      }
+      if (WAIT && !have_alpha) {
+        walpha = wait_alpha(a.ctrl, a.round - 1, box);
+        have_alpha = true;
+      }
+      if (mine) {
+        if (FOLD) {
+          const Fe alpha = WAIT ? walpha : fe_to_mont(fe_vgpr(load_words_fe(a.ctrl->alpha[a.round - 2])));
           u0 = fe_lerp(a0, a2, alpha);
           u1 = fe_lerp(a1, a3, alpha);
           store_el(dst, a.dst_pitch, j, u0);
           store_el(dst, a.dst_pitch, j + q, u1);
-        } else {
-          u0 = load_el(src, a.src_pitch, j);
-          u1 = load_el(src, a.src_pitch, j + q);
         }
         lds_put(sh[pl][g][0], u0);
         lds_put(sh[pl][g][1], u1);
       }
       __syncthreads();
       if (j < q && g < (uint32_t)NH) {
-        auto get = [&](int t, Fe& u0, Fe& u1) __attribute__((always_inline)) {
-          u0 = lds_fe(sh[pl][t][0]);
-          u1 = lds_fe(sh[pl][t][1]);
+        auto get = [&](int t, Fe& v0, Fe& v1) __attribute__((always_inline)) {
+          v0 = lds_fe(sh[pl][t][0]);
+          v1 = lds_fe(sh[pl][t][1]);
         };
         const Fe E = resolve_eq(er);
         c = fe_addmod(c, fe_reduce2(fe_mul(point_f<Gate>(get, g), E)));
@@ -1231,8 +1289,14 @@ __global__ __launch_bounds__(kBlock) void k_round_split(RoundArgs a, TabPtrs src
     }
   }
   const Fe tot = group_reduce<NH>(c);
-  if (threadIdx.x < NH)
-    store_words_fe(a.partials + ((uint64_t)blockIdx.x * part_stride(NH) + threadIdx.x) * 8, tot);
+  if (threadIdx.x < NH) store_words_fe(a.partials + ((uint64_t)blk * part_stride(NH) + threadIdx.x) * 8, tot);
+}
+
+// Round with 16 lanes per pair; the grid strides over the pairs and is sized
+// like k_round's.
+template <class Gate, bool FOLD>
+__global__ __launch_bounds__(kBlock) void k_round_split(RoundArgs a, TabPtrs srct, TabPtrs dstt) {
+  split_body<Gate, FOLD, false>(a, srct, dstt, blockIdx.x, gridDim.x);
 }
 
 // ---- speculative rounds (gates of degree <= 3) -----------------------------------------
@@ -1424,7 +1488,7 @@ __device__ __forceinline__ void finish_body(const RoundArgs& a, const TabPtrs& d
     }
     __syncthreads();
   }
-  emit_round<Gate::D>(a.ctrl, a.round, S, a.evals_out, a.alpha_out, a.check != 0);
+  emit_round<Gate::D>(a.ctrl, a.round, S, a.evals_out, a.alpha_out, a.check != 0, NoSideWork{}, a.signal != 0);
   if (a.tail) run_tail<Gate>(a, dst, S, SPEC);
 }
 
@@ -1448,6 +1512,19 @@ __global__ __launch_bounds__(kBlock) void k_fin_spec(RoundArgs fa, RoundArgs sa,
 template <class Gate>
 __global__ __launch_bounds__(kBlock) void k_finish_spec(RoundArgs a, TabPtrs dst) {
   finish_body<Gate, true>(a, dst);
+}
+
+// Gates without speculation (degree > 3): the finisher of round i-1 (block 0,
+// no tail, fa.signal set) beside the lane-split evaluation of round i (the
+// other blocks), which folds the tables in place with alpha_{i-1} as soon as
+// block 0 posts it.  Blocks are dispatched in order, so block 0 runs before
+// any block waits for it.
+template <class Gate>
+__global__ __launch_bounds__(kBlock) void k_fin_wait(RoundArgs fa, RoundArgs sa, TabPtrs tabs) {
+  if (blockIdx.x == 0)
+    finish_body<Gate, false>(fa, tabs);
+  else
+    split_body<Gate, true, true>(sa, tabs, tabs, blockIdx.x - 1, gridDim.x - 1);
 }
 
 // ---- batches: many instances, round by round in lockstep ------------------------------

@@ -26,19 +26,20 @@ inline uint64_t split_q(uint32_t) { return 16384u; }
 
 enum RoundKind { kPerPair = 0, kSplit = 1, kSplitTail = 2, kInTail = 3, kSpec = 4, kSpecTail = 5 };
 
-// Speculative lane-split rounds (gates of degree <= 3, whose (d+1)^2
-// evaluations per pair fit the 16 lanes of a pair): round i is evaluated
-// for every candidate alpha_{i-1} in 0..d beside the finisher of round i-1,
-// and its own finisher interpolates.  s0 is the first lane-split round, r the
-// round whose finisher starts the tail; rounds s0..r-1 are kSpec, r is
-// kSpecTail.  Used when s0 >= 3 and r > s0.
+// Fused lane-split rounds: round i is evaluated in the same launch as the
+// finisher of round i-1.  Gates of degree <= 3 (whose (d+1)^2 evaluations per
+// pair fit the 16 lanes of a pair) evaluate it for every candidate
+// alpha_{i-1} in 0..d, and its own finisher interpolates (speculation); the
+// other gates' blocks wait for alpha_{i-1}, which the finisher block posts
+// when it has it, with their first loads already issued.  s0 is the first
+// lane-split round, r the round whose finisher starts the tail; rounds
+// s0..r-1 are kSpec, r is kSpecTail.  Used when s0 >= 3 and r > s0.
 struct SpecPlan {
   uint32_t s0, r;
   bool on;
 };
 inline SpecPlan spec_plan(uint32_t mu, uint32_t degree) {
   SpecPlan p{0, 0, false};
-  if (degree > 3) return p;
   for (uint32_t i = 1; i <= mu; ++i) {
     const uint64_t q = 1ull << (mu - i);
     if (!p.s0 && q <= split_q(degree)) p.s0 = i;
@@ -61,11 +62,10 @@ inline RoundKind prove_round_kind(uint32_t mu, uint32_t i, uint32_t degree) {
   return (i == 1 || prev_q > first_tail_q) ? kSplitTail : kInTail;
 }
 
-// The launches of a speculative schedule: the last thread-per-pair round
-// without its finisher; the finisher of round r-1 beside the speculative
-// round r (first or later); the finisher of the last speculative round,
-// which runs the tail.  *blocks receives the number of partial-sum blocks
-// written.  Negative for a gate without speculation.
+// The launches of a fused schedule: the last thread-per-pair round without
+// its finisher; the finisher of round r-1 beside round r (first or later);
+// the finisher of the last fused round, which runs the tail.  *blocks
+// receives the number of partial-sum blocks written.
 enum SpecStep { kSpecRoundOnly = 0, kSpecFirst = 1, kSpecNext = 2, kSpecFinishTail = 3 };
 constexpr uint32_t kSpecBlocks = 1024;  // partial-sum blocks of a speculative round, at most
 

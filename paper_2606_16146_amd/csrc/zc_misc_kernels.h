@@ -33,6 +33,7 @@ __device__ __forceinline__ void setup_body(const uint32_t* __restrict__ r, uint3
     ctrl->err = 0;
     ctrl->round_done = 0;
     ctrl->fold_done = 0;
+    __hip_atomic_store(&ctrl->mbox_round, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     store_words_fe(ctrl->npr, fe_const(kOne));
     store_words_fe(ctrl->nqr, fe_zero());
   }

@@ -125,10 +125,11 @@ def test_round_kernel_schedule_is_consistent():
             assert all(k in (0, split) for k in kinds[:t]), (mu, kinds)
             # thread-per-pair rounds come first (largest q), then lane-split rounds
             assert kinds[:t] == sorted(kinds[:t]), (mu, kinds)
-            # speculation: gates of degree <= 3, after at least two thread-per-pair rounds
+            # fused rounds (speculative for degree <= 3, waiting for the
+            # challenge otherwise): after at least two thread-per-pair rounds
             if tail == 5:
-                assert d <= 3 and kinds[:2] == [0, 0], (mu, kinds)
-            if d <= 3 and kinds.count(0) >= 2 and kinds[t - 1] != 0:
+                assert kinds[:2] == [0, 0], (mu, kinds)
+            if kinds.count(0) >= 2 and kinds[t - 1] != 0:
                 assert tail == 5, (mu, kinds)
     s = zc.shape(5, 0, 0)
     assert h.zc_prove_round_kernel(ctypes.byref(s), 0) < 0 and h.zc_prove_round_kernel(ctypes.byref(s), 6) < 0

@@ -179,15 +179,17 @@ def test_extreme_values_thread_per_pair_rounds(zc, gate, m):
 
 
 @pytest.mark.parametrize("mu,gate,m", [(16, 0, 0), (17, 0, 0), (18, 0, 0), (17, 1, 2), (17, 1, 1), (17, 2, 3),
-                                       (17, 2, 50), (18, 2, 2), (17, 2, 4), (17, 1, 3)])
-def test_speculative_schedule_boundaries_match_c_oracle(zc, mu, gate, m):
-    """Around the sizes where speculative rounds switch on (degree <= 3 and at
-    least two thread-per-pair rounds: on from mu = 17), for the gates that
-    use them and two that do not (degree 4), against the C oracle."""
+                                       (17, 2, 50), (18, 2, 2), (17, 2, 4), (17, 1, 3),
+                                       (16, 1, 8), (17, 1, 8), (18, 1, 8), (19, 1, 4)])
+def test_fused_schedule_boundaries_match_c_oracle(zc, mu, gate, m):
+    """Around the sizes where the fused lane-split rounds switch on (at least
+    two thread-per-pair rounds: from mu = 17): speculative for gates of
+    degree <= 3, waiting for the challenge beside the finisher for degree 4,
+    5 and 9, against the C oracle."""
     import ctypes
     s = zc.shape(mu, gate, m)
     kinds = [zc.lib().zc_prove_round_kernel(ctypes.byref(s), i) for i in range(1, mu + 1)]
-    assert (5 in kinds) == (zc.degree(s) <= 3 and mu >= 17), kinds
+    assert (5 in kinds) == (mu >= 17), kinds
     inst = I.make_instance(60 + mu, m, mu, gate, m)
     res = gpu_prove(inst)
     assert res["err"] == 0
