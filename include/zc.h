@@ -249,6 +249,18 @@ int zc_serve_admit(void* pool, uint32_t slots, uint32_t slot, const zc_instance*
 int zc_serve_step(void* pool, uint32_t slots, uint32_t n, const uint32_t* slot_ids, const uint32_t* rounds,
                   const zc_instance* inst, hipStream_t stream);
 
+/* One part of one step of one admitted instance: round `round` split into
+   `parts` launches (1 <= parts <= 64, 0 <= part < parts) of equal block
+   counts, part `part` of them; the last part also runs the round's finisher
+   (and, at round zc_serve_rounds(shape), the rest of the proof, which is
+   never split: parts must be 1 there).  The parts of a round run in order
+   on one stream, as whole steps do, and may interleave with other work on
+   other streams: a large instance's round then takes the GPU in short
+   launches.  ZC_EINVAL if the split would need more than 2048 blocks in all.
+   Same bytes as zc_serve_step. */
+int zc_serve_step_part(void* pool, uint32_t slots, uint32_t slot, uint32_t round, uint32_t part, uint32_t parts,
+                       const zc_instance* inst, hipStream_t stream);
+
 /* Synchronizes `stream` and returns the first device-detected error stored in
    ws (ZC_OK if none), or ZC_EHIP if the synchronization fails.  The error word
    is cleared when zc_prove or zc_round(1) starts; a workspace that has run

@@ -427,6 +427,7 @@ int launch_batch_key(uint32_t key, const BatchStep& bs, uint32_t blocks, bool fo
 // ---- serving -------------------------------------------------------------------
 
 constexpr uint32_t kServeSlots = 65535;  // slot ids travel as u16
+constexpr uint32_t kServeMaxParts = 64;   // launches one round of zc_serve_step_part may be split into
 
 // admission of one instance: its descriptor into the pool and setup_body in
 // block 0, T_0 in the last block, the eq rows in between
@@ -702,6 +703,7 @@ int zc_serve_step(void* pool, uint32_t slots, uint32_t n, const uint32_t* slot_i
       bool tail = false;
       auto flush = [&]() -> int {
         if (ss.count == 0) return ZC_OK;
+        ss.nfin = ss.count;
         const int rc = launch_serve_key(key, ss, ss.prefix[ss.count], fold != 0, tail, stream);
         ss.count = 0;
         tail = false;
@@ -712,6 +714,8 @@ int zc_serve_step(void* pool, uint32_t slots, uint32_t n, const uint32_t* slot_i
         const uint32_t c = ss.count;
         ss.slot[c] = (uint16_t)slot_ids[i];
         ss.rnd[c] = (uint8_t)rounds[i];
+        ss.prt[c] = 0;
+        ss.nprt[c] = 1;
         ss.prefix[c + 1] = ss.prefix[c] + tile_blocks(inst[i].shape.mu, rounds[i], inst[i].tile);
         if (rounds[i] == last_round(inst[i].shape.mu)) tail = true;
         if (++ss.count == (uint32_t)kServeMax) {
@@ -724,6 +728,31 @@ int zc_serve_step(void* pool, uint32_t slots, uint32_t n, const uint32_t* slot_i
     }
   }
   return ZC_OK;
+}
+
+int zc_serve_step_part(void* pool, uint32_t slots, uint32_t slot, uint32_t round, uint32_t part, uint32_t parts,
+                       const zc_instance* inst, hipStream_t stream) {
+  if (!pool || !aligned(pool, 256) || slots < 1 || slots > kServeSlots || !inst || slot >= slots) return ZC_EINVAL;
+  Layout L;
+  const int rc = make_layout(&inst->shape, &L);
+  if (rc != ZC_OK) return rc;
+  const uint32_t last = last_round(inst->shape.mu);
+  if (round < 1 || round > last || parts < 1 || parts > kServeMaxParts || part >= parts) return ZC_EINVAL;
+  if (round == last && parts != 1) return ZC_EINVAL;  // the round that runs the tail is not split
+  const uint32_t b = tile_blocks(inst->shape.mu, round, inst->tile);
+  const uint32_t nb = (b + parts - 1) / parts;
+  if ((uint64_t)nb * parts > (uint64_t)kMaxBlocks) return ZC_EINVAL;
+  ServeStep ss{};
+  ss.pool = reinterpret_cast<const InstDesc*>(pool);
+  ss.count = 1;
+  ss.nfin = part + 1 == parts ? 1u : 0u;
+  ss.prefix[0] = 0;
+  ss.prefix[1] = nb;
+  ss.slot[0] = (uint16_t)slot;
+  ss.rnd[0] = (uint8_t)round;
+  ss.prt[0] = (uint8_t)part;
+  ss.nprt[0] = (uint8_t)parts;
+  return launch_serve_key(gate_key(inst->shape), ss, nb, round > 1, round == last, stream);
 }
 
 int zc_read_error(void* ws, hipStream_t stream) {

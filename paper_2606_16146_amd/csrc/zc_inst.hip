@@ -208,8 +208,9 @@ int launch_serve(const ServeStep& ss, uint32_t blocks, bool fold, bool tail, hip
     hipLaunchKernelGGL((k_serve_round<Gate, false>), dim3(blocks), dim3(kBlock), 0, st, ss);
   int rc = launch_ok();
   if (rc != 0) return rc;
+  if (ss.nfin == 0) return 0;
   if (tail) allow_tail_lds<ServeFinishTag<Gate>>(reinterpret_cast<const void*>(&k_serve_finish<Gate>), tail_lds_bytes<Gate>());
-  hipLaunchKernelGGL((k_serve_finish<Gate>), dim3(ss.count), dim3(kBlock), tail ? tail_lds_bytes<Gate>() : 0, st, ss);
+  hipLaunchKernelGGL((k_serve_finish<Gate>), dim3(ss.nfin), dim3(kBlock), tail ? tail_lds_bytes<Gate>() : 0, st, ss);
   return launch_ok();
 }
 

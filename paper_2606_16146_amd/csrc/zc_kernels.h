@@ -1566,21 +1566,32 @@ struct BatchStep {
   __device__ __forceinline__ uint32_t pre(uint32_t i) const { return prefix[i]; }
   __device__ __forceinline__ const InstDesc& desc(uint32_t i) const { return descs[inst[i]]; }
   __device__ __forceinline__ uint32_t round(uint32_t) const { return step + 1; }
+  __device__ __forceinline__ uint32_t part(uint32_t) const { return 0; }
+  __device__ __forceinline__ uint32_t parts(uint32_t) const { return 1; }
 };
 
 // One gate's share of a serving step: up to kServeMax instances, each at its
 // own round, carried whole in the kernel arguments (no copy per step).
 constexpr int kServeMax = 256;
+// An instance's round may also be split into `parts` launches of equal
+// block counts (part p runs blocks [p nb, (p + 1) nb) of the nb * parts
+// blocks of the round); only the last part's launch has a finisher.
+// nfin: entries 0..nfin-1 get a finisher block.
 struct ServeStep {
   const InstDesc* pool;
   uint32_t count;
+  uint32_t nfin;
   uint32_t prefix[kServeMax + 1];
   uint16_t slot[kServeMax];
   uint8_t rnd[kServeMax];
+  uint8_t prt[kServeMax];
+  uint8_t nprt[kServeMax];
   __device__ __forceinline__ uint32_t n() const { return count; }
   __device__ __forceinline__ uint32_t pre(uint32_t i) const { return prefix[i]; }
   __device__ __forceinline__ const InstDesc& desc(uint32_t i) const { return pool[slot[i]]; }
   __device__ __forceinline__ uint32_t round(uint32_t i) const { return rnd[i]; }
+  __device__ __forceinline__ uint32_t part(uint32_t i) const { return prt[i]; }
+  __device__ __forceinline__ uint32_t parts(uint32_t i) const { return nprt[i]; }
 };
 static_assert(sizeof(ServeStep) <= 4096 - 64, "kernel argument size");
 
@@ -1620,16 +1631,19 @@ __device__ __forceinline__ void batch_round_body(const Step& st) {
   const uint32_t i = batch_find(st, blockIdx.x);
   const InstDesc& d = st.desc(i);
   const uint32_t round = st.round(i);
-  const uint32_t p0 = st.pre(i), nblk = st.pre(i + 1) - p0;
+  const uint32_t p0 = st.pre(i), nb = st.pre(i + 1) - p0;  // this launch's blocks of the round
+  const uint32_t nblk = nb * st.parts(i);                   // all the round's blocks
   const RoundArgs a = batch_round_args(d, round, nblk);
-  round_body<Gate, FOLD>(a, round <= 2 ? d.orig : d.fold, round == 1 ? d.orig : d.fold, blockIdx.x - p0, nblk);
+  round_body<Gate, FOLD>(a, round <= 2 ? d.orig : d.fold, round == 1 ? d.orig : d.fold,
+                         blockIdx.x - p0 + st.part(i) * nb, nblk);
 }
 
 template <class Gate, class Step>
 __device__ __forceinline__ void batch_finish_body(const Step& st) {
   const InstDesc& d = st.desc(blockIdx.x);
   const uint32_t round = st.round(blockIdx.x);
-  const RoundArgs a = batch_round_args(d, round, st.pre(blockIdx.x + 1) - st.pre(blockIdx.x));
+  const RoundArgs a =
+      batch_round_args(d, round, (st.pre(blockIdx.x + 1) - st.pre(blockIdx.x)) * st.parts(blockIdx.x));
   finish_body<Gate>(a, round == 1 ? d.orig : d.fold);
 }
 

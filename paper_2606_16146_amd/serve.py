@@ -22,17 +22,21 @@ zc_prove (zc_prove_pitch for a window) instead of being stepped, up to
 priority).  A step runs every (gate, fold) group's round and finisher
 launches for one round of each admitted request, which at low concurrency
 costs a request several times its proof alone; zc_prove runs the
-single-proof schedule (lane-split and speculative rounds, the LDS tail in one
+single-proof schedule (lane-split and fused rounds, the LDS tail in one
 launch).  Proofs on distinct streams share the GPU: a small proof's chain of
 short kernels runs in the gaps of a large proof's wide rounds rather than
 after it.  The fast path takes the waiting request with the fewest hypercube
 points (`order="sjf"`, shortest job first) unless the oldest has waited
-`max_wait_s`, or the oldest (`order="fcfs"`); requests of 2^big_mu points
-or more hold at most `big_lanes` lanes at once, so that the others stay free
-for small requests, and (`share_big`) run with ZC_FLAG_SHARED_GPU grids,
-whose shorter-lived blocks free compute units for the small proofs' kernels
-during a large round.  A queue longer than `fast_queue`, and arrivals while
-steps run, go to continuous batching.
+`max_wait_s`, or the oldest (`order="fcfs"`).  Requests of 2^big_mu points
+or more hold at most `big_lanes` lanes at once and (`share_big`) run with
+ZC_FLAG_SHARED_GPU grids, whose shorter-lived blocks free compute units for
+the small proofs' kernels during a large round.  While no other large
+request waits (`split_big`), a large request is instead stepped through the
+pool round by round, each large round in parts of about `part_blocks`
+blocks (zc_serve_step_part), and its next part waits while small proofs
+run (at most `hold_big_s`): small requests then run with the GPU nearly to
+themselves, as under shortest-remaining-work-first.  A queue longer than
+`fast_queue`, and arrivals while steps run, go to continuous batching.
 Outputs stay on the device.  Every request's bytes equal its zc_prove proof
 (each instance owns its workspace; sharing a launch changes nothing it
 computes).
@@ -107,7 +111,8 @@ class Server:
     def __init__(self, slots: int = 256, mem_budget: int | None = None, ahead: int = 2, device="cuda",
                  stream: torch.cuda.Stream | None = None, fast_queue: int = 16, order: str = "sjf",
                  max_wait_s: float = 0.05, lanes: int = 4, big_mu: int | None = 21, big_lanes: int = 1,
-                 share_big: bool = True):
+                 share_big: bool = True, split_big: bool = True, part_blocks: int = 256,
+                 hold_big_s: float = 0.001):
         self.dev = torch.device(device)
         self.pool = zc.ServePool(slots, self.dev)
         self.slots = slots
@@ -127,6 +132,15 @@ class Server:
         self.big_lanes = big_lanes    # ... hold at most this many lanes at once
         self.share_big = share_big and lanes > 1  # ... with ZC_FLAG_SHARED_GPU grids
         self.book = _lane_streams(self.dev, 1)[0]  # runs only the error-word reads
+        # split_big: while no other large request waits, a large one is
+        # stepped through the pool in parts of about part_blocks blocks
+        # (zc_serve_step_part) on a stream of its own, its next part held back
+        # while small proofs run (at most hold_big_s after its previous part
+        # ended); otherwise it is proved whole like the others
+        self.split_big = split_big and big_mu is not None
+        self.part_blocks = part_blocks
+        self.hold_big_s = hold_big_s
+        self.big_stream = _lane_streams(self.dev, lanes + 1)[lanes]
         self.order = order
         self.max_wait_s = max_wait_s
 
@@ -162,6 +176,19 @@ class Server:
             return ok[0]
         return min(ok, key=lambda j: (waiting[j].points, waiting[j].arrival))
 
+    def _parts(self, mu: int, rnd: int, last: int, tile: int = 0) -> int:
+        """Parts of round rnd of a split request: a power of two, so that they
+        divide the round's blocks (zc_serve_step_part: 2^(mu - rnd) pairs in
+        blocks of 256 x tile pairs, tile 0 meaning 4, at most 2048 blocks)."""
+        if rnd == last:
+            return 1
+        per = 256 * (tile or 4)
+        blocks = max(1, min(2048, ((1 << (mu - rnd)) + per - 1) // per))
+        parts = 1
+        while parts * 2 <= min(8, blocks // self.part_blocks):
+            parts *= 2
+        return parts
+
     def _prove_alone(self, req: Request, now: float, stream: torch.cuda.Stream):
         """The fast path: the whole proof, single-proof schedule, on `stream`
         (its workspace and outputs allocated in that stream's order)."""
@@ -173,15 +200,16 @@ class Server:
         req.t_admit = now
         req.fast_path = True
 
-    def _admit(self, req: Request, slot: int, now: float):
+    def _admit(self, req: Request, slot: int, now: float, stream: torch.cuda.Stream | None = None):
+        stream = stream or self.stream
         s = req.shape
-        self._device_state(req, self.stream)
+        self._device_state(req, stream)
         ev, al, op = req.outputs
         req._tabarr = (ctypes.c_void_p * len(req._dev_tables))(*[t.data_ptr() for t in req._dev_tables])
         req._inst = zc.Instance(s, ctypes.cast(req._tabarr, ctypes.c_void_p), req.r.data_ptr(),
                                 req.ws.data_ptr(), ev.data_ptr(), al.data_ptr(), op.data_ptr(), req.tile,
                                 req.pitch)
-        self.pool.admit(slot, req._inst)
+        self.pool.admit(slot, req._inst, stream)
         req.t_admit = now
 
     def run(self, requests: list[Request]) -> dict:
@@ -192,19 +220,29 @@ class Server:
         in_flight: list = []        # [event, [reqs it completes], lane or -1 for a step], oldest first
         lane_busy = [0] * len(self.lanes)
         big_running = 0
+        bigs: list = []             # split large requests: [req, slot, round, last, part, parts, in flight, since]
         free_slots = list(range(self.slots - 1, -1, -1))
         mem_used = 0
         steps = 0
         fast_n = 0
+        split_n = 0
 
         def retire(entry):
             nonlocal mem_used, big_running
-            ev, done, lane = entry
+            ev, done, lane = entry[:3]
             ev.synchronize()
             t = time.perf_counter() - t0
             if lane >= 0:
                 lane_busy[lane] -= 1
                 big_running -= sum(self._big(q) for q in done)
+            elif lane == -2:  # a part of a split request
+                b = entry[3]
+                b[6] -= 1
+                b[7] = t
+                if done:
+                    bigs.remove(b)
+                    free_slots.append(b[1])  # its last part has completed
+                    big_running -= 1
             for req in done:
                 req.t_done = t
                 mem_used -= req._bytes
@@ -218,7 +256,7 @@ class Server:
 
         with torch.cuda.stream(self.stream):
             t0 = time.perf_counter()
-            while pending or waiting or active or in_flight:
+            while pending or waiting or active or in_flight or bigs:
                 now = time.perf_counter() - t0
                 while pending and pending[0].arrival <= now:
                     waiting.append(pending.popleft())
@@ -227,12 +265,30 @@ class Server:
                 depth = 2 if len(self.lanes) == 1 else 1
                 while fast and waiting:
                     lane = min(range(len(self.lanes)), key=lambda j: lane_busy[j])
-                    if lane_busy[lane] >= depth:
+                    allow_big = big_running < self.big_lanes
+                    if lane_busy[lane] >= depth and not (self.split_big and allow_big and free_slots):
                         break
-                    pick = self._pick(waiting, now, big_running < self.big_lanes)
+                    pick = self._pick(waiting, now, allow_big)
                     if pick < 0 or (mem_used + footprint(waiting[pick]) > self.mem_budget and in_flight):
                         break
                     req = waiting[pick]
+                    # split a large request only while no other large one waits
+                    # (light load); under load the whole-proof path keeps the
+                    # throughput
+                    light = not any(self._big(q) for q in waiting if q is not req)
+                    if self.split_big and self._big(req) and free_slots and light:
+                        del waiting[pick]
+                        slot = free_slots.pop()
+                        self._admit(req, slot, now, self.big_stream)
+                        req._bytes = footprint(req)
+                        mem_used += req._bytes
+                        big_running += 1
+                        bigs.append([req, slot, 1, zc.serve_rounds(req.shape), 0, 0, 0, now])
+                        split_n += 1
+                        launched = True
+                        continue
+                    if lane_busy[lane] >= depth:
+                        break
                     del waiting[pick]
                     self._prove_alone(req, now, self.lanes[lane])
                     req._bytes = footprint(req)
@@ -254,6 +310,28 @@ class Server:
                     req._bytes = need
                     mem_used += need
                     active.append([req, slot, 1, zc.serve_rounds(req.shape)])
+                # split requests: the next part when small proofs leave the GPU
+                small_running = sum(1 for e in in_flight if e[2] >= 0)
+                for b in list(bigs):
+                    if b[2] > b[3]:  # every part issued; retires when its last part completes
+                        continue
+                    if b[6] >= (1 if small_running else 2) or (small_running and now - b[7] < self.hold_big_s):
+                        continue
+                    req, slot, rnd, last = b[0], b[1], b[2], b[3]
+                    if b[4] == 0:
+                        b[5] = self._parts(req.shape.mu, rnd, last, req.tile)
+                    self.pool.step_part(slot, rnd, b[4], b[5], req._inst, self.big_stream)
+                    ev = torch.cuda.Event()
+                    ev.record(self.big_stream)
+                    b[4] += 1
+                    finished = False
+                    if b[4] == b[5]:
+                        b[2] += 1
+                        b[4] = 0
+                        finished = b[2] > last
+                    b[6] += 1
+                    in_flight.append([ev, [req] if finished else [], -2, b])
+                    launched = True
                 if active:
                     self.pool.step([a[1] for a in active], [a[2] for a in active], [a[0]._inst for a in active])
                     ev = torch.cuda.Event()
@@ -271,8 +349,8 @@ class Server:
                 for entry in [e for e in in_flight if e[0].query()]:
                     in_flight.remove(entry)
                     retire(entry)
-                while sum(1 for e in in_flight if e[2] < 0) > self.ahead:
-                    entry = next(e for e in in_flight if e[2] < 0)
+                while sum(1 for e in in_flight if e[2] == -1) > self.ahead:
+                    entry = next(e for e in in_flight if e[2] == -1)
                     in_flight.remove(entry)
                     retire(entry)
                 if not launched and not in_flight and not waiting and pending:
@@ -291,5 +369,5 @@ class Server:
             by_mu[str(mu)] = {"n": len(lm), "p50_ms": pct(lm, 50) * 1e3, "p99_ms": pct(lm, 99) * 1e3}
         return {"requests": len(requests), "points": pts, "wall_s": wall, "points_per_s": pts / wall,
                 "p50_ms": pct(lat, 50) * 1e3, "p99_ms": pct(lat, 99) * 1e3, "steps": steps,
-                "fast_path_requests": fast_n,
+                "fast_path_requests": fast_n, "split_requests": split_n,
                 "errors": sum(1 for q in requests if q.err != 0), "by_mu": by_mu}

@@ -73,6 +73,8 @@ _SIGS = {
     "zc_serve_rounds": (ctypes.c_int, [ctypes.POINTER(Shape)]),
     "zc_serve_admit": (ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.c_uint32, _VP, _VP]),
     "zc_serve_step": (ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.c_uint32, _VP, _VP, _VP, _VP]),
+    "zc_serve_step_part": (ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                          ctypes.c_uint32, _VP, _VP]),
 }
 
 
@@ -291,6 +293,11 @@ class ServePool:
         rd = (ctypes.c_uint32 * n)(*rounds)
         arr = (Instance * n)(*insts)
         _check(lib().zc_serve_step(_ptr(self.mem), self.slots, n, sl, rd, arr, _stream(stream)), "zc_serve_step")
+
+    def step_part(self, slot: int, rnd: int, part: int, parts: int, inst: "Instance", stream=None):
+        """zc_serve_step_part: part `part` of `parts` of round `rnd` of one instance."""
+        _check(lib().zc_serve_step_part(_ptr(self.mem), self.slots, slot, rnd, part, parts, ctypes.byref(inst),
+                                        _stream(stream)), "zc_serve_step_part")
 
 
 class HipEvents:

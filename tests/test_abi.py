@@ -165,3 +165,34 @@ def test_batch_host_validation_without_gpu():
     for one in (no_r, misaligned_ws, short_pitch, huge_pitch):
         a1 = (zc.Instance * 1)(one)
         assert h.zc_batch_prove(1, a1, bws, None) == zc.ZC_EINVAL
+
+
+def test_serve_step_part_host_validation_without_gpu():
+    """zc_serve_step_part rejects bad splits before any launch: no pool, a
+    misaligned pool, a slot out of range, round 0 or past zc_serve_rounds,
+    parts 0 or above 64, part >= parts, a split tail round, and a split that
+    would need more than 2048 blocks."""
+    h = zc.lib()
+    fake = 0x1000
+    tabs = (ctypes.c_void_p * 8)(*([fake] * 8))
+    inst = zc.Instance(zc.shape(20, 0), ctypes.cast(tabs, ctypes.c_void_p), fake, fake, fake, fake, fake, 0)
+    pool = ctypes.c_void_p(0x100000)
+    last = h.zc_serve_rounds(ctypes.byref(inst.shape))
+    assert last == 14
+    E = zc.ZC_EINVAL
+    step = h.zc_serve_step_part
+    assert step(None, 4, 0, 1, 0, 2, ctypes.byref(inst), None) == E
+    assert step(ctypes.c_void_p(0x100004), 4, 0, 1, 0, 2, ctypes.byref(inst), None) == E
+    assert step(pool, 4, 4, 1, 0, 2, ctypes.byref(inst), None) == E          # slot out of range
+    assert step(pool, 4, 0, 0, 0, 2, ctypes.byref(inst), None) == E          # round 0
+    assert step(pool, 4, 0, last + 1, 0, 1, ctypes.byref(inst), None) == E   # past the last round
+    assert step(pool, 4, 0, 1, 0, 0, ctypes.byref(inst), None) == E          # no parts
+    assert step(pool, 4, 0, 1, 0, 65, ctypes.byref(inst), None) == E         # too many parts
+    assert step(pool, 4, 0, 1, 2, 2, ctypes.byref(inst), None) == E          # part >= parts
+    assert step(pool, 4, 0, last, 0, 2, ctypes.byref(inst), None) == E       # the tail round split
+    # round 14 of mu = 20 has 64 pairs, one block of the default tile: 64 parts of one block
+    # fit, but a round of 2048 blocks cannot take a part count that rounds its size up past 2048
+    big = zc.Instance(zc.shape(24, 0), ctypes.cast(tabs, ctypes.c_void_p), fake, fake, fake, fake, fake, 1)
+    assert step(pool, 4, 0, 1, 0, 3, ctypes.byref(big), None) == E           # 2048 blocks in 3 parts -> 2049
+    bad = zc.Instance(zc.shape(20, 7), ctypes.cast(tabs, ctypes.c_void_p), fake, fake, fake, fake, fake, 0)
+    assert step(pool, 4, 0, 1, 0, 2, ctypes.byref(bad), None) == zc.ZC_EUNSUPPORTED

@@ -132,12 +132,17 @@ def test_served_large_mix_with_pool_windows_matches_c_oracle():
         return reqs
 
     policies = [dict(fast_queue=0), dict(fast_queue=2),
-                dict(fast_queue=16, lanes=3, big_mu=19, big_lanes=1)]  # every request on the fast path
+                # every request proved whole on the fast path
+                dict(fast_queue=16, lanes=3, big_mu=19, big_lanes=1, split_big=False),
+                # mu >= 19 stepped in parts of 16 blocks beside the fast path
+                dict(fast_queue=16, lanes=3, big_mu=19, big_lanes=1, split_big=True, part_blocks=16)]
     for pol in policies:
         reqs = requests()
         stats = S.Server(slots=6, **pol).run(reqs)
         assert stats["errors"] == 0 and stats["requests"] == len(mix)
         assert (stats["fast_path_requests"] == 0) == (pol["fast_queue"] == 0)
+        if "split_big" in pol:
+            assert (stats["split_requests"] > 0) == pol["split_big"]
         for q, (_, _, alone) in zip(reqs, refs):
             print(f"policy {pol} request {q.rid} mu={q.shape.mu} gate={q.shape.gate} "
                   f"m={q.shape.m} pitch={q.pitch} fast={q.fast_path}", flush=True)
@@ -171,3 +176,51 @@ def test_device_errors_reach_their_own_request(fast_queue):
         if q.rid not in bad:
             got = [o.cpu().numpy() for o in q.outputs]
             assert all(np.array_equal(a, b) for a, b in zip(got, _alone(inst)))
+
+
+def test_split_serve_rounds_give_the_same_bytes():
+    """zc_serve_step_part: every instance's rounds run as 1, 2, 3 or 5 parts
+    (its last round whole), the parts of different instances interleaved on
+    one stream; each result equals zc_prove alone."""
+    import ctypes
+    specs = [(18, 0, 0), (17, 1, 8), (15, 2, 4), (12, 1, 3), (16, 2, 34)]
+    pool = zc.ServePool(len(specs))
+    keep, insts, states = [], [], []
+    for i, (mu, gate, m) in enumerate(specs):
+        inst = I.make_instance(47, i, mu, gate, m, workers=8)
+        s = zc.shape(mu, gate, m)
+        ws = zc.new_workspace(s)
+        tabs = [zc.pack(dev(t), ws) for t in inst.tables]
+        r = dev(inst.r)
+        outs = zc.new_outputs(s)
+        arr = (ctypes.c_void_p * len(tabs))(*[t.data_ptr() for t in tabs])
+        desc = zc.Instance(s, ctypes.cast(arr, ctypes.c_void_p), r.data_ptr(), ws.data_ptr(), outs[0].data_ptr(),
+                           outs[1].data_ptr(), outs[2].data_ptr(), i % 3, 0)
+        pool.admit(i, desc)
+        keep.append((tabs, arr, r, ws))
+        insts.append(inst)
+        states.append([desc, 1, zc.serve_rounds(s), outs])
+    # round-robin over the instances, one part at a time
+    part_counts = (1, 2, 3, 5)
+    pending = {i: [0, None] for i in range(len(specs))}  # instance -> [part, parts of the current round]
+    while pending:
+        for i in list(pending):
+            desc, rnd, last, _ = states[i]
+            part, parts = pending[i]
+            if parts is None:
+                parts = 1 if rnd == last else part_counts[(rnd + i) % len(part_counts)]
+            pool.step_part(i, rnd, part, parts, desc)
+            part += 1
+            if part == parts:
+                states[i][1] += 1
+                part, parts = 0, None
+                if states[i][1] > last:
+                    del pending[i]
+                    continue
+            pending[i] = [part, parts]
+    torch.cuda.synchronize()
+    for i, inst in enumerate(insts):
+        print(f"instance {i} mu={inst.mu} gate={inst.gate} m={inst.m}", flush=True)
+        assert zc.read_error(keep[i][3]) == 0
+        got = [o.cpu().numpy() for o in states[i][3]]
+        assert all(np.array_equal(a, b) for a, b in zip(got, _alone(inst)))
