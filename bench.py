@@ -43,9 +43,9 @@ MADS_PER_MUL = 162  # radix-2^29 Montgomery product: 81 a_i*b_j + 81 m_i*p_j
 # profiles/k_round_fused_hbm_traffic.md.  Valid only for the kernel sources
 # they were taken on (fingerprint below); otherwise traffic is reported null.
 MEASURED_TRAFFIC = {
-    "fingerprint": "a7629b9868377ee2",
-    "plain20_d3": 251236782,
-    "plain20_d9": 238248555,
+    "fingerprint": "46a54a8d56245555",
+    "plain20_d3": 251291429,
+    "plain20_d9": 238249272,
 }
 
 
