@@ -311,7 +311,7 @@ class Server:
                     mem_used += need
                     active.append([req, slot, 1, zc.serve_rounds(req.shape)])
                 # split requests: the next part when small proofs leave the GPU
-                small_running = sum(1 for e in in_flight if e[2] >= 0)
+                small_running = sum(1 for e in in_flight if e[2] >= 0 and not any(self._big(q) for q in e[1]))
                 for b in list(bigs):
                     if b[2] > b[3]:  # every part issued; retires when its last part completes
                         continue
