@@ -71,7 +71,15 @@ enum {
      other streams' kernels.  The proof's bytes do not change; alone, a large
      proof takes a few percent longer.  zc_prove / zc_prove_pitch /
      zc_prove_static only (batches and serving size their own grids). */
-  ZC_FLAG_SHARED_GPU = 2
+  ZC_FLAG_SHARED_GPU = 2,
+  /* The caller asserts that the witness satisfies the gate on the whole
+     hypercube (f_M = 0 at every row), so that G_1(0) = G_1(1) = 0: round 1
+     then evaluates the points X = 2..d+1 only (Sec. 3.3: every hypercube
+     term of H_1(0) and H_1(1) vanishes).  For such a witness the bytes are
+     those of the proof without the flag.  For any other witness the proof
+     is not the honest one (its G_1(0), G_1(1) are 0).  zc_prove /
+     zc_prove_pitch / zc_prove_static only; batches and serving ignore it. */
+  ZC_FLAG_ASSUME_SATISFIED = 4
 };
 
 typedef enum {

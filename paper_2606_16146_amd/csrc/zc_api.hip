@@ -60,7 +60,8 @@ int shape_d(const zc_shape* s) {
 int make_layout(const zc_shape* s, Layout* L) {
   const int k = shape_k(s);
   if (k < 0) return k;
-  if (s->mu < 1 || s->mu > (uint32_t)kMuMax || (s->flags & ~(uint32_t)(ZC_FLAG_CHECK_CLAIMS | ZC_FLAG_SHARED_GPU)))
+  if (s->mu < 1 || s->mu > (uint32_t)kMuMax ||
+      (s->flags & ~(uint32_t)(ZC_FLAG_CHECK_CLAIMS | ZC_FLAG_SHARED_GPU | ZC_FLAG_ASSUME_SATISFIED)))
     return ZC_EINVAL;
   L->k = (uint32_t)k;
   L->d = (uint32_t)shape_d(s);
@@ -169,6 +170,7 @@ RoundArgs round_args(const zc_shape* s, const Layout& L, void* ws, uint32_t i,
   a.eq.mu = s->mu;
   a.check = (s->flags & ZC_FLAG_CHECK_CLAIMS) ? 1u : 0u;
   a.share = (s->flags & ZC_FLAG_SHARED_GPU) ? 1u : 0u;
+  a.skip01 = (i == 1 && (s->flags & ZC_FLAG_ASSUME_SATISFIED)) ? 1u : 0u;
   return a;
 }
 

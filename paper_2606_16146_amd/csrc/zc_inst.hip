@@ -40,7 +40,7 @@ int resident_blocks(const void* kernel) {
   return n;
 }
 
-template <class Gate, bool FOLD, bool SPLIT>
+template <class Gate, bool FOLD, bool SPLIT, int X0 = 0>
 struct RoundTag {};
 template <class Gate>
 struct FinishTag {};
@@ -83,26 +83,36 @@ int launch_round(bool fold, RoundKind kind, RoundArgs a, const TabPtrs& src, con
                  hipEvent_t after) {
   int rc = 0;
   uint32_t blocks;
+  // round 1 under ZC_FLAG_ASSUME_SATISFIED: the kernels that skip X = 0, 1
+  const bool skip = !fold && a.skip01 != 0;
   if (kind == kPerPair) {
     const void* kern = fold ? reinterpret_cast<const void*>(&k_round<Gate, true>)
-                            : reinterpret_cast<const void*>(&k_round<Gate, false>);
+                       : skip ? reinterpret_cast<const void*>(&k_round<Gate, false, 2>)
+                              : reinterpret_cast<const void*>(&k_round<Gate, false>);
     const int per_cu = fold ? resident_blocks<RoundTag<Gate, true, false>>(kern)
-                            : resident_blocks<RoundTag<Gate, false, false>>(kern);
+                       : skip ? resident_blocks<RoundTag<Gate, false, false, 2>>(kern)
+                              : resident_blocks<RoundTag<Gate, false, false>>(kern);
     blocks = round_grid((a.q + kBlock - 1) / kBlock, per_cu, &rc, a.share != 0);
     if (rc) return rc;
     if (fold)
       hipLaunchKernelGGL((k_round<Gate, true>), dim3(blocks), dim3(kBlock), 0, st, a, src, dst);
+    else if (skip)
+      hipLaunchKernelGGL((k_round<Gate, false, 2>), dim3(blocks), dim3(kBlock), 0, st, a, src, dst);
     else
       hipLaunchKernelGGL((k_round<Gate, false>), dim3(blocks), dim3(kBlock), 0, st, a, src, dst);
   } else {
     const void* kern = fold ? reinterpret_cast<const void*>(&k_round_split<Gate, true>)
-                            : reinterpret_cast<const void*>(&k_round_split<Gate, false>);
+                       : skip ? reinterpret_cast<const void*>(&k_round_split<Gate, false, 2>)
+                              : reinterpret_cast<const void*>(&k_round_split<Gate, false>);
     const int per_cu = fold ? resident_blocks<RoundTag<Gate, true, true>>(kern)
-                            : resident_blocks<RoundTag<Gate, false, true>>(kern);
+                       : skip ? resident_blocks<RoundTag<Gate, false, true, 2>>(kern)
+                              : resident_blocks<RoundTag<Gate, false, true>>(kern);
     blocks = round_grid((a.q + kSplitPairs - 1) / kSplitPairs, per_cu, &rc);
     if (rc) return rc;
     if (fold)
       hipLaunchKernelGGL((k_round_split<Gate, true>), dim3(blocks), dim3(kBlock), 0, st, a, src, dst);
+    else if (skip)
+      hipLaunchKernelGGL((k_round_split<Gate, false, 2>), dim3(blocks), dim3(kBlock), 0, st, a, src, dst);
     else
       hipLaunchKernelGGL((k_round_split<Gate, false>), dim3(blocks), dim3(kBlock), 0, st, a, src, dst);
   }

@@ -54,6 +54,15 @@ struct Unroll<N, N> {
   __device__ __forceinline__ static void run(F&) {}
 };
 
+// lo + N dl by N additions: the extension at the first evaluated point when
+// the points below N are skipped (the same additions as stepping up to it).
+template <int N>
+__device__ __forceinline__ Fe ext_at(Fe lo, const Fe& dl) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) lo = fe_add(lo, dl);
+  return lo;
+}
+
 // Converts a loaded pair to (lo, dl) = (t[j], t[j+q] - t[j] mod p).
 __device__ __forceinline__ void cvt_pair(const RawPair& r, Fe& lo, Fe& dl) {
   lo = fe_from_words(r.w0);
@@ -219,7 +228,8 @@ struct GateVanilla {
     const Fe t5 = fe_mul(e[6], e[2]);                 // qO*c < 2p
     return fe_add(fe_add(fe_add(t3, t4), t5), e[7]);  // < 11p
   }
-  template <class Src>
+  // X0 = 2: only the points X >= 2 (round 1 under ZC_FLAG_ASSUME_SATISFIED)
+  template <class Src, int X0 = 0>
   __device__ static __forceinline__ void eval(const Src& src, const EqRows& er, Fe (&acc)[NH]) {
     // lazy differences: every extension at X <= 3 is < 6p
     Fe bx[NH], s[NH], lo, dl, e;
@@ -230,31 +240,35 @@ struct GateVanilla {
     typename Src::Raw ra = src.issue(0);   // a
     typename Src::Raw rr = src.issue(5);   // qR
     auto fb = [&](auto x) __attribute__((always_inline)) {
-      bx[x] = (x == 0) ? lo : fe_add(bx[x > 0 ? x - 1 : 0], dl);
+      bx[x] = (x == X0) ? ext_at<X0>(lo, dl) : fe_add(bx[x > X0 ? x - 1 : X0], dl);
     };
-    Unroll<0, NH>::run(fb);
+    Unroll<X0, NH>::run(fb);
     src.getl(rm, 3, lo, dl);  // qM
     typename Src::Raw ro = src.issue(6);   // qO
     typename Src::Raw rc = src.issue(2);   // c
-    e = lo;
+    e = ext_at<X0>(lo, dl);
     auto f1 = [&](auto x) __attribute__((always_inline)) {
       s[x] = fe_mul(e, bx[x]);  // < 2p (6*6)
       e = fe_add(e, dl);
     };
-    Unroll<0, NH>::run(f1);
+    Unroll<X0, NH>::run(f1);
     src.getl(rl, 4, lo, dl);  // qL
     typename Src::Raw rq = src.issue(7);   // qC
-    e = lo;
+    e = ext_at<X0>(lo, dl);
     auto f2 = [&](auto x) __attribute__((always_inline)) {
       s[x] = fe_add(s[x], e);  // < 8p
       e = fe_add(e, dl);
     };
-    Unroll<0, NH>::run(f2);
+    Unroll<X0, NH>::run(f2);
     Fe ea, da, er5, dr5, eo, dlo, ec, dc;
     src.getl(ra, 0, ea, da);    // a
     src.getl(rr, 5, er5, dr5);  // qR
     src.getl(ro, 6, eo, dlo);   // qO
     src.getl(rc, 2, ec, dc);    // c
+    ea = ext_at<X0>(ea, da);
+    er5 = ext_at<X0>(er5, dr5);
+    eo = ext_at<X0>(eo, dlo);
+    ec = ext_at<X0>(ec, dc);
     auto f3 = [&](auto x) __attribute__((always_inline)) {
       const Fe fa[3] = {ea, er5, eo};
       const Fe fb2[3] = {s[x], bx[x], ec};
@@ -264,16 +278,16 @@ struct GateVanilla {
       eo = fe_add(eo, dlo);
       ec = fe_add(ec, dc);
     };
-    Unroll<0, NH>::run(f3);
+    Unroll<X0, NH>::run(f3);
     src.getl(rq, 7, lo, dl);  // qC
     const Fe E = resolve_eq(er);
-    e = lo;
+    e = ext_at<X0>(lo, dl);
     auto f6 = [&](auto x) __attribute__((always_inline)) {
       const Fe f = fe_add(s[x], e);           // < 8p
       acc[x] = fe_add(acc[x], fe_mul(f, E));  // product < 2p (8*1)
       e = fe_add(e, dl);
     };
-    Unroll<0, NH>::run(f6);
+    Unroll<X0, NH>::run(f6);
   }
 };
 
@@ -299,7 +313,7 @@ struct GateProd {
   // The field elements summed are the same.
   static constexpr bool kEqInS = M >= 3;
   static constexpr int kExtraAcc = kEqInS ? 2 : 0;
-  template <int NA>
+  template <int NA, int X0 = 0>
   __device__ static __forceinline__ void finalize(Fe (&acc)[NA]) {
     if constexpr (kEqInS) {
       // acc[x] -= acc[NH] + x acc[NH+1]  (all < p: the sums were reduced)
@@ -307,10 +321,10 @@ struct GateProd {
         const Fe t = fe_reduce32(fe_add(acc[NH], fe_mul_small(acc[NH + 1], (uint32_t)x)));  // < p + 10p
         acc[x] = fe_submod(acc[x], t);
       };
-      Unroll<0, NH>::run(f);
+      Unroll<X0, NH>::run(f);
     }
   }
-  template <class Src, int NA>
+  template <class Src, int NA, int X0 = 0>
   __device__ static __forceinline__ void eval(const Src& src, const EqRows& er, Fe (&acc)[NA]) {
     // s and w1 with strict differences (extensions at X <= m+1 < (m+2) p <= 10p,
     // so their product fits: 10*10), the other tables lazy (< 2(m+1) p <= 18p)
@@ -327,9 +341,9 @@ struct GateProd {
       dl = fe_reduce2(fe_mul(E, dl));
     }
     auto f0 = [&](auto x) __attribute__((always_inline)) {
-      pr[x] = (x == 0) ? lo : fe_add(pr[x > 0 ? x - 1 : 0], dl);
+      pr[x] = (x == X0) ? ext_at<X0>(lo, dl) : fe_add(pr[x > X0 ? x - 1 : X0], dl);
     };
-    Unroll<0, NH>::run(f0);
+    Unroll<X0, NH>::run(f0);
 #pragma unroll 1
     for (int k = 1; k <= M; ++k) {  // pr *= w_k  (< 2p after each product: 10*10, then 2*18)
       cur = nxt;
@@ -338,28 +352,28 @@ struct GateProd {
         src.get(cur, k, lo, dl);
       else
         src.getl(cur, k, lo, dl);
-      e = lo;
+      e = ext_at<X0>(lo, dl);
       auto fk = [&](auto x) __attribute__((always_inline)) {
         pr[x] = fe_mul(pr[x], e);
         e = fe_add(e, dl);
       };
-      Unroll<0, NH>::run(fk);
+      Unroll<X0, NH>::run(fk);
     }
     src.getl(nxt, M + 1, lo, dl);  // o (< 18p): pr + 18p - o < 20p
     if constexpr (kEqInS) {
       auto fe = [&](auto x) __attribute__((always_inline)) { acc[x] = fe_add(acc[x], pr[x]); };  // pr < 2p
-      Unroll<0, NH>::run(fe);
+      Unroll<X0, NH>::run(fe);
       acc[NH] = fe_add(acc[NH], fe_reduce2(fe_mul(E, lo)));          // < p (o[lo] < p)
       acc[NH + 1] = fe_add(acc[NH + 1], fe_reduce2(fe_mul(E, dl)));  // < p (1*2 <= 128, then reduced)
     } else {
       E = resolve_eq(er);
-      e = lo;
+      e = ext_at<X0>(lo, dl);
       auto fo = [&](auto x) __attribute__((always_inline)) {
         const Fe f = fe_sub_plus(pr[x], e, kP18);
         acc[x] = fe_add(acc[x], fe_mul(f, E));  // product < 2p (20*1)
         e = fe_add(e, dl);
       };
-      Unroll<0, NH>::run(fo);
+      Unroll<X0, NH>::run(fo);
     }
   }
 };
@@ -383,7 +397,7 @@ struct GateSum {
     Unroll<P, K>::run(ad);
     return f;
   }
-  template <class Src>
+  template <class Src, int X0 = 0>
   __device__ static __forceinline__ void eval(const Src& src, const EqRows& er, Fe (&acc)[NH]) {
     // lazy differences: extensions at X <= P are < 2P p <= 8p
     Fe f[NH], lo, dl;
@@ -391,14 +405,14 @@ struct GateSum {
     typename Src::Raw nxt = src.issue(1);
     src.getl(cur, 0, lo, dl);
     auto f0 = [&](auto x) __attribute__((always_inline)) {
-      f[x] = (x == 0) ? lo : fe_add(f[x > 0 ? x - 1 : 0], dl);
+      f[x] = (x == X0) ? ext_at<X0>(lo, dl) : fe_add(f[x > X0 ? x - 1 : X0], dl);
     };
-    Unroll<0, NH>::run(f0);
+    Unroll<X0, NH>::run(f0);
     auto step = [&](auto k) __attribute__((always_inline)) {
       cur = nxt;
       if (k + 1 < K) nxt = src.issue(k + 1 < K ? k + 1 : 0);
       src.getl(cur, k, lo, dl);
-      Fe e = lo;
+      Fe e = ext_at<X0>(lo, dl);
       auto px = [&](auto x) __attribute__((always_inline)) {
         if (k < P)
           f[x] = fe_mul(f[x], e);  // < 2p (8*8, then 2*8)
@@ -406,14 +420,14 @@ struct GateSum {
           f[x] = fe_add(f[x], e);  // < 26p after A <= 3 additions
         e = fe_add(e, dl);
       };
-      Unroll<0, NH>::run(px);
+      Unroll<X0, NH>::run(px);
     };
     Unroll<1, K>::run(step);
     const Fe E = resolve_eq(er);
     auto fo = [&](auto x) __attribute__((always_inline)) {
       acc[x] = fe_add(acc[x], fe_mul(f[x], E));  // product < 2p (26*1)
     };
-    Unroll<0, NH>::run(fo);
+    Unroll<X0, NH>::run(fo);
   }
 };
 
@@ -553,6 +567,7 @@ struct RoundArgs {
   uint32_t check;              // 1: the verifier's claim checks on the device (ZC_FLAG_CHECK_CLAIMS)
   uint32_t share;              // host only: round grids sized for a shared GPU (ZC_FLAG_SHARED_GPU)
   uint32_t signal;             // 1: the finisher also posts alpha_i to the mailbox (k_fin_wait)
+  uint32_t skip01;             // host only: round 1 skips X = 0, 1 (ZC_FLAG_ASSUME_SATISFIED)
 };
 
 // Montgomery product reduced below p.
@@ -814,21 +829,38 @@ constexpr uint32_t kLazyPairs = 32;
 template <class Gate, class = void>
 struct GateAcc {
   static constexpr int kExtra = 0;
-  template <int NA>
+  template <int NA, int X0 = 0>
   __device__ static __forceinline__ void finalize(Fe (&)[NA]) {}
 };
 template <class Gate>
 struct GateAcc<Gate, std::void_t<decltype(Gate::kExtraAcc)>> {
   static constexpr int kExtra = Gate::kExtraAcc;
-  template <int NA>
+  template <int NA, int X0 = 0>
   __device__ static __forceinline__ void finalize(Fe (&acc)[NA]) {
-    Gate::finalize(acc);
+    Gate::template finalize<NA, X0>(acc);
   }
 };
 
-template <class Gate, bool FOLD>
+// Evaluation of one pair at the points X0..NH-1 (X0 = 0: all of them).  The
+// gates with extra accumulators take their count as a template argument.
+template <class Gate, class = void>
+struct EvalTakesNA : std::false_type {};
+template <class Gate>
+struct EvalTakesNA<Gate, std::void_t<decltype(Gate::kExtraAcc)>> : std::true_type {};
+template <class Gate, int X0, class Src, int NA>
+__device__ __forceinline__ void gate_eval(const Src& src, const EqRows& er, Fe (&acc)[NA]) {
+  if constexpr (EvalTakesNA<Gate>::value)
+    Gate::template eval<Src, NA, X0>(src, er, acc);
+  else
+    Gate::template eval<Src, X0>(src, er, acc);
+}
+
+// X0 = 2 (round 1 only, ZC_FLAG_ASSUME_SATISFIED): the points 0 and 1 are not
+// evaluated and their sums stay 0.
+template <class Gate, bool FOLD, int X0 = 0>
 __device__ __forceinline__ void round_body(const RoundArgs& a, const TabPtrs& src, const TabPtrs& dst, uint32_t blk,
                                            uint32_t nblk) {
+  static_assert(X0 == 0 || !FOLD, "only round 1 skips points");
   constexpr int NH = Gate::NH;
   constexpr int NA = NH + GateAcc<Gate>::kExtra;
   Fe acc[NA];
@@ -847,7 +879,7 @@ __device__ __forceinline__ void round_body(const RoundArgs& a, const TabPtrs& sr
       for (uint32_t j = j0; j < jend; j += stride) {
         const EqRows er = issue_eq(a.eq, a.round, j);
         if (FOLD && Gate::kFoldInGate) {
-          Gate::eval(FoldSrc{src, dst, a.src_pitch, a.dst_pitch, j, q, alpha}, er, acc);
+          gate_eval<Gate, 0>(FoldSrc{src, dst, a.src_pitch, a.dst_pitch, j, q, alpha}, er, acc);
         } else if (FOLD) {
           // fold every table first (a rolled loop: one copy of the code), then
           // evaluate on the folded pairs, which the L2 still holds (so the
@@ -864,9 +896,9 @@ __device__ __forceinline__ void round_body(const RoundArgs& a, const TabPtrs& sr
             store_el(dst.p[t], dp, j, fe_lerp(fe_from_words(c01.w0), fe_from_words(c23.w0), alpha));
             store_el(dst.p[t], dp, j + q, fe_lerp(fe_from_words(c01.w1), fe_from_words(c23.w1), alpha));
           }
-          Gate::eval(PairSrc{dst, dp, j, q}, er, acc);
+          gate_eval<Gate, 0>(PairSrc{dst, dp, j, q}, er, acc);
         } else {
-          Gate::eval(PairSrcT<true>{src, a.src_pitch, j, q}, er, acc);
+          gate_eval<Gate, X0>(PairSrcT<true>{src, a.src_pitch, j, q}, er, acc);
         }
       }
       Unroll<0, NA>::run(lower);
@@ -874,7 +906,7 @@ __device__ __forceinline__ void round_body(const RoundArgs& a, const TabPtrs& sr
   }
   auto red = [&](auto x) __attribute__((always_inline)) { acc[x] = fe_reduce2(acc[x]); };  // < 2p after lower
   Unroll<0, NA>::run(red);
-  GateAcc<Gate>::finalize(acc);  // every acc[x] < p again
+  GateAcc<Gate>::template finalize<NA, X0>(acc);  // every acc[x] < p again
   Fe pts[NH];
   auto cp = [&](auto x) __attribute__((always_inline)) { pts[x] = acc[x]; };
   Unroll<0, NH>::run(cp);
@@ -882,9 +914,9 @@ __device__ __forceinline__ void round_body(const RoundArgs& a, const TabPtrs& sr
   if (threadIdx.x < NH) store_words_fe(a.partials + ((uint64_t)blk * part_stride(NH) + threadIdx.x) * 8, tot);
 }
 
-template <class Gate, bool FOLD>
+template <class Gate, bool FOLD, int X0 = 0>
 __global__ __launch_bounds__(kBlock) void k_round(RoundArgs a, TabPtrs src, TabPtrs dst) {
-  round_body<Gate, FOLD>(a, src, dst, blockIdx.x, gridDim.x);
+  round_body<Gate, FOLD, X0>(a, src, dst, blockIdx.x, gridDim.x);
 }
 
 // ---- lane-split rounds: 16 lanes per pair -------------------------------------------
@@ -1217,10 +1249,11 @@ __device__ __forceinline__ Fe wait_alpha(Ctrl* ctrl, uint32_t round, uint32_t* b
 // WAIT (FOLD only): alpha_{i-1} comes from the mailbox once block 0 of the
 // same launch has posted it; the block's first loads are issued before the
 // wait, so their latency overlaps the hash.
-template <class Gate, bool FOLD, bool WAIT>
+template <class Gate, bool FOLD, bool WAIT, int X0 = 0>
 __device__ __forceinline__ void split_body(const RoundArgs& a, const TabPtrs& srct, const TabPtrs& dstt, uint32_t blk,
                                            uint32_t nblk) {
   static_assert(FOLD || !WAIT, "only a folding round waits for its challenge");
+  static_assert(X0 == 0 || !FOLD, "only round 1 skips points");
   constexpr int K = Gate::K;
   constexpr int NH = Gate::NH;
   __shared__ uint32_t sh[kSplitPairs][K][2][NL];
@@ -1277,7 +1310,7 @@ __device__ __forceinline__ void split_body(const RoundArgs& a, const TabPtrs& sr
         lds_put(sh[pl][g][1], u1);
       }
       __syncthreads();
-      if (j < q && g < (uint32_t)NH) {
+      if (j < q && g < (uint32_t)NH && g >= (uint32_t)X0) {
         auto get = [&](int t, Fe& v0, Fe& v1) __attribute__((always_inline)) {
           v0 = lds_fe(sh[pl][t][0]);
           v1 = lds_fe(sh[pl][t][1]);
@@ -1294,9 +1327,9 @@ __device__ __forceinline__ void split_body(const RoundArgs& a, const TabPtrs& sr
 
 // Round with 16 lanes per pair; the grid strides over the pairs and is sized
 // like k_round's.
-template <class Gate, bool FOLD>
+template <class Gate, bool FOLD, int X0 = 0>
 __global__ __launch_bounds__(kBlock) void k_round_split(RoundArgs a, TabPtrs srct, TabPtrs dstt) {
-  split_body<Gate, FOLD, false>(a, srct, dstt, blockIdx.x, gridDim.x);
+  split_body<Gate, FOLD, false, X0>(a, srct, dstt, blockIdx.x, gridDim.x);
 }
 
 // ---- speculative rounds (gates of degree <= 3) -----------------------------------------

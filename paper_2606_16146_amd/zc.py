@@ -21,6 +21,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 ZC_OK, ZC_EINVAL, ZC_EUNSUPPORTED, ZC_EHIP, ZC_ERANGE, ZC_ESTATE, ZC_ETOOBIG, ZC_ECLAIM = 0, -1, -2, -3, -4, -5, -6, -7
 ZC_FLAG_CHECK_CLAIMS = 1
 ZC_FLAG_SHARED_GPU = 2
+ZC_FLAG_ASSUME_SATISFIED = 4
 GATE_VANILLA, GATE_PROD, GATE_SUMPROD = 0, 1, 2
 
 

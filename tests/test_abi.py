@@ -42,8 +42,8 @@ def test_invalid_shapes(mu, gate, m):
 
 
 def test_unknown_flags_are_rejected():
-    assert zc.workspace_bytes(zc.shape(10, 0, 0, 4)) == 0
-    both = zc.ZC_FLAG_CHECK_CLAIMS | zc.ZC_FLAG_SHARED_GPU
+    assert zc.workspace_bytes(zc.shape(10, 0, 0, 8)) == 0
+    both = zc.ZC_FLAG_CHECK_CLAIMS | zc.ZC_FLAG_SHARED_GPU | zc.ZC_FLAG_ASSUME_SATISFIED
     assert zc.workspace_bytes(zc.shape(10, 0, 0, both)) == zc.workspace_bytes(zc.shape(10, 0))
     assert zc.workspace_bytes(zc.shape(10, 0, 0, zc.ZC_FLAG_CHECK_CLAIMS)) == zc.workspace_bytes(zc.shape(10, 0))
 

@@ -291,3 +291,38 @@ def test_shared_gpu_grids_give_the_same_bytes(zc, mu, gate, m):
         outs.append([o.cpu().numpy() for o in zc.prove(s, tabs, dev(inst.r), ws)])
         assert zc.read_error(ws) == 0
     assert all(np.array_equal(a, b) for a, b in zip(*outs))
+
+
+@pytest.mark.parametrize("mu,gate,m", [(3, 0, 0), (9, 1, 8), (12, 0, 0), (17, 0, 0), (20, 1, 8), (18, 1, 2),
+                                       (10, 2, 34), (11, 2, 4), (6, 1, 5)])
+def test_assume_satisfied_gives_the_same_bytes_on_satisfying_witnesses(zc, mu, gate, m):
+    """ZC_FLAG_ASSUME_SATISFIED: round 1 evaluates X >= 2 only (thread per
+    pair or 16 lanes per pair, every gate family, with and without the
+    product gate's separate o sums); on a witness that satisfies the gate the
+    proof is byte for byte the one without the flag, i.e. the oracle's."""
+    inst = I.make_instance(84, mu, mu, gate, m, workers=8)
+    outs = []
+    for flags in (0, zc.ZC_FLAG_ASSUME_SATISFIED):
+        s = zc.shape(mu, gate, m, flags)
+        ws = zc.new_workspace(s)
+        tabs = [zc.pack(dev(t), ws) for t in inst.tables]
+        outs.append([o.cpu().numpy() for o in zc.prove(s, tabs, dev(inst.r), ws)])
+        assert zc.read_error(ws) == 0
+    assert all(np.array_equal(a, b) for a, b in zip(*outs))
+    assert not outs[0][0][0, :2].any()  # G_1(0) = G_1(1) = 0 for a satisfying witness
+
+
+def test_assume_satisfied_on_a_nonsatisfying_witness_zeroes_round_1(zc):
+    """With the flag the caller's assertion is taken as given: on a witness
+    that does not satisfy the gate, G_1(0) and G_1(1) come out 0 (the honest
+    proof's do not) while G_1(2), G_1(3) are still evaluated."""
+    inst = I.make_instance(85, 0, 10, 0, 0, satisfying=False)
+    res = []
+    for flags in (0, zc.ZC_FLAG_ASSUME_SATISFIED):
+        s = zc.shape(10, 0, 0, flags)
+        ws = zc.new_workspace(s)
+        tabs = [zc.pack(dev(t), ws) for t in inst.tables]
+        res.append([o.cpu().numpy() for o in zc.prove(s, tabs, dev(inst.r), ws)])
+    honest, flagged = res
+    assert honest[0][0, :2].any() and not flagged[0][0, :2].any()
+    assert np.array_equal(honest[0][0, 2:4], flagged[0][0, 2:4])
