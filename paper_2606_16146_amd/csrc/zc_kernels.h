@@ -711,6 +711,15 @@ __device__ __forceinline__ void emit_round(Ctrl* ctrl, uint32_t round, FinLds<D>
   constexpr uint32_t LEN = FinLds<D>::LEN, NB = FinLds<D>::NB;
   static_assert(NH <= 16, "one 16-lane group");
   const uint32_t t = threadIdx.x;
+  // the state lanes (see below) load their eq1-row factor now, so that its
+  // latency overlaps the G step; the rows are written at setup only
+  const uint32_t sk = t - 128, sl = sk % ((uint32_t)NC + 1);
+  const bool st_lane = t >= 128 && t < 128 + 2 * ((uint32_t)NC + 1), sq = sk > (uint32_t)NC;
+  Fe sf = fe_zero();
+  if (st_lane) {
+    const Eq1Row* row = eq1_rows(ctrl) + (round - 1);
+    sf = load_words_fe(sl == (uint32_t)NC ? (sq ? row->tr2 : row->omr) : (sq ? row->v[sl] : row->u[sl]));
+  }
   if (t < 64) {
     // wave 0, lanes x <= d: G(x) = coef[x] H(x)
     if (t < (uint32_t)NH) {
@@ -751,17 +760,13 @@ __device__ __forceinline__ void emit_round(Ctrl* ctrl, uint32_t round, FinLds<D>
     sha256_first16(v, S.msg);
   } else if (t >= 64 && t < 64 + NB) {
     sha256_expand_block<LEN>(S.msg, S.kw, t - 64);
-  } else if (t >= 128 && t < 128 + 2 * ((uint32_t)NC + 1)) {
+  } else if (st_lane) {
     // the state of round+1, one product with C_i R per lane (the eq1 row
-    // holds the other factor): lanes 128 + l (l < NC): nu_l, lane 128 + NC:
-    // npr, lanes 128 + NC + 1 + l: nv_l, lane 128 + 2 NC + 1: nqr
-    const uint32_t k = t - 128, l = k % ((uint32_t)NC + 1);
-    const bool qv = k > (uint32_t)NC;
-    const Eq1Row* row = eq1_rows(ctrl) + (round - 1);
-    const uint32_t* f = l == (uint32_t)NC ? (qv ? row->tr2 : row->omr) : (qv ? row->v[l] : row->u[l]);
-    const Fe y = mont(fe_vgpr(lds_fe(S.cm)), load_words_fe(f));
-    lds_put(l == (uint32_t)NC ? (qv ? S.q2 : S.pc) : (qv ? S.v[l] : S.u[l]), y);
-    store_words_fe(l == (uint32_t)NC ? (qv ? ctrl->nqr : ctrl->npr) : (qv ? ctrl->nv[l] : ctrl->nu[l]), y);
+    // holds the other factor, sf): lanes 128 + l (l < NC): nu_l, lane
+    // 128 + NC: npr, lanes 128 + NC + 1 + l: nv_l, lane 128 + 2 NC + 1: nqr
+    const Fe y = mont(fe_vgpr(lds_fe(S.cm)), sf);
+    lds_put(sl == (uint32_t)NC ? (sq ? S.q2 : S.pc) : (sq ? S.v[sl] : S.u[sl]), y);
+    store_words_fe(sl == (uint32_t)NC ? (sq ? ctrl->nqr : ctrl->npr) : (sq ? ctrl->nv[sl] : ctrl->nu[sl]), y);
   } else if (check && t == kBlock - 1) {
     // self-check (Sec. 3.4): G_i(0) + G_i(1) = G_{i-1}(alpha_{i-1}), the claim
     // of round i-1 (0 before round 1)
@@ -1130,20 +1135,26 @@ __device__ __forceinline__ void run_tail(const RoundArgs& a, const TabPtrs& dst,
 #pragma unroll
     for (int k = 0; k < 8; ++k) w[k] = S.ac[k];
     const Fe ac = fe_vgpr(fe_from_words(w));
-    const Fe alpha = fe_to_mont(ac);
     const uint32_t h = L / 2;
-    for (uint32_t idx = tid; idx < K * h; idx += blockDim.x) {
-      const uint32_t t = idx / h, e = idx % h;
-      const Fe u0 = lds_fe(T(t, e)), u1 = lds_fe(T(t, e + h));
-      lds_put(T(t, e), fe_lerp(u0, u1, alpha));
-    }
+    auto fold = [&](uint32_t first, uint32_t step) __attribute__((always_inline)) {
+      const Fe alpha = fe_to_mont(ac);
+      for (uint32_t idx = first; idx < K * h; idx += step) {
+        const uint32_t t = idx / h, e = idx % h;
+        const Fe u0 = lds_fe(T(t, e)), u1 = lds_fe(T(t, e + h));
+        lds_put(T(t, e), fe_lerp(u0, u1, alpha));
+      }
+    };
+    // round r was evaluated during round r-1's hash (spec_r): its message
+    // needs no folded table, so waves 1-3 fold during round r's hash, before
+    // they speculate on round r+1
+    const bool spec_r = SPECT && r >= a.round + 2 && r <= a.mu;
+    if (!spec_r) fold(tid, blockDim.x);
     if (tid < (uint32_t)NC) {
       if (r <= a.mu) lds_put(S.cf[tid], fe_addmod(lds_fe(S.u[tid]), mont(ac, lds_fe(S.v[tid]))));
     } else if (tid == (uint32_t)NC) {
       lds_put(S.cm, fe_addmod(fe_vgpr(lds_fe(S.pc)), mont(ac, fe_vgpr(lds_fe(S.q2)))));
     }
-    // round r was evaluated during round r-1's hash: the weights L_c(alpha_{r-1})
-    const bool spec_r = SPECT && r >= a.round + 2 && r <= a.mu;
+    // spec_r: the weights L_c(alpha_{r-1})
     Fe lcr = fe_zero();
     const uint32_t sx = tid & 3u, sc = (tid >> 2) & 3u;
     if constexpr (SPECT) {
@@ -1165,7 +1176,12 @@ __device__ __forceinline__ void run_tail(const RoundArgs& a, const TabPtrs& dst,
       }
       __syncthreads();
       auto side = [&]() __attribute__((always_inline)) {
-        if constexpr (SPECT) tail_speculate<Gate>(r, L, a.mu, T, U, eqrow, HSP, RED3, CTR, bar_target);
+        if constexpr (SPECT) {
+          fold(tid - 64, blockDim.x - 64);
+          bar_target += 3;
+          waves123_barrier(CTR, bar_target);
+          tail_speculate<Gate>(r, L, a.mu, T, U, eqrow, HSP, RED3, CTR, bar_target);
+        }
       };
       emit_round<Gate::D>(a.ctrl, r, S, a.evals_out + (uint64_t)(r - a.round) * Gate::NE * 8,
                           a.alpha_out + (uint64_t)(r - a.round) * 8, a.check != 0, side);
