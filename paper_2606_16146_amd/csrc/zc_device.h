@@ -51,10 +51,11 @@ struct Ctrl {
   uint32_t npr[8];                  // C_i (1 - r_i) R
   uint32_t nqr[8];                  // C_i (2 r_i - 1) R^2
   // Mailbox of a launch whose block 0 finishes round i-1 while its other
-  // blocks wait to evaluate round i: alpha_{i-1} and then i-1, both written
-  // and read with device-coherent (agent-scope) accesses.
-  uint32_t mbox_alpha[8];
-  uint32_t mbox_round;
+  // blocks wait to evaluate round i: word k is (i-1) << 32 | word k of
+  // alpha_{i-1}, each written and read as one 64-bit device-coherent
+  // (agent-scope) access, so a reader that finds the tag i-1 in all eight
+  // words holds the whole challenge, whatever order the words landed in.
+  uint64_t mbox[8];
 };
 
 constexpr uint32_t kCtrlBytes = 4096;

@@ -699,10 +699,9 @@ struct NoSideWork {
 // `side` runs on waves 1..3 while lane 0 compresses the message after its
 // first 16 rounds (the hash's serial part); it must not use __syncthreads.
 //
-// With `signal`, lane 0 also posts alpha_i and then i to the control block's
-// mailbox with device-coherent stores, the second only once the first have
-// completed, for the blocks of the same launch that wait for alpha_i
-// (k_fin_wait).
+// With `signal`, lane 0 also posts alpha_i to the control block's mailbox,
+// each word tagged with i (see Ctrl::mbox), before its other stores, for the
+// blocks of the same launch that wait for alpha_i (k_fin_wait).
 template <int D, class Side = NoSideWork>
 __device__ __forceinline__ void emit_round(Ctrl* ctrl, uint32_t round, FinLds<D>& S, uint32_t* evals_out,
                                            uint32_t* alpha_out, bool check, Side side = Side{},
@@ -789,6 +788,12 @@ __device__ __forceinline__ void emit_round(Ctrl* ctrl, uint32_t round, FinLds<D>
     al = fe_csub(fe_csub(fe_csub(al, kP4), kP2), kP);
     uint32_t w[8];
     fe_to_words(al, w);
+    if (signal) {
+      // the mailbox first, so that its stores leave ahead of the others
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        __hip_atomic_store(&ctrl->mbox[k], (uint64_t)round << 32 | w[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       S.msg[k] = dg[k];
@@ -798,12 +803,6 @@ __device__ __forceinline__ void emit_round(Ctrl* ctrl, uint32_t round, FinLds<D>
       alpha_out[k] = w[k];
     }
     ctrl->round_done = round;
-    if (signal) {
-#pragma unroll
-      for (int k = 0; k < 8; ++k) __hip_atomic_store(&ctrl->mbox_alpha[k], w[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the alpha words have completed
-      __hip_atomic_store(&ctrl->mbox_round, round, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
   } else if (t >= 64) {
     side();
   }
@@ -1234,25 +1233,29 @@ __device__ __forceinline__ void run_tail(const RoundArgs& a, const TabPtrs& dst,
   if (tid == K) store_words_fe(a.openings + K * 8, fe_from_mont(fe_vgpr(lds_fe(S.cm))));
 }
 
-// alpha_{round} for the blocks of a k_fin_wait launch: lane 0 polls the
-// mailbox (device-coherent loads) until block 0 has posted round `round`, or
-// a device error is set, or ~10 ms have passed (then ZC_ESTATE: the bytes are
-// wrong but every block ends); the block then reads alpha from LDS.  All
-// threads of the block call it (it has a barrier).
+// alpha_{round} for the blocks of a k_fin_wait launch: lanes 0..7 poll the
+// eight mailbox words (one device-coherent 64-bit load each, together one
+// request) until every word carries the tag `round`, or a device error is
+// set, or ~10 ms have passed (then ZC_ESTATE: the bytes are wrong but every
+// block ends); the block then reads alpha from LDS.  The exits are uniform
+// over the eight lanes.  All threads of the block call it (it has a barrier).
 constexpr uint64_t kWaitTicks = 1000000;  // s_memrealtime runs at 100 MHz
 __device__ __forceinline__ Fe wait_alpha(Ctrl* ctrl, uint32_t round, uint32_t* box) {
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < 8) {
+    const uint32_t k = threadIdx.x;
     const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-    while (__hip_atomic_load(&ctrl->mbox_round, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < round) {
+    uint64_t m;
+    for (;;) {
+      m = __hip_atomic_load(&ctrl->mbox[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (__all((uint32_t)(m >> 32) == round)) break;
       if (__hip_atomic_load(&ctrl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
       if (__builtin_amdgcn_s_memrealtime() - t0 > kWaitTicks) {
-        set_error(ctrl, -5);
+        if (k == 0) set_error(ctrl, -5);
         break;
       }
       __builtin_amdgcn_s_sleep(2);
     }
-#pragma unroll
-    for (int k = 0; k < 8; ++k) box[k] = __hip_atomic_load(&ctrl->mbox_alpha[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    box[k] = (uint32_t)m;
   }
   __syncthreads();
   uint32_t w[8];
@@ -1645,7 +1648,7 @@ struct ServeStep {
 static_assert(sizeof(ServeStep) <= 4096 - 64, "kernel argument size");
 
 __device__ __forceinline__ RoundArgs batch_round_args(const InstDesc& d, uint32_t round, uint32_t nparts) {
-  RoundArgs a;
+  RoundArgs a{};  // every field set: signal, share and skip01 stay 0 here
   const uint64_t n = 1ull << d.mu;
   a.src_pitch = round <= 2 ? d.pitch : n / 2;
   a.dst_pitch = round == 1 ? d.pitch : n / 2;

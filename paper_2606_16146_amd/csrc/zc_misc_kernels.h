@@ -33,7 +33,8 @@ __device__ __forceinline__ void setup_body(const uint32_t* __restrict__ r, uint3
     ctrl->err = 0;
     ctrl->round_done = 0;
     ctrl->fold_done = 0;
-    __hip_atomic_store(&ctrl->mbox_round, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) __hip_atomic_store(&ctrl->mbox[k], (uint64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     store_words_fe(ctrl->npr, fe_const(kOne));
     store_words_fe(ctrl->nqr, fe_zero());
   }
