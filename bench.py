@@ -255,7 +255,12 @@ def run_workload(name, steps, warmup, cpu_baseline):
            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic}
     alu = {"bound": "alu", "achieved": round(tops, 2), "peak": round(MAD_PEAK_TOPS, 2),
            "unit": "TOP/s (v_mad_u64_u32)", "frac": round(tops / MAD_PEAK_TOPS, 4), "traffic": traffic}
-    common = {"kernel": f"k_round<{'GateVanilla' if gate == 0 else f'GateProd<{m}>'}, true>",
+    kname = f"k_round<{'GateVanilla' if gate == 0 else f'GateProd<{m}>'}, true>"
+    last = max((i for i in range(2, mu + 1) if kinds[i - 1] == 0), default=1)
+    if gate != 0 and (1 << (mu - last)) <= 32768:
+        # the last of these rounds, at 32768 pairs or fewer, runs two waves per 64 pairs
+        kname += f" (round {last} in the two-wave form, k_round<..., true, 0, true>)"
+    common = {"kernel": kname,
               "traffic_unit": "HBM bytes per launch (PMC, copy-calibrated)",
               "launches": launches, "avg_launch_us": round(avg_launch_s * 1e6, 2),
               "algorithmic_bytes_per_launch": fused_b // launches,

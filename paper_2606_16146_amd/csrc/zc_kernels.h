@@ -174,6 +174,7 @@ struct FoldSrc {
   uint64_t sp, dp;
   uint32_t j, q;
   Fe alpha;
+  bool st = true;  // store the folded pair (a second wave folding the same pairs does not)
   struct Raw {
     RawPair lo2, hi2;  // (t[j], t[j+q]), (t[j+2q], t[j+3q])
   };
@@ -183,8 +184,10 @@ struct FoldSrc {
   __device__ __forceinline__ void fold(const Raw& r, int t, Fe& u0, Fe& u1) const {
     u0 = fe_lerp(fe_from_words(r.lo2.w0), fe_from_words(r.hi2.w0), alpha);
     u1 = fe_lerp(fe_from_words(r.lo2.w1), fe_from_words(r.hi2.w1), alpha);
-    store_el<true>(dst.p[t], dp, j, u0);
-    store_el<true>(dst.p[t], dp, j + q, u1);
+    if (st) {
+      store_el<true>(dst.p[t], dp, j, u0);
+      store_el<true>(dst.p[t], dp, j + q, u1);
+    }
   }
   __device__ __forceinline__ void get(const Raw& r, int t, Fe& lo, Fe& dl) const {
     Fe u1;
@@ -229,7 +232,7 @@ struct GateVanilla {
     return fe_add(fe_add(fe_add(t3, t4), t5), e[7]);  // < 11p
   }
   // X0 = 2: only the points X >= 2 (round 1 under ZC_FLAG_ASSUME_SATISFIED)
-  template <class Src, int X0 = 0>
+  template <class Src, int X0 = 0, int XE = NH>
   __device__ static __forceinline__ void eval(const Src& src, const EqRows& er, Fe (&acc)[NH]) {
     // lazy differences: every extension at X <= 3 is < 6p
     Fe bx[NH], s[NH], lo, dl, e;
@@ -242,7 +245,7 @@ struct GateVanilla {
     auto fb = [&](auto x) __attribute__((always_inline)) {
       bx[x] = (x == X0) ? ext_at<X0>(lo, dl) : fe_add(bx[x > X0 ? x - 1 : X0], dl);
     };
-    Unroll<X0, NH>::run(fb);
+    Unroll<X0, XE>::run(fb);
     src.getl(rm, 3, lo, dl);  // qM
     typename Src::Raw ro = src.issue(6);   // qO
     typename Src::Raw rc = src.issue(2);   // c
@@ -251,7 +254,7 @@ struct GateVanilla {
       s[x] = fe_mul(e, bx[x]);  // < 2p (6*6)
       e = fe_add(e, dl);
     };
-    Unroll<X0, NH>::run(f1);
+    Unroll<X0, XE>::run(f1);
     src.getl(rl, 4, lo, dl);  // qL
     typename Src::Raw rq = src.issue(7);   // qC
     e = ext_at<X0>(lo, dl);
@@ -259,7 +262,7 @@ struct GateVanilla {
       s[x] = fe_add(s[x], e);  // < 8p
       e = fe_add(e, dl);
     };
-    Unroll<X0, NH>::run(f2);
+    Unroll<X0, XE>::run(f2);
     Fe ea, da, er5, dr5, eo, dlo, ec, dc;
     src.getl(ra, 0, ea, da);    // a
     src.getl(rr, 5, er5, dr5);  // qR
@@ -278,7 +281,7 @@ struct GateVanilla {
       eo = fe_add(eo, dlo);
       ec = fe_add(ec, dc);
     };
-    Unroll<X0, NH>::run(f3);
+    Unroll<X0, XE>::run(f3);
     src.getl(rq, 7, lo, dl);  // qC
     const Fe E = resolve_eq(er);
     e = ext_at<X0>(lo, dl);
@@ -287,7 +290,7 @@ struct GateVanilla {
       acc[x] = fe_add(acc[x], fe_mul(f, E));  // product < 2p (8*1)
       e = fe_add(e, dl);
     };
-    Unroll<X0, NH>::run(f6);
+    Unroll<X0, XE>::run(f6);
   }
 };
 
@@ -313,7 +316,7 @@ struct GateProd {
   // The field elements summed are the same.
   static constexpr bool kEqInS = M >= 3;
   static constexpr int kExtraAcc = kEqInS ? 2 : 0;
-  template <int NA, int X0 = 0>
+  template <int NA, int X0 = 0, int XE = NH>
   __device__ static __forceinline__ void finalize(Fe (&acc)[NA]) {
     if constexpr (kEqInS) {
       // acc[x] -= acc[NH] + x acc[NH+1]  (all < p: the sums were reduced)
@@ -321,10 +324,10 @@ struct GateProd {
         const Fe t = fe_reduce32(fe_add(acc[NH], fe_mul_small(acc[NH + 1], (uint32_t)x)));  // < p + 10p
         acc[x] = fe_submod(acc[x], t);
       };
-      Unroll<X0, NH>::run(f);
+      Unroll<X0, XE>::run(f);
     }
   }
-  template <class Src, int NA, int X0 = 0>
+  template <class Src, int NA, int X0 = 0, int XE = NH>
   __device__ static __forceinline__ void eval(const Src& src, const EqRows& er, Fe (&acc)[NA]) {
     // s and w1 with strict differences (extensions at X <= m+1 < (m+2) p <= 10p,
     // so their product fits: 10*10), the other tables lazy (< 2(m+1) p <= 18p)
@@ -343,7 +346,7 @@ struct GateProd {
     auto f0 = [&](auto x) __attribute__((always_inline)) {
       pr[x] = (x == X0) ? ext_at<X0>(lo, dl) : fe_add(pr[x > X0 ? x - 1 : X0], dl);
     };
-    Unroll<X0, NH>::run(f0);
+    Unroll<X0, XE>::run(f0);
 #pragma unroll 1
     for (int k = 1; k <= M; ++k) {  // pr *= w_k  (< 2p after each product: 10*10, then 2*18)
       cur = nxt;
@@ -357,12 +360,12 @@ struct GateProd {
         pr[x] = fe_mul(pr[x], e);
         e = fe_add(e, dl);
       };
-      Unroll<X0, NH>::run(fk);
+      Unroll<X0, XE>::run(fk);
     }
     src.getl(nxt, M + 1, lo, dl);  // o (< 18p): pr + 18p - o < 20p
     if constexpr (kEqInS) {
       auto fe = [&](auto x) __attribute__((always_inline)) { acc[x] = fe_add(acc[x], pr[x]); };  // pr < 2p
-      Unroll<X0, NH>::run(fe);
+      Unroll<X0, XE>::run(fe);
       acc[NH] = fe_add(acc[NH], fe_reduce2(fe_mul(E, lo)));          // < p (o[lo] < p)
       acc[NH + 1] = fe_add(acc[NH + 1], fe_reduce2(fe_mul(E, dl)));  // < p (1*2 <= 128, then reduced)
     } else {
@@ -373,7 +376,7 @@ struct GateProd {
         acc[x] = fe_add(acc[x], fe_mul(f, E));  // product < 2p (20*1)
         e = fe_add(e, dl);
       };
-      Unroll<X0, NH>::run(fo);
+      Unroll<X0, XE>::run(fo);
     }
   }
 };
@@ -397,7 +400,7 @@ struct GateSum {
     Unroll<P, K>::run(ad);
     return f;
   }
-  template <class Src, int X0 = 0>
+  template <class Src, int X0 = 0, int XE = NH>
   __device__ static __forceinline__ void eval(const Src& src, const EqRows& er, Fe (&acc)[NH]) {
     // lazy differences: extensions at X <= P are < 2P p <= 8p
     Fe f[NH], lo, dl;
@@ -407,7 +410,7 @@ struct GateSum {
     auto f0 = [&](auto x) __attribute__((always_inline)) {
       f[x] = (x == X0) ? ext_at<X0>(lo, dl) : fe_add(f[x > X0 ? x - 1 : X0], dl);
     };
-    Unroll<X0, NH>::run(f0);
+    Unroll<X0, XE>::run(f0);
     auto step = [&](auto k) __attribute__((always_inline)) {
       cur = nxt;
       if (k + 1 < K) nxt = src.issue(k + 1 < K ? k + 1 : 0);
@@ -420,14 +423,14 @@ struct GateSum {
           f[x] = fe_add(f[x], e);  // < 26p after A <= 3 additions
         e = fe_add(e, dl);
       };
-      Unroll<X0, NH>::run(px);
+      Unroll<X0, XE>::run(px);
     };
     Unroll<1, K>::run(step);
     const Fe E = resolve_eq(er);
     auto fo = [&](auto x) __attribute__((always_inline)) {
       acc[x] = fe_add(acc[x], fe_mul(f[x], E));  // product < 2p (26*1)
     };
-    Unroll<X0, NH>::run(fo);
+    Unroll<X0, XE>::run(fo);
   }
 };
 
@@ -833,39 +836,51 @@ constexpr uint32_t kLazyPairs = 32;
 template <class Gate, class = void>
 struct GateAcc {
   static constexpr int kExtra = 0;
-  template <int NA, int X0 = 0>
+  template <int NA, int X0 = 0, int XE = 0>
   __device__ static __forceinline__ void finalize(Fe (&)[NA]) {}
 };
 template <class Gate>
 struct GateAcc<Gate, std::void_t<decltype(Gate::kExtraAcc)>> {
   static constexpr int kExtra = Gate::kExtraAcc;
-  template <int NA, int X0 = 0>
+  template <int NA, int X0 = 0, int XE = Gate::NH>
   __device__ static __forceinline__ void finalize(Fe (&acc)[NA]) {
-    Gate::template finalize<NA, X0>(acc);
+    Gate::template finalize<NA, X0, XE>(acc);
   }
 };
 
-// Evaluation of one pair at the points X0..NH-1 (X0 = 0: all of them).  The
+// Evaluation of one pair at the points X0..XE-1 (0..NH-1: all of them).  The
 // gates with extra accumulators take their count as a template argument.
 template <class Gate, class = void>
 struct EvalTakesNA : std::false_type {};
 template <class Gate>
 struct EvalTakesNA<Gate, std::void_t<decltype(Gate::kExtraAcc)>> : std::true_type {};
-template <class Gate, int X0, class Src, int NA>
+template <class Gate, int X0, int XE = Gate::NH, class Src, int NA>
 __device__ __forceinline__ void gate_eval(const Src& src, const EqRows& er, Fe (&acc)[NA]) {
   if constexpr (EvalTakesNA<Gate>::value)
-    Gate::template eval<Src, NA, X0>(src, er, acc);
+    Gate::template eval<Src, NA, X0, XE>(src, er, acc);
   else
-    Gate::template eval<Src, X0>(src, er, acc);
+    Gate::template eval<Src, X0, XE>(src, er, acc);
 }
 
 // X0 = 2 (round 1 only, ZC_FLAG_ASSUME_SATISFIED): the points 0 and 1 are not
 // evaluated and their sums stay 0.
-template <class Gate, bool FOLD, int X0 = 0>
+//
+// HALF (a round that folds inside the gate's evaluation, with fewer pairs
+// than one wave per SIMD holds): waves 2v and 2v+1 of a block take the same
+// 64 pairs; both fold them, the first evaluates the points [0, NH/2) and
+// stores the folded pairs, the second evaluates [NH/2, NH).  Each point's sum comes from the wave that owns it
+// (the other holds 0 there), so the block sums are the same field elements.
+// Twice the waves, each with about half the products.
+template <class Gate, bool FOLD, int X0 = 0, bool HALF = false>
 __device__ __forceinline__ void round_body(const RoundArgs& a, const TabPtrs& src, const TabPtrs& dst, uint32_t blk,
                                            uint32_t nblk) {
   static_assert(X0 == 0 || !FOLD, "only round 1 skips points");
+  static_assert(!HALF || (FOLD && X0 == 0 && Gate::kFoldInGate), "halves split a round that folds in the gate");
   constexpr int NH = Gate::NH;
+  constexpr int XM = HALF ? NH / 2 : NH;
+  const uint32_t half = HALF ? (threadIdx.x >> 6) & 1u : 0u;
+  const uint32_t slot = HALF ? ((threadIdx.x >> 7) << 6) | (threadIdx.x & 63u) : threadIdx.x;
+  const uint32_t slots = HALF ? blockDim.x / 2 : blockDim.x;  // pairs per block and pass
   constexpr int NA = NH + GateAcc<Gate>::kExtra;
   Fe acc[NA];
   auto z = [&](auto x) __attribute__((always_inline)) { acc[x] = fe_zero(); };
@@ -876,14 +891,18 @@ __device__ __forceinline__ void round_body(const RoundArgs& a, const TabPtrs& sr
     Fe alpha;
     if (FOLD) alpha = fe_to_mont(fe_vgpr(load_words_fe(a.ctrl->alpha[a.round - 2])));
     const uint32_t q = (uint32_t)a.q;
-    const uint32_t stride = nblk * blockDim.x;
+    const uint32_t stride = nblk * slots;
     // chunks of kLazyPairs pairs per thread, the sums lowered after each
-    for (uint32_t j0 = blk * blockDim.x + threadIdx.x; j0 < q; j0 += kLazyPairs * stride) {
+    for (uint32_t j0 = blk * slots + slot; j0 < q; j0 += kLazyPairs * stride) {
       const uint32_t jend = (uint32_t)min((uint64_t)q, (uint64_t)j0 + (uint64_t)kLazyPairs * stride);
       for (uint32_t j = j0; j < jend; j += stride) {
         const EqRows er = issue_eq(a.eq, a.round, j);
         if (FOLD && Gate::kFoldInGate) {
-          gate_eval<Gate, 0>(FoldSrc{src, dst, a.src_pitch, a.dst_pitch, j, q, alpha}, er, acc);
+          const FoldSrc fs{src, dst, a.src_pitch, a.dst_pitch, j, q, alpha, half == 0};
+          if (half == 0)
+            gate_eval<Gate, 0, XM>(fs, er, acc);
+          else
+            gate_eval<Gate, XM, NH>(fs, er, acc);
         } else if (FOLD) {
           // fold every table first (a rolled loop: one copy of the code), then
           // evaluate on the folded pairs, which the L2 still holds (so the
@@ -910,7 +929,10 @@ __device__ __forceinline__ void round_body(const RoundArgs& a, const TabPtrs& sr
   }
   auto red = [&](auto x) __attribute__((always_inline)) { acc[x] = fe_reduce2(acc[x]); };  // < 2p after lower
   Unroll<0, NA>::run(red);
-  GateAcc<Gate>::template finalize<NA, X0>(acc);  // every acc[x] < p again
+  if (half == 0)
+    GateAcc<Gate>::template finalize<NA, X0, XM>(acc);  // every acc[x] < p again
+  else
+    GateAcc<Gate>::template finalize<NA, XM, NH>(acc);
   Fe pts[NH];
   auto cp = [&](auto x) __attribute__((always_inline)) { pts[x] = acc[x]; };
   Unroll<0, NH>::run(cp);
@@ -918,9 +940,9 @@ __device__ __forceinline__ void round_body(const RoundArgs& a, const TabPtrs& sr
   if (threadIdx.x < NH) store_words_fe(a.partials + ((uint64_t)blk * part_stride(NH) + threadIdx.x) * 8, tot);
 }
 
-template <class Gate, bool FOLD, int X0 = 0>
+template <class Gate, bool FOLD, int X0 = 0, bool HALF = false>
 __global__ __launch_bounds__(kBlock) void k_round(RoundArgs a, TabPtrs src, TabPtrs dst) {
-  round_body<Gate, FOLD, X0>(a, src, dst, blockIdx.x, gridDim.x);
+  round_body<Gate, FOLD, X0, HALF>(a, src, dst, blockIdx.x, gridDim.x);
 }
 
 // ---- lane-split rounds: 16 lanes per pair -------------------------------------------
