@@ -140,17 +140,15 @@ template <class Gate>
 int launch_spec(ZC_SPEC_ARGS) {
   int rc = 0;
   if (step == kSpecRoundOnly) {
-    if constexpr (Gate::kFoldInGate) {
-      if (sa.q <= kHalfQ) {
-        // two waves per 64 pairs (round_body HALF)
-        const void* kern = reinterpret_cast<const void*>(&k_round<Gate, true, 0, true>);
-        const int per_cu = resident_blocks<RoundTag<Gate, true, false, 0, true>>(kern);
-        const uint32_t b = round_grid((2 * sa.q + kBlock - 1) / kBlock, per_cu, &rc, sa.share != 0);
-        if (rc) return rc;
-        hipLaunchKernelGGL((k_round<Gate, true, 0, true>), dim3(b), dim3(kBlock), 0, st, sa, src, dst);
-        *blocks = b;
-        return launch_ok();
-      }
+    if (sa.q <= kHalfQ) {
+      // two waves per 64 pairs (round_body HALF)
+      const void* kern = reinterpret_cast<const void*>(&k_round<Gate, true, 0, true>);
+      const int per_cu = resident_blocks<RoundTag<Gate, true, false, 0, true>>(kern);
+      const uint32_t b = round_grid((2 * sa.q + kBlock - 1) / kBlock, per_cu, &rc, sa.share != 0);
+      if (rc) return rc;
+      hipLaunchKernelGGL((k_round<Gate, true, 0, true>), dim3(b), dim3(kBlock), 0, st, sa, src, dst);
+      *blocks = b;
+      return launch_ok();
     }
     const void* kern = reinterpret_cast<const void*>(&k_round<Gate, true>);
     const int per_cu = resident_blocks<RoundTag<Gate, true, false>>(kern);

@@ -292,6 +292,73 @@ struct GateVanilla {
     };
     Unroll<X0, XE>::run(f6);
   }
+  // The two waves of a two-wave round (round_body HALF) split the terms of
+  // f_M, each at every point: H = 0 adds E a (qM b + qL), H = 1 adds
+  // E (qR b + qO c + qC); the two sums of a point add up to the same field
+  // element.  Both fold on the way (FoldSrc): H = 0 stores a, b, qM, qL,
+  // H = 1 stores c, qR, qO, qC and reads b through `nb`, which does not store.
+  template <int H, class Src>
+  __device__ static __forceinline__ void eval_terms(const Src& src, const Src& nb, const EqRows& er, Fe (&acc)[NH]) {
+    if constexpr (H == 0) {
+      Fe bx[NH], s[NH], lo, dl, e;
+      typename Src::Raw rb = src.issue(1);  // b
+      typename Src::Raw rm = src.issue(3);  // qM
+      src.getl(rb, 1, lo, dl);
+      typename Src::Raw rl = src.issue(4);  // qL
+      auto fb = [&](auto x) __attribute__((always_inline)) { bx[x] = x == 0 ? lo : fe_add(bx[x > 0 ? x - 1 : 0], dl); };
+      Unroll<0, NH>::run(fb);
+      src.getl(rm, 3, lo, dl);
+      typename Src::Raw ra = src.issue(0);  // a
+      e = lo;
+      auto f1 = [&](auto x) __attribute__((always_inline)) {
+        s[x] = fe_mul(e, bx[x]);  // < 2p (6*6)
+        e = fe_add(e, dl);
+      };
+      Unroll<0, NH>::run(f1);
+      src.getl(rl, 4, lo, dl);
+      e = lo;
+      auto f2 = [&](auto x) __attribute__((always_inline)) {
+        s[x] = fe_add(s[x], e);  // < 8p
+        e = fe_add(e, dl);
+      };
+      Unroll<0, NH>::run(f2);
+      src.getl(ra, 0, lo, dl);
+      // E a(X) = E a[lo] + X E a[dl], both products < p: extensions < 4p
+      const Fe E = resolve_eq(er);
+      Fe ea = fe_reduce2(fe_mul(E, lo));
+      const Fe da = fe_reduce2(fe_mul(E, dl));  // (1*2)
+      auto f3 = [&](auto x) __attribute__((always_inline)) {
+        acc[x] = fe_add(acc[x], fe_mul(ea, s[x]));  // product < 2p (4*8)
+        ea = fe_add(ea, da);
+      };
+      Unroll<0, NH>::run(f3);
+    } else {
+      Fe lb, db, lr, dr, lo, dO, lc, dc, lq, dq;
+      typename Src::Raw rb = nb.issue(1);   // b
+      typename Src::Raw rr = src.issue(5);  // qR
+      nb.getl(rb, 1, lb, db);
+      typename Src::Raw ro = src.issue(6);  // qO
+      src.getl(rr, 5, lr, dr);
+      typename Src::Raw rc = src.issue(2);  // c
+      src.getl(ro, 6, lo, dO);
+      typename Src::Raw rq = src.issue(7);  // qC
+      src.getl(rc, 2, lc, dc);
+      src.getl(rq, 7, lq, dq);
+      const Fe E = resolve_eq(er);
+      auto f4 = [&](auto x) __attribute__((always_inline)) {
+        const Fe fa[2] = {lr, lo};
+        const Fe fb2[2] = {lb, lc};
+        const Fe u = fe_add(fe_sop<2>(fa, fb2), lq);  // qR b + qO c < 2p (6*6 + 6*6), + qC < 8p
+        acc[x] = fe_add(acc[x], fe_mul(u, E));       // product < 2p (8*1)
+        lr = fe_add(lr, dr);
+        lo = fe_add(lo, dO);
+        lb = fe_add(lb, db);
+        lc = fe_add(lc, dc);
+        lq = fe_add(lq, dq);
+      };
+      Unroll<0, NH>::run(f4);
+    }
+  }
 };
 
 // f = s*w1*...*wm - o, columns [s w1 .. wm o], degree m+1.
@@ -865,17 +932,20 @@ __device__ __forceinline__ void gate_eval(const Src& src, const EqRows& er, Fe (
 // X0 = 2 (round 1 only, ZC_FLAG_ASSUME_SATISFIED): the points 0 and 1 are not
 // evaluated and their sums stay 0.
 //
-// HALF (a round that folds inside the gate's evaluation, with fewer pairs
-// than one wave per SIMD holds): waves 2v and 2v+1 of a block take the same
-// 64 pairs; both fold them, the first evaluates the points [0, NH/2) and
-// stores the folded pairs, the second evaluates [NH/2, NH).  Each point's sum comes from the wave that owns it
-// (the other holds 0 there), so the block sums are the same field elements.
-// Twice the waves, each with about half the products.
+// HALF (a folding round with fewer pairs than one wave per SIMD holds):
+// waves 2v and 2v+1 of a block take the same 64 pairs.  For gates that fold
+// inside their evaluation both fold every table, the first evaluates the
+// points [0, NH/2) and stores the folded pairs, the second evaluates
+// [NH/2, NH); each point's sum comes from the wave that owns it (the other
+// holds 0 there).  The vanilla gate splits its terms instead
+// (GateVanilla::eval_terms), each wave folding and storing the tables its
+// terms use.  Either way the block sums are the same field elements, from
+// twice the waves, each with about half the products.
 template <class Gate, bool FOLD, int X0 = 0, bool HALF = false>
 __device__ __forceinline__ void round_body(const RoundArgs& a, const TabPtrs& src, const TabPtrs& dst, uint32_t blk,
                                            uint32_t nblk) {
   static_assert(X0 == 0 || !FOLD, "only round 1 skips points");
-  static_assert(!HALF || (FOLD && X0 == 0 && Gate::kFoldInGate), "halves split a round that folds in the gate");
+  static_assert(!HALF || (FOLD && X0 == 0), "halves split a folding round");
   constexpr int NH = Gate::NH;
   constexpr int XM = HALF ? NH / 2 : NH;
   const uint32_t half = HALF ? (threadIdx.x >> 6) & 1u : 0u;
@@ -903,6 +973,16 @@ __device__ __forceinline__ void round_body(const RoundArgs& a, const TabPtrs& sr
             gate_eval<Gate, 0, XM>(fs, er, acc);
           else
             gate_eval<Gate, XM, NH>(fs, er, acc);
+        } else if (FOLD && HALF) {
+          if constexpr (HALF && !Gate::kFoldInGate) {
+            const FoldSrc fs{src, dst, a.src_pitch, a.dst_pitch, j, q, alpha, true};
+            if (half == 0) {
+              Gate::template eval_terms<0>(fs, fs, er, acc);
+            } else {
+              const FoldSrc nb{src, dst, a.src_pitch, a.dst_pitch, j, q, alpha, false};
+              Gate::template eval_terms<1>(fs, nb, er, acc);
+            }
+          }
         } else if (FOLD) {
           // fold every table first (a rolled loop: one copy of the code), then
           // evaluate on the folded pairs, which the L2 still holds (so the

@@ -25,9 +25,8 @@ constexpr int kTailQ = 32;  // the tail runs rounds with at most this many pairs
 inline uint64_t split_q(uint32_t) { return 16384u; }
 
 // The last thread-per-pair round before the fused lane-split rounds runs two
-// waves per 64 pairs when it has at most this many pairs (gates that fold
-// inside their evaluation): 32768 pairs are 512 waves, one for half the SIMDs
-// of 256 CUs.
+// waves per 64 pairs when it has at most this many pairs: 32768 pairs are 512
+// waves, one for half the SIMDs of 256 CUs.
 constexpr uint64_t kHalfQ = 32768;
 
 enum RoundKind { kPerPair = 0, kSplit = 1, kSplitTail = 2, kInTail = 3, kSpec = 4, kSpecTail = 5 };
