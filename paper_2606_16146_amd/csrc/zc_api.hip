@@ -223,6 +223,11 @@ int prove_impl(const zc_shape* shape, const uint32_t* const* tables, const uint3
                            reinterpret_cast<uint32_t*>(bytes(ws) + L.specparts) + (size_t)kSpecBlocks * 16 * 8};
   uint32_t prev_blocks = 0;      // partial-sum blocks of the previous launch (speculative schedule)
   uint32_t* prev_parts = nullptr;
+  // The folded tables of the fused rounds.  The last thread-per-pair round
+  // runs in its two-wave form out of place when it is small enough
+  // (kHalfQ): it reads entries [0, 4q) of each folded table and writes
+  // [4q, 6q), and the later rounds fold in place from there.
+  TabPtrs cur = fold;
   for (uint32_t i = 1; i <= mu; ++i) {
     const RoundKind kind = prove_round_kind(mu, i, L.d);
     if (sp.on && (i + 1 == sp.s0 || kind == kSpec || kind == kSpecTail)) {
@@ -235,7 +240,10 @@ int prove_impl(const zc_shape* shape, const uint32_t* const* tables, const uint3
       if (ev && hipEventRecord(ev[2 * (i - 1)], stream) != hipSuccess) return ZC_EHIP;
       uint32_t blocks = 0;
       if (i + 1 == sp.s0) {
-        rc = dispatch_spec(shape, kSpecRoundOnly, sa, fold, sa, i <= 2 ? orig : fold, fold, stream, &blocks);
+        const uint64_t hq = shape->gate == ZC_GATE_VANILLA ? kHalfQVanilla : kHalfQ;
+        if (i >= 3 && sa.q <= hq && 6 * sa.q <= half)
+          for (uint32_t t = 0; t < L.k; ++t) cur.p[t] = fold.p[t] + 4 * sa.q;
+        rc = dispatch_spec(shape, kSpecRoundOnly, sa, cur, sa, i <= 2 ? orig : fold, cur, stream, &blocks);
         prev_parts = sa.partials;
       } else {
         RoundArgs fa = round_args(shape, L, ws, i - 1, round_evals, challenges);
@@ -243,7 +251,7 @@ int prove_impl(const zc_shape* shape, const uint32_t* const* tables, const uint3
         fa.partials = prev_parts;
         sa.partials = spec_buf[i & 1];
         sa.src_pitch = sa.dst_pitch = half;
-        rc = dispatch_spec(shape, i == sp.s0 ? kSpecFirst : kSpecNext, fa, fold, sa, fold, fold, stream, &blocks);
+        rc = dispatch_spec(shape, i == sp.s0 ? kSpecFirst : kSpecNext, fa, cur, sa, cur, cur, stream, &blocks);
         prev_parts = sa.partials;
       }
       if (rc != ZC_OK) return rc;
@@ -256,7 +264,7 @@ int prove_impl(const zc_shape* shape, const uint32_t* const* tables, const uint3
         fa.tail = 1;
         fa.openings = openings;
         fa.src_pitch = fa.dst_pitch = half;
-        if ((rc = dispatch_spec(shape, kSpecFinishTail, fa, fold, fa, fold, fold, stream, &blocks)) != ZC_OK) return rc;
+        if ((rc = dispatch_spec(shape, kSpecFinishTail, fa, cur, fa, cur, cur, stream, &blocks)) != ZC_OK) return rc;
       }
       continue;
     }

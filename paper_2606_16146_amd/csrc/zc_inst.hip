@@ -42,6 +42,11 @@ int resident_blocks(const void* kernel) {
 
 template <class Gate, bool FOLD, bool SPLIT, int X0 = 0, bool HALF = false>
 struct RoundTag {};
+
+template <class Gate>
+constexpr uint64_t half_q() {
+  return Gate::kFoldInGate ? kHalfQ : kHalfQVanilla;
+}
 template <class Gate>
 struct FinishTag {};
 template <class Gate>
@@ -85,7 +90,15 @@ int launch_round(bool fold, RoundKind kind, RoundArgs a, const TabPtrs& src, con
   uint32_t blocks;
   // round 1 under ZC_FLAG_ASSUME_SATISFIED: the kernels that skip X = 0, 1
   const bool skip = !fold && a.skip01 != 0;
-  if (kind == kPerPair) {
+  if (kind == kPerPair && fold && a.q <= half_q<Gate>() && src.p[0] != dst.p[0]) {
+    // two waves per 64 pairs (round_body HALF), never in place: both waves
+    // read every pair that one of them then overwrites
+    const void* kern = reinterpret_cast<const void*>(&k_round<Gate, true, 0, true>);
+    const int per_cu = resident_blocks<RoundTag<Gate, true, false, 0, true>>(kern);
+    blocks = round_grid((2 * a.q + kBlock - 1) / kBlock, per_cu, &rc, a.share != 0);
+    if (rc) return rc;
+    hipLaunchKernelGGL((k_round<Gate, true, 0, true>), dim3(blocks), dim3(kBlock), 0, st, a, src, dst);
+  } else if (kind == kPerPair) {
     const void* kern = fold ? reinterpret_cast<const void*>(&k_round<Gate, true>)
                        : skip ? reinterpret_cast<const void*>(&k_round<Gate, false, 2>)
                               : reinterpret_cast<const void*>(&k_round<Gate, false>);
@@ -140,8 +153,9 @@ template <class Gate>
 int launch_spec(ZC_SPEC_ARGS) {
   int rc = 0;
   if (step == kSpecRoundOnly) {
-    if (sa.q <= kHalfQ) {
-      // two waves per 64 pairs (round_body HALF)
+    if (sa.q <= half_q<Gate>() && src.p[0] != dst.p[0]) {
+      // two waves per 64 pairs (round_body HALF), never in place (see
+      // launch_round); the proof moves its folded tables for it
       const void* kern = reinterpret_cast<const void*>(&k_round<Gate, true, 0, true>);
       const int per_cu = resident_blocks<RoundTag<Gate, true, false, 0, true>>(kern);
       const uint32_t b = round_grid((2 * sa.q + kBlock - 1) / kBlock, per_cu, &rc, sa.share != 0);

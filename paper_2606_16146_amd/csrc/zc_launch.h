@@ -24,10 +24,13 @@ constexpr int kTailQ = 32;  // the tail runs rounds with at most this many pairs
 // and 8192 measured the same and 4096 slower).
 inline uint64_t split_q(uint32_t) { return 16384u; }
 
-// The last thread-per-pair round before the fused lane-split rounds runs two
-// waves per 64 pairs when it has at most this many pairs: 32768 pairs are 512
-// waves, one for half the SIMDs of 256 CUs.
+// Folding thread-per-pair rounds run two waves per 64 pairs when they have at
+// most this many pairs: 32768 pairs are 512 waves, one for half the SIMDs of
+// 256 CUs.  kHalfQ for the gates that fold inside their evaluation (whose two
+// waves both fold every table), kHalfQVanilla for the vanilla gate (whose
+// waves split its terms and tables).
 constexpr uint64_t kHalfQ = 32768;
+constexpr uint64_t kHalfQVanilla = 32768;
 
 enum RoundKind { kPerPair = 0, kSplit = 1, kSplitTail = 2, kInTail = 3, kSpec = 4, kSpecTail = 5 };
 
