@@ -223,11 +223,22 @@ int prove_impl(const zc_shape* shape, const uint32_t* const* tables, const uint3
                            reinterpret_cast<uint32_t*>(bytes(ws) + L.specparts) + (size_t)kSpecBlocks * 16 * 8};
   uint32_t prev_blocks = 0;      // partial-sum blocks of the previous launch (speculative schedule)
   uint32_t* prev_parts = nullptr;
-  // The folded tables of the fused rounds.  The last thread-per-pair round
-  // runs in its two-wave form out of place when it is small enough
-  // (kHalfQ): it reads entries [0, 4q) of each folded table and writes
-  // [4q, 6q), and the later rounds fold in place from there.
+  // The folded tables the next round reads.  A thread-per-pair round from
+  // round 3 on folds in place, except in its two-wave form (small enough,
+  // kHalfQ), which runs out of place: it reads entries [0, 4q) of each folded
+  // table and writes [4q, 6q), and the later rounds continue from there
+  // (coff: that offset from the start of the folded tables).
   TabPtrs cur = fold;
+  uint64_t coff = 0;
+  const uint64_t hq = shape->gate == ZC_GATE_VANILLA ? kHalfQVanilla : kHalfQ;
+  auto moved = [&](uint64_t q) {
+    TabPtrs d = cur;
+    if (coff + 6 * q <= half) {
+      for (uint32_t t = 0; t < L.k; ++t) d.p[t] = cur.p[t] + 4 * q;
+      coff += 4 * q;
+    }
+    return d;
+  };
   for (uint32_t i = 1; i <= mu; ++i) {
     const RoundKind kind = prove_round_kind(mu, i, L.d);
     if (sp.on && (i + 1 == sp.s0 || kind == kSpec || kind == kSpecTail)) {
@@ -240,10 +251,9 @@ int prove_impl(const zc_shape* shape, const uint32_t* const* tables, const uint3
       if (ev && hipEventRecord(ev[2 * (i - 1)], stream) != hipSuccess) return ZC_EHIP;
       uint32_t blocks = 0;
       if (i + 1 == sp.s0) {
-        const uint64_t hq = shape->gate == ZC_GATE_VANILLA ? kHalfQVanilla : kHalfQ;
-        if (i >= 3 && sa.q <= hq && 6 * sa.q <= half)
-          for (uint32_t t = 0; t < L.k; ++t) cur.p[t] = fold.p[t] + 4 * sa.q;
-        rc = dispatch_spec(shape, kSpecRoundOnly, sa, cur, sa, i <= 2 ? orig : fold, cur, stream, &blocks);
+        const TabPtrs src = i <= 2 ? orig : cur;
+        if (i >= 3 && sa.q <= hq) cur = moved(sa.q);
+        rc = dispatch_spec(shape, kSpecRoundOnly, sa, cur, sa, src, cur, stream, &blocks);
         prev_parts = sa.partials;
       } else {
         RoundArgs fa = round_args(shape, L, ws, i - 1, round_evals, challenges);
@@ -278,8 +288,9 @@ int prove_impl(const zc_shape* shape, const uint32_t* const* tables, const uint3
     a.openings = openings;
     a.src_pitch = i <= 2 ? tp : half;
     a.dst_pitch = i == 1 ? tp : half;
-    const TabPtrs& src = i <= 2 ? orig : fold;
-    const TabPtrs& dst = i == 1 ? orig : fold;
+    const TabPtrs src = i <= 2 ? orig : cur;
+    if (i >= 3 && kind == kPerPair && a.q <= hq) cur = moved(a.q);
+    const TabPtrs dst = i == 1 ? orig : cur;
     if (ev && hipEventRecord(ev[2 * (i - 1)], stream) != hipSuccess) return ZC_EHIP;
     if ((rc = dispatch_round(shape, i > 1, kind, a, src, dst, stream, ev ? ev[2 * (i - 1) + 1] : nullptr)) != ZC_OK)
       return rc;
