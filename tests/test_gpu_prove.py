@@ -214,6 +214,23 @@ def test_profiled_prove_equals_prove(zc):
     assert all(ev.elapsed_ms(2 * i, 2 * i + 1) >= 0 for i in range(17))
 
 
+@pytest.mark.parametrize("mu,gate,m,seed", [(17, 0, 0, 1), (19, 0, 0, 2), (19, 1, 8, 3), (19, 2, 18, 4),
+                                            (18, 0, 0, 5), (18, 1, 8, 6), (21, 1, 5, 7)])
+def test_two_wave_round_matches_c_oracle(zc, mu, gate, m, seed):
+    """The last thread-per-pair round (32768 pairs) in its two-wave form:
+    from the caller's tables at mu = 17 (round 2), out of place in the moved
+    region of the folded tables at mu = 19 and 21 (points split for the
+    product and Table 1 gates, terms split for the vanilla gate); at mu = 18
+    it runs on one wave in place.  Against the C oracle."""
+    inst = I.make_instance(70 + seed, m, mu, gate, m, workers=8)
+    print(f"two-wave round mu={mu} gate={gate} m={m}", flush=True)
+    res = gpu_prove(inst)
+    assert res["err"] == 0
+    ora = C.prove(mu, gate, m, inst.tables, inst.r)
+    assert np.array_equal(res["evals"], ora["evals"]) and np.array_equal(res["alphas"], ora["alphas"])
+    assert np.array_equal(res["openings"], ora["openings"])
+
+
 @pytest.mark.parametrize("name", ["plain20_d3", "plain20_d9"])
 def test_full_size_matches_c_oracle(zc, name):
     inst = I.preset_instance(name)
